@@ -1,0 +1,6 @@
+"""CPU FP64 oracle for the polarizability build -- test infrastructure only.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package; the library never does.
+"""
+from . import chi  # noqa: F401

@@ -1,0 +1,306 @@
+"""Seeded synthetic inputs for the imaginary-time polarizability build.
+
+This module only *prepares inputs*: orbitals, eigenvalues, the plane-wave
+sphere, the imaginary time/frequency grids and the cosine-transform
+coefficients.  It holds none of the polarizability arithmetic (no Green's
+functions, no products, no FFT of chi, no transform of chi), so both the
+GPU path and the CPU oracle can draw their inputs from it.
+
+Workload shapes follow the space-time GW method of Liu, Kaltak, Klimes and
+Kresse (arXiv:1607.02859):
+
+* orbitals on a real-space grid, occupied below and unoccupied above the
+  Fermi level, which sits at zero (Sec. II.A.1, the text after Eqs. (1)-(2));
+* a response cutoff sphere of plane waves (Sec. II.C step (i), the cutoff
+  sphere after Eqs. (43)-(44));
+* a small nonuniform time/frequency grid (Sec. II.A.2) with cosine
+  coefficients gamma_kj obtained by minimising the error function of
+  Eq. (5) over a range of transition energies (Sec. II.A.3).
+
+The physical orbitals of the paper are not available; the stand-ins here are
+seeded Gaussian columns orthonormalised by QR.  They fix only shapes, value
+ranges and conditioning.
+"""
+from __future__ import annotations
+
+import dataclasses
+import functools
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "Item",
+    "g_sphere",
+    "ct_grid",
+    "make_item",
+    "make_config",
+    "CONFIGS",
+    "algorithmic_flops",
+]
+
+
+@dataclasses.dataclass
+class Item:
+    """One independent polarizability problem (one k-point or one system).
+
+    Arrays use the C-ABI layout: orbitals band-major ``[band][r]`` (complex
+    arrays are interleaved re/im in memory), ``ct`` row-major ``[k][j]``.
+    """
+
+    n: tuple                 # FFT grid (n0, n1, n2); r = (i0*n1 + i1)*n2 + i2
+    phi_occ: np.ndarray      # (n_occ, N_r) float64 or complex128
+    phi_unocc: np.ndarray    # (n_unocc, N_r)
+    eps_occ: np.ndarray      # (n_occ,) eV
+    eps_unocc: np.ndarray    # (n_unocc,) eV
+    mu: float                # eV, strictly inside the gap
+    tau: np.ndarray          # (n_tau,) eV^-1, > 0
+    omega: np.ndarray        # (n_omega,) eV (kept for reporting; the build uses ct)
+    ct: np.ndarray           # (n_omega, n_tau): gamma_kj * cos(omega_k tau_j)
+    g_index: np.ndarray      # (n_g,) int32 flat FFT indices, output order
+
+    @property
+    def n_r(self) -> int:
+        return int(self.n[0] * self.n[1] * self.n[2])
+
+    @property
+    def is_complex(self) -> bool:
+        return np.iscomplexobj(self.phi_occ)
+
+    @property
+    def n_occ(self) -> int:
+        return self.phi_occ.shape[0]
+
+    @property
+    def n_unocc(self) -> int:
+        return self.phi_unocc.shape[0]
+
+    @property
+    def n_tau(self) -> int:
+        return self.tau.shape[0]
+
+    @property
+    def n_omega(self) -> int:
+        return self.ct.shape[0]
+
+    @property
+    def n_g(self) -> int:
+        return self.g_index.shape[0]
+
+
+# ----------------------------------------------------------------------------
+# Plane-wave sphere
+# ----------------------------------------------------------------------------
+
+def g_sphere(n: Sequence[int], frac2: float = 5.0 / 36.0) -> np.ndarray:
+    """Flat FFT indices of the plane waves m with |m|^2 <= floor(frac2 * n^2).
+
+    Integer vectors m lie in the open box (-n/2, n/2) per axis, so no vector
+    sits on a Nyquist plane.  Ordering is by (|m|^2, m0, m1, m2).  For a cubic
+    grid this gives 389 / 895 / 1309 / 1743 / 2969 / 4729 / 7123 plane waves
+    at n = 12 / 16 / 18 / 20 / 24 / 28 / 32, about 22 % of the grid.
+    """
+    n0, n1, n2 = (int(v) for v in n)
+    nmin = min(n0, n1, n2)
+    cut = math.floor(frac2 * nmin * nmin)
+
+    def rng(nd):
+        h = (nd - 1) // 2
+        return np.arange(-h, h + 1)
+
+    m0, m1, m2 = np.meshgrid(rng(n0), rng(n1), rng(n2), indexing="ij")
+    m0, m1, m2 = m0.ravel(), m1.ravel(), m2.ravel()
+    q = m0 * m0 + m1 * m1 + m2 * m2
+    keep = q <= cut
+    m0, m1, m2, q = m0[keep], m1[keep], m2[keep], q[keep]
+    order = np.lexsort((m2, m1, m0, q))
+    m0, m1, m2 = m0[order], m1[order], m2[order]
+    flat = ((m0 % n0) * n1 + (m1 % n1)) * n2 + (m2 % n2)
+    return flat.astype(np.int32)
+
+
+# ----------------------------------------------------------------------------
+# Time / frequency grid and cosine-transform coefficients
+# ----------------------------------------------------------------------------
+
+def _fit_ct(tau, omega, x, ridge):
+    """Least-squares cosine coefficients c_kj = gamma_kj cos(omega_k tau_j).
+
+    For each omega_k, minimise the relative residual of the error function
+    eta^c (Eq. (5)): 2x/(x^2+omega_k^2) - sum_j c_kj exp(-x tau_j), sampled
+    on the transition energies x, plus a small ridge term on column-scaled
+    coefficients to keep the transform well conditioned.
+    """
+    E = np.exp(-np.outer(x, tau))
+    C = np.empty((len(omega), len(tau)))
+    err = 0.0
+    amp = 0.0
+    for k, w in enumerate(omega):
+        f = 2.0 * x / (x * x + w * w)
+        A = E / f[:, None]
+        s = np.sqrt((A * A).sum(0))
+        As = A / s
+        if ridge > 0.0:
+            M = np.vstack([As, ridge * np.eye(len(tau))])
+            rhs = np.concatenate([np.ones(len(x)), np.zeros(len(tau))])
+        else:
+            M, rhs = As, np.ones(len(x))
+        c = np.linalg.lstsq(M, rhs, rcond=None)[0] / s
+        C[k] = c
+        err = max(err, float(np.abs(A @ c - 1.0).max()))
+        amp = max(amp, float((np.abs(A) @ np.abs(c)).max()))
+    return C, err, amp
+
+
+def _family(n_tau, x_min, x_max, a, b, p):
+    t = np.linspace(0.0, 1.0, n_tau) ** p
+    lo, hi = math.log(a / x_max), math.log(b / x_min)
+    tau = np.exp(lo + t * (hi - lo))
+    omega = np.geomspace(x_min / 2.0, x_max, n_tau)
+    return tau, omega
+
+
+@functools.lru_cache(maxsize=64)
+def _ct_grid_cached(n_tau, x_min, x_max, ridge):
+    x = np.geomspace(x_min, x_max, 600)
+    best = None
+    for a in (0.05, 0.1, 0.2, 0.3, 0.5):
+        for b in (1.0, 2.0, 3.0, 5.0, 8.0):
+            for p in (0.7, 0.85, 1.0, 1.2):
+                tau, omega = _family(n_tau, x_min, x_max, a, b, p)
+                _, err, amp = _fit_ct(tau, omega, x, 0.0)
+                score = math.log(err) + 0.5 * math.log(amp)
+                if best is None or score < best[0]:
+                    best = (score, tau, omega)
+    _, tau, omega = best
+    xf = np.geomspace(x_min, x_max, 1500)
+    ct, err, _ = _fit_ct(tau, omega, xf, ridge)
+    return tau, omega, ct, err
+
+
+def ct_grid(n_tau: int, x_min: float, x_max: float, ridge: float = 1e-6):
+    """Nonuniform tau/omega grids and cosine coefficients for transition
+    energies x in [x_min, x_max] (eV).
+
+    The minimax grids the paper uses (Sec. II.A.2) come from a method that is
+    not restated in the paper, so a stand-in is used: omega_k log-spaced in
+    [x_min/2, x_max]; tau_j from a three-parameter log-spaced family picked to
+    minimise log(fit error) + 0.5 log(amplification); coefficients from the
+    least-squares minimisation of Eq. (5).  Returns (tau, omega, ct, fit_err)
+    with ct of shape (n_omega, n_tau).
+    """
+    tau, omega, ct, err = _ct_grid_cached(int(n_tau), float(x_min), float(x_max), float(ridge))
+    return tau.copy(), omega.copy(), ct.copy(), err
+
+
+def gauss_legendre_ct(omega: np.ndarray, t_max: float, panel: float = 0.1, nodes: int = 8):
+    """Dense-quadrature cosine coefficients for the Laplace-identity check.
+
+    Composite Gauss-Legendre rule on [0, t_max] with panels of width <= panel
+    and ``nodes`` nodes each: ct[k][j] = 2 w_j cos(omega_k tau_j), so that
+    sum_j ct[k][j] exp(-x tau_j) -> 2 int_0^inf cos(omega tau) exp(-x tau) dtau
+    = 2x/(x^2+omega^2), the closed form under the brace of Eq. (5).
+    """
+    n_pan = int(math.ceil(t_max / panel))
+    h = t_max / n_pan
+    xg, wg = np.polynomial.legendre.leggauss(nodes)
+    left = np.arange(n_pan) * h
+    tau = (left[:, None] + (xg[None, :] + 1.0) * 0.5 * h).ravel()
+    w = np.tile(wg * 0.5 * h, n_pan)
+    ct = 2.0 * w[None, :] * np.cos(np.outer(omega, tau))
+    return tau, ct
+
+
+# ----------------------------------------------------------------------------
+# Items and configurations
+# ----------------------------------------------------------------------------
+
+def _orbitals(rng, n_r, k, cplx):
+    a = rng.standard_normal((n_r, k))
+    if cplx:
+        a = a + 1j * rng.standard_normal((n_r, k))
+    q, _ = np.linalg.qr(a, mode="reduced")
+    return np.ascontiguousarray(q.T)
+
+
+def make_item(seed, n, n_occ, n_unocc, cplx, n_tau, *, gap=1.0, x_min=None,
+              eps_lo=-15.0, eps_hi=60.0, x_max=75.0, mu=0.0, n_g=None, ct=None) -> Item:
+    """One seeded item.
+
+    Eigenvalues: occupied uniform in [eps_lo, -gap/2], unoccupied uniform in
+    [gap/2, eps_hi], sorted, then shifted by mu.  The tau/omega grid covers
+    transition energies [x_min, x_max] (x_min defaults to the gap).
+    """
+    rng = np.random.default_rng(seed)
+    n = tuple(int(v) for v in n)
+    n_r = n[0] * n[1] * n[2]
+    phi = _orbitals(rng, n_r, n_occ + n_unocc, cplx)
+    eps_o = np.sort(rng.uniform(eps_lo, -gap / 2.0, n_occ))
+    eps_u = np.sort(rng.uniform(gap / 2.0, eps_hi, n_unocc))
+    if ct is None:
+        tau, omega, ctm, _ = ct_grid(n_tau, gap if x_min is None else x_min, x_max)
+    else:
+        tau, omega, ctm = ct
+    g = g_sphere(n)
+    if n_g is not None:
+        g = g[:n_g]
+    return Item(n=n, phi_occ=np.ascontiguousarray(phi[:n_occ]),
+                phi_unocc=np.ascontiguousarray(phi[n_occ:]),
+                eps_occ=eps_o + mu, eps_unocc=eps_u + mu, mu=float(mu),
+                tau=np.asarray(tau, float), omega=np.asarray(omega, float),
+                ct=np.ascontiguousarray(ctm, dtype=float), g_index=g)
+
+
+def _cfg5_system(s):
+    n = [16, 18, 20, 24, 28][(5 * s) // 32]
+    n_o = 16 + int(round(80 * s / 31))
+    return n, n_o, 16 * n_o, 0.1 * 100.0 ** ((s % 8) / 7.0)
+
+
+CONFIGS = {
+    # id: description used in reports
+    1: "gamma-only real, 12^3, 16+112 bands, 6 tau",
+    2: "gamma-only complex, 24^3, 64+960 bands, 12 tau, 2048-column slabs",
+    3: "8 k-points, 24^3 complex, occ 48-64 / unocc 700-1000, 16 tau",
+    4: "32^3 complex, 128+2048 bands, 16 tau",
+    5: "32 real systems, 16^3-28^3, 16/256-96/1536 bands, gaps 0.1-10 eV, 20 tau",
+}
+
+
+def make_config(cfg: int, *, scale: Optional[float] = None) -> List[Item]:
+    """The items of a workload configuration, seeded by (cfg, item).
+
+    ``scale`` is not used to shrink anything silently: callers that want a
+    small variant build it with :func:`make_item` directly.
+    """
+    if cfg == 1:
+        return [make_item([1, 0], (12, 12, 12), 16, 112, False, 6, x_min=0.5)]
+    if cfg == 2:
+        return [make_item([2, 0], (24, 24, 24), 64, 960, True, 12, x_min=0.5)]
+    if cfg == 3:
+        out = []
+        rng = np.random.default_rng([3, 99])
+        occ = rng.integers(48, 65, 8)
+        unocc = rng.integers(700, 1001, 8)
+        for k in range(8):
+            out.append(make_item([3, k], (24, 24, 24), int(occ[k]), int(unocc[k]), True, 16,
+                                 x_min=0.5))
+        return out
+    if cfg == 4:
+        return [make_item([4, 0], (32, 32, 32), 128, 2048, True, 16, x_min=0.5)]
+    if cfg == 5:
+        out = []
+        for s in range(32):
+            n, n_o, n_u, gap = _cfg5_system(s)
+            out.append(make_item([5, s], (n, n, n), n_o, n_u, False, 20, gap=gap))
+        return out
+    raise ValueError(f"unknown configuration {cfg}")
+
+
+def algorithmic_flops(item: Item) -> float:
+    """Flops per build the method must spend on the band contractions,
+    counting the full N_r x N_r square: 8 N_r^2 K per tau (complex) or
+    2 N_r^2 K (real), K = n_occ + n_unocc."""
+    per = 8.0 if item.is_complex else 2.0
+    return per * item.n_r ** 2 * (item.n_occ + item.n_unocc) * item.n_tau
