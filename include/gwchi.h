@@ -1,0 +1,179 @@
+/*
+ * gwchi.h -- imaginary-time polarizability chi(G, G', i omega) of the
+ * cubic-scaling space-time GW method (Liu, Kaltak, Klimes, Kresse,
+ * arXiv:1607.02859) on AMD MI355X (gfx950).
+ *
+ * What one build computes, per item and per imaginary time tau_j
+ * (Sec. II.A.1 Eqs. (1)-(2); Sec. II.B Eqs. (14)-(15); Sec. II.C Eqs. (43)-(45)):
+ *
+ *   G_occ(r,r')   =  sum_i phi_i(r) conj(phi_i(r')) exp(+(eps_i - mu) tau_j)
+ *   G_unocc(r,r') =  sum_a phi_a(r) conj(phi_a(r')) exp(-(eps_a - mu) tau_j)
+ *   chi(r,r')     = -G_occ(r,r') * conj(G_unocc(r,r'))      (pointwise)
+ *   chi(G,G')     =  sum_{r,r'} exp(-i G.r) chi(r,r') exp(+i G'.r')
+ *   chi(G,G',i omega_k) = sum_j ct[k][j] chi(G,G', i tau_j)   (Eq. (4) / (45))
+ *
+ * The pointwise product is the tau < 0 branch of Eq. (15) (occupied and
+ * unoccupied functions exchanged); for real orbitals both branches agree.
+ * There is no 1/N_r, cell-volume or spin factor.  r runs over the grid
+ * points (i0/n0, i1/n1, i2/n2) with flat index r = (i0*n1 + i1)*n2 + i2, and
+ * a plane wave G is named by its flat FFT index (k0*n1 + k1)*n2 + k2 with
+ * k_d = m_d mod n_d.
+ *
+ * Conventions for every entry point:
+ *  - All buffers are owned by the caller.  The library keeps no pointer to
+ *    them after the call returns (device variant: after the enqueued work
+ *    completes).  The context owns its device scratch and HIP objects.
+ *  - No C++ exception crosses this interface.  On any status other than
+ *    GWCHI_OK the contents of chi_out are unspecified and
+ *    gwchi_last_error(ctx) describes the failure.
+ *  - Precision: GWCHI_FP64 computes every step in FP64.  GWCHI_FP32 and
+ *    GWCHI_BF16X3 compute the weights and the cosine transform in FP64 and
+ *    the band contractions, products and FFTs in FP32; GWCHI_BF16X3 runs the
+ *    band contractions as split-BF16 (hi + lo parts, three products
+ *    hi*hi + hi*lo + lo*hi) on MFMA with FP32 accumulation.
+ */
+#ifndef GWCHI_H
+#define GWCHI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gwchi_ctx gwchi_ctx;
+
+typedef enum {
+  GWCHI_OK = 0,
+  GWCHI_EINVAL = 1,   /* invalid argument (see gwchi_validate)                */
+  GWCHI_ENOMEM = 2,   /* device memory: even the narrowest plan does not fit  */
+  GWCHI_EDEVICE = 3,  /* HIP runtime error, or no usable gfx950 device        */
+  GWCHI_ENOTSUP = 4,  /* grid size outside the supported FFT sizes            */
+  GWCHI_ENUMERIC = 5  /* optional output check found NaN or Inf               */
+} gwchi_status;
+
+typedef enum {
+  GWCHI_FP64 = 0,
+  GWCHI_FP32 = 1,
+  GWCHI_BF16X3 = 2
+} gwchi_precision;
+
+/* One independent problem: one k-point (complex orbitals on the unit-cell
+ * grid; the q = 0 contribution of that k) or one Gamma-only system (real
+ * orbitals).  Items of one call may differ in every size. */
+typedef struct {
+  int32_t n[3];          /* FFT grid n0, n1, n2; each 7-smooth and in [1, 32] (else ENOTSUP) */
+  int32_t is_complex;    /* 0: real orbitals, 1: complex orbitals interleaved (re, im)      */
+  int32_t n_occ;         /* >= 1 */
+  int32_t n_unocc;       /* >= 1 */
+  /* Orbitals, band-major: phi_occ[b*N_r + r] (real) or phi_occ[2*(b*N_r + r) + {0,1}]
+   * (complex), N_r = n0*n1*n2, FP64.  Any normalisation is accepted; the
+   * synthetic workloads use sum_r |phi(r)|^2 = 1.
+   * gwchi_chi_build: host memory.  gwchi_chi_build_device: device memory. */
+  const double *phi_occ;
+  const double *phi_unocc;
+  const double *eps_occ;    /* [n_occ]   eV, any order, host memory                       */
+  const double *eps_unocc;  /* [n_unocc] eV, any order, host memory                       */
+  double mu;                /* eV; max(eps_occ) < mu < min(eps_unocc) strictly            */
+  int32_t n_tau;            /* >= 1 */
+  int32_t n_omega;          /* >= 1 */
+  const double *tau;        /* [n_tau] imaginary times > 0 (eV^-1), host memory           */
+  const double *ct;         /* [n_omega][n_tau] row-major, ct[k][j] = gamma_kj cos(omega_k tau_j)
+                               (Eq. (4)), host memory                                     */
+  int32_t n_g;              /* >= 1 */
+  const int32_t *g_index;   /* [n_g] distinct flat FFT indices in [0, N_r), output order; host */
+  /* Output chi[k][g][g'] complex interleaved FP64, row index g (first index,
+   * exp(-i G.r)), column g' (exp(+i G'.r')), shape [n_omega][n_g][n_g].
+   * gwchi_chi_build: host memory.  gwchi_chi_build_device: device memory. */
+  double *chi_out;
+} gwchi_item;
+
+/* Per-call measurements.  Phase times are GPU time between HIP events
+ * recorded on the build stream around each launch of that phase, summed. */
+typedef struct {
+  double ms_total;          /* stream time of the whole build                        */
+  double ms_stage;          /* weights (FP64) + scaled operand staging               */
+  double ms_gemm;           /* fused band contractions + Hadamard product             */
+  double ms_fft_r;          /* FFT over r with sphere gather                          */
+  double ms_fft_rp;         /* FFT over r' with sphere gather                         */
+  double ms_ct;             /* cosine transform (FP64 accumulation)                   */
+  int32_t n_gemm_launches;  /* launches that make up ms_gemm                          */
+  int32_t n_fft_launches;   /* launches that make up ms_fft_r + ms_fft_rp             */
+  double alg_flops;         /* 8 N_r^2 K (complex) or 2 N_r^2 K (real) per tau, summed */
+  double mfma_flops;        /* flops issued on MFMA (split-BF16 counts 3 products)     */
+  int32_t slab_width;       /* r' columns per slab used                                */
+  int32_t tau_batch;        /* tau points processed per pass                           */
+  int32_t tile_id;          /* GEMM tile configuration used                            */
+  int32_t graph_replayed;   /* 1 if the build ran as a replay of a cached hipGraph     */
+  double kappa_F_max;       /* max_k sum_j |c'_kj| ||chi(tau_j)||_F / ||chi(i w_k)||_F */
+} gwchi_report;
+
+/* Context options.  gwchi_create sets the defaults noted below;
+ * gwchi_set_options replaces every field. */
+typedef struct {
+  int32_t slab_width;        /* r' columns per slab, multiple of 256; 0 = planner
+                                (2048, narrowed until the plan fits)                  */
+  int32_t tau_batch;         /* (item, tau) jobs per pass; 0 = planner (all that fit)   */
+  int32_t tile_id;           /* GEMM tile: 0 = tuned if cached, else the first of the
+                                menu; t >= 1 = menu entry t-1 (default 0)              */
+  int32_t use_graph;         /* 1 = capture the build into a hipGraph and replay it
+                                (default 1)                                             */
+  int32_t check_output;      /* 1 = scan chi_out for NaN/Inf (ENUMERIC), host build only
+                                (default 0)                                             */
+  int32_t timing;            /* 1 = fill the per-phase times of gwchi_report (default 0) */
+  int32_t skip_zero_bands;   /* 1 = drop bands whose scaled orbitals are exactly zero in
+                                the working precision; never on FP64 (default 0)       */
+  int32_t hermitian;         /* 1 = compute only the lower block triangle of chi(r,r')
+                                and complete by Hermiticity (default 0)                 */
+  int64_t max_device_bytes;  /* cap on the context's scratch; 0 = 60% of free memory   */
+} gwchi_options;
+
+/* Create a context on HIP device device_id (must be gfx950).
+ * tune_cache_path: JSON file written by gwchi_autotune, or NULL. */
+gwchi_status gwchi_create(gwchi_ctx **ctx, int32_t device_id, const char *tune_cache_path);
+
+/* Release every device buffer, stream, event and graph the context owns. */
+gwchi_status gwchi_destroy(gwchi_ctx *ctx);
+
+gwchi_status gwchi_set_options(gwchi_ctx *ctx, const gwchi_options *opt);
+gwchi_status gwchi_get_options(const gwchi_ctx *ctx, gwchi_options *opt);
+
+/* Host-only check of items (no device is touched).  EINVAL on: null
+ * pointer, n_d <= 0, n_occ or n_unocc < 1, n_tau or n_omega or n_g < 1,
+ * non-finite eps / mu / tau / ct (and non-finite orbitals when orbital
+ * pointers are host memory: check_orbitals != 0), tau <= 0, mu not strictly
+ * inside the gap, g_index out of range or duplicated.  ENOTSUP when a grid
+ * size is not 7-smooth or exceeds 32. */
+gwchi_status gwchi_validate(const gwchi_item *items, int32_t n_items, int32_t check_orbitals);
+
+/* Build chi(G,G',i omega) for every item; host buffers in and out.
+ * Blocking: returns after chi_out is written.  report may be NULL. */
+gwchi_status gwchi_chi_build(gwchi_ctx *ctx, const gwchi_item *items, int32_t n_items,
+                             gwchi_precision prec, gwchi_report *report);
+
+/* Same with phi_occ, phi_unocc and chi_out in device memory of the
+ * context's device; all other arrays in host memory.  The work is enqueued
+ * on hip_stream (a hipStream_t; NULL = the context's own stream).  Returns
+ * once enqueued unless report is non-NULL, in which case it waits for the
+ * stream and fills the report. */
+gwchi_status gwchi_chi_build_device(gwchi_ctx *ctx, const gwchi_item *items, int32_t n_items,
+                                    gwchi_precision prec, void *hip_stream,
+                                    gwchi_report *report);
+
+/* Time every GEMM tile configuration on these items (host memory, as for
+ * gwchi_chi_build; chi_out is not written), keep the fastest per
+ * (precision, real/complex) in the context and write the tune cache file. */
+gwchi_status gwchi_autotune(gwchi_ctx *ctx, const gwchi_item *items, int32_t n_items,
+                            gwchi_precision prec);
+
+/* Message of the last failure on this context (never NULL). */
+const char *gwchi_last_error(const gwchi_ctx *ctx);
+
+/* Library version string. */
+const char *gwchi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GWCHI_H */

@@ -1,0 +1,1336 @@
+// Host runtime behind the C ABI of gwchi.h: validation, planning, launch
+// sequence, hipGraph cache, timing and report.
+//
+// One call is planned as a list of jobs, one per (item, tau_j), cut into
+// passes that fit the device-memory budget.  Per pass:
+//   stage (FP64 weights, scaled operands)                 - all jobs of the pass
+//   for every r' slab: band GEMM + Hadamard, FFT over r   - one launch each, all jobs
+//   FFT over r'                                           - one launch, all jobs
+// and after the last pass one cosine-transform launch for all items.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/gwchi.h"
+#include "common.h"
+
+using namespace gw;
+
+namespace {
+
+thread_local std::string g_tls_error;
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t n = 0;
+  hipError_t ensure(size_t bytes, bool *moved) {
+    if (bytes <= n) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      if (e != hipSuccess) return e;
+      p = nullptr;
+      n = 0;
+    }
+    size_t want = bytes + bytes / 8 + 256;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    n = want;
+    if (moved) *moved = true;
+    return hipSuccess;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+struct HostPinned {
+  void *p = nullptr;
+  size_t n = 0;
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= n) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+    size_t want = bytes + bytes / 8 + 256;
+    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    n = want;
+    return hipSuccess;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+enum Phase { PH_STAGE = 0, PH_GEMM, PH_FFT_R, PH_FFT_RP, PH_CT, PH_NORM, PH_COUNT };
+
+struct Launch {
+  int phase;
+  int kind;   // 0 stage, 1 gemm, 2 fft, 3 ct, 4 norms, 5 fill
+  size_t off; // offset of the launch struct's tables in the table blob
+  // typed payloads (device pointers patched in)
+  StageLaunch stage;
+  GemmLaunch gemm;
+  FftLaunch fft;
+  CtLaunch ct;
+  int fft_sign = -1;
+  int fft_grid = 0;
+  int fft_lds = 0;
+  int gemm_grid = 0;
+  int max_omega = 0;
+  int max_mats = 0;
+  void *fill_ptr = nullptr;
+  int64_t fill_bytes = 0;
+  const int32_t *toff = nullptr, *woff = nullptr;
+};
+
+}  // namespace
+
+struct gwchi_ctx {
+  int device = 0;
+  int num_cu = 256;
+  size_t lds_max = 65536;
+  hipStream_t stream = nullptr;
+  gwchi_options opt{};
+  std::string err;
+  std::string tune_path;
+  std::map<std::string, int> tune;   // key -> tile index
+  DevBuf b_phi, b_out, b_psi, b_slab, b_xr, b_x, b_scratch, b_tables, b_norm;
+  HostPinned h_tables, h_norm;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::vector<hipEvent_t> ev_pool;
+  // graph cache: one entry keyed by the structural signature of the plan
+  std::string graph_key;
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  size_t graph_events = 0;
+};
+
+namespace {
+
+void set_err(gwchi_ctx *ctx, const std::string &m) {
+  if (ctx) ctx->err = m;
+  g_tls_error = m;
+}
+
+#define HIPCHK(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      set_err(ctx, std::string(#call) + ": " + hipGetErrorString(e_));               \
+      return e_ == hipErrorOutOfMemory ? GWCHI_ENOMEM : GWCHI_EDEVICE;                \
+    }                                                                                 \
+  } while (0)
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+bool finite_all(const double *p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+gwchi_status validate_items(gwchi_ctx *ctx, const gwchi_item *items, int32_t n_items,
+                            bool check_orbitals) {
+  if (!items || n_items < 1) {
+    set_err(ctx, "items is NULL or n_items < 1");
+    return GWCHI_EINVAL;
+  }
+  for (int32_t t = 0; t < n_items; ++t) {
+    const gwchi_item &it = items[t];
+    std::string pre = "item " + std::to_string(t) + ": ";
+    for (int d = 0; d < 3; ++d)
+      if (it.n[d] < 1) {
+        set_err(ctx, pre + "grid size must be >= 1");
+        return GWCHI_EINVAL;
+      }
+    if (it.n_occ < 1 || it.n_unocc < 1) {
+      set_err(ctx, pre + "n_occ and n_unocc must be >= 1");
+      return GWCHI_EINVAL;
+    }
+    if (it.n_tau < 1 || it.n_omega < 1 || it.n_g < 1) {
+      set_err(ctx, pre + "n_tau, n_omega and n_g must be >= 1");
+      return GWCHI_EINVAL;
+    }
+    if (!it.phi_occ || !it.phi_unocc || !it.eps_occ || !it.eps_unocc || !it.tau || !it.ct ||
+        !it.g_index || !it.chi_out) {
+      set_err(ctx, pre + "NULL pointer");
+      return GWCHI_EINVAL;
+    }
+    if (it.is_complex != 0 && it.is_complex != 1) {
+      set_err(ctx, pre + "is_complex must be 0 or 1");
+      return GWCHI_EINVAL;
+    }
+    for (int d = 0; d < 3; ++d)
+      if (!fft_supported(it.n[d])) {
+        set_err(ctx, pre + "grid size " + std::to_string(it.n[d]) +
+                         " unsupported (7-smooth and <= 32 required)");
+        return GWCHI_ENOTSUP;
+      }
+    const int64_t n_r = (int64_t)it.n[0] * it.n[1] * it.n[2];
+    if (!finite_all(it.eps_occ, it.n_occ) || !finite_all(it.eps_unocc, it.n_unocc) ||
+        !std::isfinite(it.mu) || !finite_all(it.tau, it.n_tau) ||
+        !finite_all(it.ct, (int64_t)it.n_tau * it.n_omega)) {
+      set_err(ctx, pre + "non-finite eigenvalue, mu, tau or ct");
+      return GWCHI_EINVAL;
+    }
+    const double homo = *std::max_element(it.eps_occ, it.eps_occ + it.n_occ);
+    const double lumo = *std::min_element(it.eps_unocc, it.eps_unocc + it.n_unocc);
+    if (!(homo < it.mu && it.mu < lumo)) {
+      set_err(ctx, pre + "mu must lie strictly between max(eps_occ) and min(eps_unocc)");
+      return GWCHI_EINVAL;
+    }
+    for (int j = 0; j < it.n_tau; ++j)
+      if (!(it.tau[j] > 0.0)) {
+        set_err(ctx, pre + "tau must be > 0");
+        return GWCHI_EINVAL;
+      }
+    std::vector<char> seen((size_t)n_r, 0);
+    for (int g = 0; g < it.n_g; ++g) {
+      const int32_t f = it.g_index[g];
+      if (f < 0 || f >= n_r) {
+        set_err(ctx, pre + "g_index out of range");
+        return GWCHI_EINVAL;
+      }
+      if (seen[f]) {
+        set_err(ctx, pre + "g_index has duplicates");
+        return GWCHI_EINVAL;
+      }
+      seen[f] = 1;
+    }
+    if (check_orbitals) {
+      const int64_t m = n_r * (it.is_complex ? 2 : 1);
+      if (!finite_all(it.phi_occ, m * it.n_occ) || !finite_all(it.phi_unocc, m * it.n_unocc)) {
+        set_err(ctx, pre + "non-finite orbital value");
+        return GWCHI_EINVAL;
+      }
+    }
+  }
+  return GWCHI_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Plan
+// ----------------------------------------------------------------------------
+
+struct ItemPlan {
+  int n0, n1, n2;
+  int64_t n_r, n_r_pad;
+  int cplx;
+  int k_o, k_u, k_o_pad, k_u_pad;
+  int n_tau, n_omega, n_g;
+  double homo, lumo;
+  std::vector<int32_t> perm_o, perm_u;
+  std::vector<double> eps_o, eps_u;
+  std::vector<int32_t> disk_i12, slot_dk;
+  int n_disk = 0, planes = 1, disk_lds = 1;
+  std::vector<double> coef;    // [n_omega][n_tau]
+  std::vector<double> tau;
+  const double *phi_o = nullptr, *phi_u = nullptr;
+  double *out = nullptr;
+  int64_t x_off = 0;           // byte offset in b_x
+  int job0 = 0;
+};
+
+struct JobPlan {
+  int item, j;
+  int k_o_eff, k_u_eff;
+};
+
+struct Plan {
+  int prec = 0;
+  int tile = 0, bm = 0, bn = 0, kc = 0;
+  int slab_w = 2048;
+  int jobs_per_pass = 1;
+  std::vector<ItemPlan> items;
+  std::vector<JobPlan> jobs;
+  // per-job slot sizes (bytes), uniform across slots (maxima)
+  int64_t psi_slot = 0, slab_slot = 0, xr_slot = 0;
+  int64_t x_bytes = 0, scratch_bytes = 0;
+  int64_t scratch_slot_elems = 0;
+  int fft_grid = 0, fft_lds = 0;
+  double alg_flops = 0, mfma_flops = 0;
+  int cplx_any = 0, real_any = 0;
+};
+
+int bpb_of(int prec, int cplx) {   // operand bytes per band element
+  if (prec == P_FP64) return cplx ? 16 : 8;
+  return cplx ? 8 : 4;
+}
+int elem_c(int prec) { return prec == P_FP64 ? 16 : 8; }            // complex working element
+int elem_slab(int prec, int cplx) { return cplx ? elem_c(prec) : elem_c(prec) / 2; }
+
+std::string tune_key(int prec, int cplx) {
+  return std::string(prec == P_FP64 ? "fp64" : prec == P_FP32 ? "fp32" : "bf16x3") +
+         (cplx ? "/c" : "/r");
+}
+
+gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int prec,
+                        Plan &P) {
+  P = Plan();
+  P.prec = prec;
+  // all items of one call use one (precision, complexity) tile family; mixed real/complex
+  // items are allowed and use their own tile family each
+  for (int t = 0; t < n_items; ++t) (items[t].is_complex ? P.cplx_any : P.real_any) = 1;
+  if (P.cplx_any && P.real_any) {
+    set_err(ctx, "items of one call must be all real or all complex");
+    return GWCHI_EINVAL;
+  }
+  const int cplx = P.cplx_any;
+  const int ntile = gemm_tile_count(prec, cplx);
+  int tile = 0;
+  if (ctx->opt.tile_id >= 1) {
+    tile = ctx->opt.tile_id - 1;
+    if (tile >= ntile) {
+      set_err(ctx, "tile_id out of range");
+      return GWCHI_EINVAL;
+    }
+  } else {
+    auto it = ctx->tune.find(tune_key(prec, cplx));
+    if (it != ctx->tune.end() && it->second >= 0 && it->second < ntile) tile = it->second;
+  }
+  P.tile = tile;
+  P.bm = gemm_tile_bm(prec, cplx, tile);
+  P.bn = gemm_tile_bn(prec, cplx, tile);
+  P.kc = gemm_tile_kc(prec, cplx, tile);
+
+  const int ec = elem_c(prec);
+  const int es = elem_slab(prec, cplx);
+  const int bpb = bpb_of(prec, cplx);
+  P.items.resize(n_items);
+  int64_t max_n_r = 0;
+  for (int t = 0; t < n_items; ++t) {
+    const gwchi_item &it = items[t];
+    ItemPlan &I = P.items[t];
+    I.n0 = it.n[0];
+    I.n1 = it.n[1];
+    I.n2 = it.n[2];
+    I.n_r = (int64_t)I.n0 * I.n1 * I.n2;
+    I.n_r_pad = round_up(I.n_r, kRowPad);
+    max_n_r = std::max(max_n_r, I.n_r);
+    I.cplx = it.is_complex;
+    I.k_o = it.n_occ;
+    I.k_u = it.n_unocc;
+    I.k_o_pad = (int)round_up(I.k_o, kBandPad);
+    I.k_u_pad = (int)round_up(I.k_u, kBandPad);
+    I.n_tau = it.n_tau;
+    I.n_omega = it.n_omega;
+    I.n_g = it.n_g;
+    // sort bands: occupied by descending energy, unoccupied ascending (edge first)
+    I.perm_o.resize(I.k_o);
+    std::iota(I.perm_o.begin(), I.perm_o.end(), 0);
+    std::stable_sort(I.perm_o.begin(), I.perm_o.end(),
+                     [&](int a, int b) { return it.eps_occ[a] > it.eps_occ[b]; });
+    I.perm_u.resize(I.k_u);
+    std::iota(I.perm_u.begin(), I.perm_u.end(), 0);
+    std::stable_sort(I.perm_u.begin(), I.perm_u.end(),
+                     [&](int a, int b) { return it.eps_unocc[a] < it.eps_unocc[b]; });
+    I.eps_o.resize(I.k_o);
+    I.eps_u.resize(I.k_u);
+    for (int k = 0; k < I.k_o; ++k) I.eps_o[k] = it.eps_occ[I.perm_o[k]];
+    for (int k = 0; k < I.k_u; ++k) I.eps_u[k] = it.eps_unocc[I.perm_u[k]];
+    I.homo = I.eps_o[0];
+    I.lumo = I.eps_u[0];
+    I.tau.assign(it.tau, it.tau + it.n_tau);
+    // cosine coefficients with the band-edge factor exp(-(lumo - homo) tau_j), FP64
+    I.coef.resize((size_t)I.n_omega * I.n_tau);
+    for (int k = 0; k < I.n_omega; ++k)
+      for (int j = 0; j < I.n_tau; ++j)
+        I.coef[(size_t)k * I.n_tau + j] =
+            it.ct[(size_t)k * I.n_tau + j] * std::exp(-(I.lumo - I.homo) * it.tau[j]);
+    // sphere tables
+    std::map<int, int> dmap;
+    I.slot_dk.resize(I.n_g);
+    for (int s = 0; s < I.n_g; ++s) {
+      const int f = it.g_index[s];
+      const int k0 = f / (I.n1 * I.n2);
+      const int i12 = f - k0 * I.n1 * I.n2;
+      auto ins = dmap.emplace(i12, (int)dmap.size());
+      I.slot_dk[s] = ins.first->second * I.n0 + k0;
+    }
+    I.n_disk = (int)dmap.size();
+    I.disk_i12.resize(I.n_disk);
+    for (auto &kv : dmap) I.disk_i12[kv.second] = kv.first;
+    // FFT LDS plan
+    const int plane = I.n1 * I.n2;
+    int pmax = std::max(1, 256 / std::max(I.n1, I.n2));
+    pmax = std::min(pmax, I.n0);
+    const int64_t lds = (int64_t)ctx->lds_max - 1024;
+    const int64_t disk_b = (int64_t)I.n_disk * I.n0 * ec;
+    int planes = pmax;
+    while (planes > 1 && (int64_t)planes * plane * ec + disk_b > lds) planes = (planes + 1) / 2;
+    if ((int64_t)planes * plane * ec + disk_b <= lds) {
+      I.planes = planes;
+      I.disk_lds = 1;
+    } else {
+      planes = pmax;
+      while (planes > 1 && (int64_t)planes * plane * ec > lds) planes = (planes + 1) / 2;
+      I.planes = planes;
+      I.disk_lds = 0;
+    }
+    I.phi_o = it.phi_occ;
+    I.phi_u = it.phi_unocc;
+    I.out = it.chi_out;
+    P.alg_flops += (I.cplx ? 8.0 : 2.0) * (double)I.n_r * (double)I.n_r * (I.k_o + I.k_u) * I.n_tau;
+  }
+  // jobs, with optional exact-zero band truncation
+  const double thr = std::ldexp(1.0, -152);
+  const bool skip = ctx->opt.skip_zero_bands && prec != P_FP64;
+  for (int t = 0; t < n_items; ++t) {
+    ItemPlan &I = P.items[t];
+    I.job0 = (int)P.jobs.size();
+    for (int j = 0; j < I.n_tau; ++j) {
+      JobPlan J{t, j, I.k_o, I.k_u};
+      if (skip) {
+        int co = 0, cu = 0;
+        for (int k = 0; k < I.k_o; ++k)
+          if (std::exp(0.5 * (I.eps_o[k] - I.homo) * I.tau[j]) >= thr) co = k + 1;
+        for (int k = 0; k < I.k_u; ++k)
+          if (std::exp(-0.5 * (I.eps_u[k] - I.lumo) * I.tau[j]) >= thr) cu = k + 1;
+        J.k_o_eff = std::max(co, 1);
+        J.k_u_eff = std::max(cu, 1);
+      }
+      J.k_o_eff = (int)std::min<int64_t>(round_up(J.k_o_eff, P.kc), I.k_o_pad);
+      J.k_u_eff = (int)std::min<int64_t>(round_up(J.k_u_eff, P.kc), I.k_u_pad);
+      P.jobs.push_back(J);
+    }
+  }
+  // sizes
+  int64_t x_total = 0;
+  int64_t psi_max = 0, xr_max = 0;
+  int max_disk_elems = 0;
+  bool any_global_disk = false;
+  for (auto &I : P.items) {
+    I.x_off = x_total;
+    x_total += round_up((int64_t)I.n_tau * I.n_g * I.n_g * ec, 256);
+    psi_max = std::max<int64_t>(psi_max, I.n_r_pad * (I.k_o_pad + I.k_u_pad) * bpb);
+    xr_max = std::max<int64_t>(xr_max, (int64_t)I.n_g * I.n_r * ec);
+    if (!I.disk_lds) {
+      any_global_disk = true;
+      max_disk_elems = std::max(max_disk_elems, I.n_disk * I.n0);
+    }
+  }
+  P.x_bytes = x_total;
+  P.psi_slot = round_up(psi_max, 256);
+  P.xr_slot = round_up(xr_max, 256);
+  P.fft_grid = ctx->num_cu * 2;
+  P.scratch_slot_elems = any_global_disk ? max_disk_elems : 0;
+  P.scratch_bytes = (int64_t)P.fft_grid * P.scratch_slot_elems * ec + 256;
+  int lds_need = 0;
+  for (auto &I : P.items) {
+    int b = I.planes * I.n1 * I.n2 * ec + (I.disk_lds ? I.n_disk * I.n0 * ec : 0);
+    lds_need = std::max(lds_need, b);
+  }
+  P.fft_lds = lds_need;
+  // budget
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)64 << 30;
+  // memory the context already holds counts as available
+  const size_t held = ctx->b_psi.n + ctx->b_slab.n + ctx->b_xr.n + ctx->b_x.n + ctx->b_scratch.n;
+  int64_t budget = ctx->opt.max_device_bytes > 0 ? ctx->opt.max_device_bytes
+                                                 : (int64_t)((free_b + held) * 0.6);
+  const int64_t fixed = P.x_bytes + P.scratch_bytes + ((int64_t)64 << 20);
+  int W = ctx->opt.slab_width > 0 ? (int)round_up(ctx->opt.slab_width, 256) : 2048;
+  const int n_jobs = (int)P.jobs.size();
+  for (;;) {
+    const int64_t slab_max = round_up((int64_t)std::min<int64_t>(W, round_up(max_n_r, 256)) *
+                                          max_n_r * es, 256);
+    const int64_t per_job = P.psi_slot + slab_max + P.xr_slot;
+    int64_t fit = per_job > 0 ? (budget - fixed) / per_job : 0;
+    int want = ctx->opt.tau_batch > 0 ? std::min(ctx->opt.tau_batch, n_jobs) : n_jobs;
+    if (fit >= 1) {
+      P.slab_w = W;
+      P.slab_slot = slab_max;
+      P.jobs_per_pass = (int)std::min<int64_t>(want, fit);
+      break;
+    }
+    if (W <= 256 || ctx->opt.slab_width > 0) {
+      set_err(ctx, "device memory budget too small for one job with a 256-column slab");
+      return GWCHI_ENOMEM;
+    }
+    W /= 2;
+  }
+  return GWCHI_OK;
+}
+
+// Blob of device tables, built on the host with offsets, then patched with the
+// device base address and copied in one transfer.
+struct Blob {
+  std::vector<char> h;
+  size_t add(const void *src, size_t bytes) {
+    size_t off = round_up((int64_t)h.size(), 64);
+    h.resize(off + bytes);
+    if (bytes) std::memcpy(h.data() + off, src, bytes);
+    return off;
+  }
+  template <typename T>
+  size_t addv(const std::vector<T> &v) {
+    return add(v.data(), v.size() * sizeof(T));
+  }
+};
+
+struct Built {
+  std::vector<Launch> launches;
+  Blob blob;
+  std::string key;     // structural signature for the graph cache
+  int n_passes = 0;
+  int64_t norm_tau_off = 0, norm_omega_off = 0;
+  int n_norm_tau = 0, n_norm_omega = 0;
+};
+
+// Build every launch descriptor.  Pointers into the blob are stored as offsets
+// and patched by patch_blob once the device address of the blob is known.
+void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
+  (void)ctx;
+  B.launches.clear();
+  B.blob.h.clear();
+  const int cplx = P.cplx_any;
+  const int ec = elem_c(P.prec);
+  const int es = elem_slab(P.prec, cplx);
+  const int n_items = (int)P.items.size();
+  char *psi_base = reinterpret_cast<char *>(ctx->b_psi.p);
+  char *slab_base = reinterpret_cast<char *>(ctx->b_slab.p);
+  char *xr_base = reinterpret_cast<char *>(ctx->b_xr.p);
+  char *x_base = reinterpret_cast<char *>(ctx->b_x.p);
+  std::ostringstream key;
+  key << "p" << P.prec << "t" << P.tile << "w" << P.slab_w << "b" << P.jobs_per_pass << "h"
+      << ctx->opt.hermitian << "n" << want_norms << "|";
+  // geometry tables
+  std::vector<size_t> off_i12(n_items), off_sdk(n_items), off_perm_o(n_items),
+      off_perm_u(n_items), off_eps_o(n_items), off_eps_u(n_items), off_coef(n_items);
+  for (int t = 0; t < n_items; ++t) {
+    const ItemPlan &I = P.items[t];
+    off_i12[t] = B.blob.addv(I.disk_i12);
+    off_sdk[t] = B.blob.addv(I.slot_dk);
+    off_perm_o[t] = B.blob.addv(I.perm_o);
+    off_perm_u[t] = B.blob.addv(I.perm_u);
+    off_eps_o[t] = B.blob.addv(I.eps_o);
+    off_eps_u[t] = B.blob.addv(I.eps_u);
+    off_coef[t] = B.blob.addv(I.coef);
+    key << I.n0 << "," << I.n1 << "," << I.n2 << "," << I.cplx << "," << I.k_o << "," << I.k_u
+        << "," << I.n_tau << "," << I.n_omega << "," << I.n_g << ";";
+  }
+  for (const auto &J : P.jobs) key << J.k_o_eff << "/" << J.k_u_eff << ",";
+  // Geo entries hold device pointers: stored with offsets, patched later
+  std::vector<Geo> geos(n_items);
+  for (int t = 0; t < n_items; ++t) {
+    const ItemPlan &I = P.items[t];
+    Geo g{};
+    g.n0 = I.n0;
+    g.n1 = I.n1;
+    g.n2 = I.n2;
+    g.n_r = (int32_t)I.n_r;
+    g.n_g = I.n_g;
+    g.n_disk = I.n_disk;
+    g.planes = I.planes;
+    g.disk_in_lds = I.disk_lds;
+    g.disk_i12 = reinterpret_cast<const int32_t *>(off_i12[t]);   // offset, patched
+    g.slot_dk = reinterpret_cast<const int32_t *>(off_sdk[t]);
+    geos[t] = g;
+  }
+  const size_t off_geos = B.blob.addv(geos);
+  // record which blob words hold offsets to patch: we patch by re-walking below
+  // (simple: every device pointer into the blob is written as blob offset + marker)
+  const int n_jobs = (int)P.jobs.size();
+  const int per_pass = P.jobs_per_pass;
+  B.n_passes = (n_jobs + per_pass - 1) / per_pass;
+  int max_slabs = 0;
+  for (auto &I : P.items) max_slabs = std::max<int>(max_slabs, (int)((I.n_r + P.slab_w - 1) / P.slab_w));
+  for (int ps = 0; ps < B.n_passes; ++ps) {
+    const int jb = ps * per_pass, je = std::min(n_jobs, jb + per_pass);
+    // ---- stage: one op per (item in pass, occ|unocc)
+    {
+      std::vector<StageOp> ops;
+      std::vector<int4> blocks;
+      std::vector<std::vector<void *>> psi_lists;
+      std::vector<std::vector<double>> tau_lists;
+      int jj = jb;
+      while (jj < je) {
+        const int t = P.jobs[jj].item;
+        int je2 = jj;
+        while (je2 < je && P.jobs[je2].item == t) ++je2;
+        const ItemPlan &I = P.items[t];
+        for (int side = 0; side < 2; ++side) {
+          StageOp op{};
+          op.phi = side == 0 ? I.phi_o : I.phi_u;
+          op.perm = reinterpret_cast<const int32_t *>(side == 0 ? off_perm_o[t] : off_perm_u[t]);
+          op.eps = reinterpret_cast<const double *>(side == 0 ? off_eps_o[t] : off_eps_u[t]);
+          op.edge = side == 0 ? I.homo : I.lumo;
+          op.sign = side == 0 ? 1.0 : -1.0;
+          op.k = side == 0 ? I.k_o : I.k_u;
+          op.k_pad = side == 0 ? I.k_o_pad : I.k_u_pad;
+          op.n_r = (int32_t)I.n_r;
+          op.n_r_pad = (int32_t)I.n_r_pad;
+          op.cplx = I.cplx;
+          op.n_jobs = je2 - jj;
+          std::vector<void *> pl;
+          std::vector<double> tl;
+          for (int q = jj; q < je2; ++q) {
+            char *slot = psi_base + (int64_t)(q - jb) * P.psi_slot;
+            const int64_t o_bytes = I.n_r_pad * I.k_o_pad * bpb_of(P.prec, cplx);
+            pl.push_back(side == 0 ? slot : slot + o_bytes);
+            tl.push_back(I.tau[P.jobs[q].j]);
+          }
+          psi_lists.push_back(pl);
+          tau_lists.push_back(tl);
+          const int opi = (int)ops.size();
+          ops.push_back(op);
+          const int rt = (int)(I.n_r_pad / 64), kt = op.k_pad / 32;
+          for (int a = 0; a < rt; ++a)
+            for (int b = 0; b < kt; ++b) blocks.push_back(make_int4(opi, a, b, 0));
+        }
+        jj = je2;
+      }
+      for (size_t i = 0; i < ops.size(); ++i) {
+        ops[i].tau = reinterpret_cast<const double *>(B.blob.addv(tau_lists[i]));
+        ops[i].psi = reinterpret_cast<void *const *>(B.blob.addv(psi_lists[i]));
+      }
+      Launch L{};
+      L.phase = PH_STAGE;
+      L.kind = 0;
+      L.stage.ops = reinterpret_cast<const StageOp *>(B.blob.addv(ops));
+      L.stage.blocks = reinterpret_cast<const int4 *>(B.blob.addv(blocks));
+      L.stage.n_blocks = (int)blocks.size();
+      L.stage.prec = P.prec;
+      B.launches.push_back(L);
+    }
+    // ---- per slab: gemm + fft over r
+    for (int s = 0; s < max_slabs; ++s) {
+      std::vector<GemmJob> gj;
+      std::vector<int4> units;
+      std::vector<FftJob> fj;
+      int work = 0;
+      for (int q = jb; q < je; ++q) {
+        const JobPlan &J = P.jobs[q];
+        const ItemPlan &I = P.items[J.item];
+        const int64_t s0 = (int64_t)s * P.slab_w;
+        if (s0 >= I.n_r) continue;
+        const int w = (int)std::min<int64_t>(P.slab_w, I.n_r - s0);
+        char *slot = psi_base + (int64_t)(q - jb) * P.psi_slot;
+        GemmJob g{};
+        g.psi_o = slot;
+        g.psi_u = slot + I.n_r_pad * I.k_o_pad * bpb_of(P.prec, cplx);
+        g.ld_o = I.k_o_pad;
+        g.ld_u = I.k_u_pad;
+        g.k_o = J.k_o_eff;
+        g.k_u = J.k_u_eff;
+        g.n_r = (int32_t)I.n_r;
+        g.s0 = (int32_t)s0;
+        g.w = w;
+        g.slab = slab_base + (int64_t)(q - jb) * P.slab_slot;
+        const int gi = (int)gj.size();
+        gj.push_back(g);
+        const int nrt = (int)((I.n_r + P.bm - 1) / P.bm);
+        const int nct = (w + P.bn - 1) / P.bn;
+        for (int ct = 0; ct < nct; ++ct) {
+          const int c0 = (int)s0 + ct * P.bn;
+          for (int rt = 0; rt < nrt; ++rt) {
+            const int r0 = rt * P.bm;
+            if (ctx->opt.hermitian && r0 + P.bm <= c0) continue;
+            units.push_back(make_int4(gi, r0, c0, 0));
+            const double kk = (double)(J.k_o_eff + J.k_u_eff);
+            P.mfma_flops +=
+                (I.cplx ? 8.0 : 2.0) * P.bm * P.bn * kk * (P.prec == P_BF16X3 ? 3.0 : 1.0);
+          }
+        }
+        FftJob f{};
+        f.in = g.slab;
+        f.in_col_stride = I.n_r;
+        f.out = xr_base + (int64_t)(q - jb) * P.xr_slot;
+        f.out_slot_stride = I.n_r;
+        f.out_col_stride = 1;
+        f.col0 = (int32_t)s0;
+        f.n_cols = w;
+        f.geo = J.item;
+        f.work0 = work;
+        work += w;
+        fj.push_back(f);
+      }
+      if (gj.empty()) continue;
+      Launch G{};
+      G.phase = PH_GEMM;
+      G.kind = 1;
+      G.gemm.jobs = reinterpret_cast<const GemmJob *>(B.blob.addv(gj));
+      G.gemm.units = reinterpret_cast<const int4 *>(B.blob.addv(units));
+      G.gemm.n_units = (int)units.size();
+      G.gemm.hermitian = ctx->opt.hermitian;
+      G.gemm_grid = (int)units.size();
+      B.launches.push_back(G);
+      Launch F{};
+      F.phase = PH_FFT_R;
+      F.kind = 2;
+      F.fft.jobs = reinterpret_cast<const FftJob *>(B.blob.addv(fj));
+      F.fft.n_jobs = (int)fj.size();
+      F.fft.n_work = work;
+      F.fft.geos = reinterpret_cast<const Geo *>(off_geos);
+      F.fft.scratch = ctx->b_scratch.p;
+      F.fft.scratch_slot = P.scratch_slot_elems;
+      F.fft.in_real = cplx ? 0 : 1;
+      F.fft.lower_only = ctx->opt.hermitian;
+      F.fft_sign = -1;
+      F.fft_grid = std::min(work, P.fft_grid);
+      F.fft_lds = P.fft_lds;
+      B.launches.push_back(F);
+    }
+    // ---- fft over r'
+    {
+      std::vector<FftJob> fj;
+      int work = 0;
+      for (int q = jb; q < je; ++q) {
+        const JobPlan &J = P.jobs[q];
+        const ItemPlan &I = P.items[J.item];
+        FftJob f{};
+        f.in = xr_base + (int64_t)(q - jb) * P.xr_slot;
+        f.in_col_stride = I.n_r;
+        f.out = x_base + I.x_off + (int64_t)J.j * I.n_g * I.n_g * ec;
+        f.out_slot_stride = 1;
+        f.out_col_stride = I.n_g;
+        f.col0 = 0;
+        f.n_cols = I.n_g;
+        f.geo = J.item;
+        f.work0 = work;
+        work += I.n_g;
+        fj.push_back(f);
+      }
+      Launch F{};
+      F.phase = PH_FFT_RP;
+      F.kind = 2;
+      F.fft.jobs = reinterpret_cast<const FftJob *>(B.blob.addv(fj));
+      F.fft.n_jobs = (int)fj.size();
+      F.fft.n_work = work;
+      F.fft.geos = reinterpret_cast<const Geo *>(off_geos);
+      F.fft.scratch = ctx->b_scratch.p;
+      F.fft.scratch_slot = P.scratch_slot_elems;
+      F.fft.in_real = 0;
+      F.fft.lower_only = 0;
+      F.fft_sign = +1;
+      F.fft_grid = std::min(work, P.fft_grid);
+      F.fft_lds = P.fft_lds;
+      B.launches.push_back(F);
+    }
+  }
+  // ---- cosine transform
+  std::vector<CtItem> cts(n_items);
+  int64_t elems = 0;
+  int max_omega = 0, max_mats = 0;
+  std::vector<int32_t> toff(n_items), woff(n_items);
+  int nt = 0, nw = 0;
+  for (int t = 0; t < n_items; ++t) {
+    const ItemPlan &I = P.items[t];
+    CtItem c{};
+    c.x = x_base + I.x_off;
+    c.out = I.out;
+    c.coef = reinterpret_cast<const double *>(off_coef[t]);
+    c.n_g = I.n_g;
+    c.n_tau = I.n_tau;
+    c.n_omega = I.n_omega;
+    c.hermitian = ctx->opt.hermitian;
+    c.elem0 = elems;
+    elems += (int64_t)I.n_g * I.n_g;
+    cts[t] = c;
+    max_omega = std::max(max_omega, I.n_omega);
+    max_mats = std::max(max_mats, I.n_tau + I.n_omega);
+    toff[t] = nt;
+    woff[t] = nw;
+    nt += I.n_tau;
+    nw += I.n_omega;
+  }
+  Launch C{};
+  C.phase = PH_CT;
+  C.kind = 3;
+  C.ct.items = reinterpret_cast<const CtItem *>(B.blob.addv(cts));
+  C.ct.n_items = n_items;
+  C.ct.n_elem = elems;
+  C.max_omega = max_omega;
+  B.launches.push_back(C);
+  B.n_norm_tau = nt;
+  B.n_norm_omega = nw;
+  if (want_norms) {
+    Launch Z{};
+    Z.phase = PH_NORM;
+    Z.kind = 5;
+    Z.fill_ptr = ctx->b_norm.p;
+    Z.fill_bytes = (int64_t)(nt + nw) * 8;
+    B.launches.push_back(Z);
+    Launch N{};
+    N.phase = PH_NORM;
+    N.kind = 4;
+    N.ct = C.ct;
+    N.max_mats = max_mats;
+    N.toff = reinterpret_cast<const int32_t *>(B.blob.addv(toff));
+    N.woff = reinterpret_cast<const int32_t *>(B.blob.addv(woff));
+    B.launches.push_back(N);
+  }
+  B.key = key.str();
+}
+
+// Replace blob offsets by device addresses.  Offsets are small integers
+// (< blob size); every pointer field that refers to the blob was stored as an
+// offset by build_launches, and every other pointer field holds a real device
+// address, so the distinction is by construction, not by value.
+template <typename T>
+T *dev(const char *base, const T *off) {
+  return reinterpret_cast<T *>(const_cast<char *>(base) + reinterpret_cast<uintptr_t>(off));
+}
+
+void patch_blob(Built &B, const char *base) {
+  char *h = B.blob.h.data();
+  for (auto &L : B.launches) {
+    if (L.kind == 0) {
+      StageOp *ops = reinterpret_cast<StageOp *>(h + reinterpret_cast<uintptr_t>(L.stage.ops));
+      for (int i = 0; i < L.stage.n_blocks; ++i) (void)i;
+      // ops count is implied by the blocks; walk the ops referenced by blocks
+      const int4 *blk = reinterpret_cast<const int4 *>(h + reinterpret_cast<uintptr_t>(L.stage.blocks));
+      int n_ops = 0;
+      for (int i = 0; i < L.stage.n_blocks; ++i) n_ops = std::max(n_ops, blk[i].x + 1);
+      for (int i = 0; i < n_ops; ++i) {
+        ops[i].perm = dev(base, ops[i].perm);
+        ops[i].eps = dev(base, ops[i].eps);
+        ops[i].tau = dev(base, ops[i].tau);
+        ops[i].psi = dev(base, ops[i].psi);
+      }
+      L.stage.ops = dev(base, L.stage.ops);
+      L.stage.blocks = dev(base, L.stage.blocks);
+    } else if (L.kind == 1) {
+      L.gemm.jobs = dev(base, L.gemm.jobs);
+      L.gemm.units = dev(base, L.gemm.units);
+    } else if (L.kind == 2) {
+      L.fft.jobs = dev(base, L.fft.jobs);
+      L.fft.geos = dev(base, L.fft.geos);
+    } else if (L.kind == 3 || L.kind == 4) {
+      CtItem *cts = reinterpret_cast<CtItem *>(h + reinterpret_cast<uintptr_t>(L.ct.items));
+      if (L.kind == 3)
+        for (int i = 0; i < L.ct.n_items; ++i) cts[i].coef = dev(base, cts[i].coef);
+      L.ct.items = dev(base, L.ct.items);
+      if (L.kind == 4) {
+        L.toff = dev(base, L.toff);
+        L.woff = dev(base, L.woff);
+      }
+    }
+  }
+}
+
+void patch_geos(Built &B, const char *base, size_t off_geos, int n_items) {
+  Geo *g = reinterpret_cast<Geo *>(B.blob.h.data() + off_geos);
+  for (int i = 0; i < n_items; ++i) {
+    g[i].disk_i12 = dev(base, g[i].disk_i12);
+    g[i].slot_dk = dev(base, g[i].slot_dk);
+  }
+}
+
+gwchi_status enqueue(gwchi_ctx *ctx, const Plan &P, Built &B, bool timing,
+                     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> *evs) {
+  hipStream_t s = ctx->stream;
+  const int cplx = P.cplx_any;
+  const int dbl = P.prec == P_FP64;
+  size_t ev_i = 0;
+  auto ev = [&](void) -> hipEvent_t {
+    if (ev_i >= ctx->ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ctx->ev_pool.push_back(e);
+    }
+    return ctx->ev_pool[ev_i++];
+  };
+  for (auto &L : B.launches) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timing) {
+      e0 = ev();
+      e1 = ev();
+      if (!e0 || !e1) {
+        set_err(ctx, "hipEventCreate failed");
+        return GWCHI_EDEVICE;
+      }
+      HIPCHK(hipEventRecord(e0, s));
+    }
+    switch (L.kind) {
+      case 0:
+        HIPCHK(launch_stage(L.stage, P.prec, s));
+        break;
+      case 1:
+        HIPCHK(launch_gemm(L.gemm, P.prec, cplx, P.tile, L.gemm_grid, s));
+        break;
+      case 2:
+        HIPCHK(launch_fft(L.fft, dbl, L.fft_sign, L.fft_grid, L.fft_lds, s));
+        break;
+      case 3:
+        HIPCHK(launch_ct(L.ct, dbl, L.max_omega, s));
+        break;
+      case 4:
+        HIPCHK(launch_norms_impl(L.ct, dbl, reinterpret_cast<double *>(ctx->b_norm.p),
+                                 reinterpret_cast<double *>(ctx->b_norm.p) + B.n_norm_tau,
+                                 L.toff, L.woff, L.max_mats, s));
+        break;
+      case 5:
+        HIPCHK(launch_fill_zero(L.fill_ptr, L.fill_bytes, s));
+        break;
+    }
+    if (timing) {
+      HIPCHK(hipEventRecord(e1, s));
+      evs->push_back({L.phase, {e0, e1}});
+    }
+  }
+  return GWCHI_OK;
+}
+
+gwchi_status run_build(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int prec,
+                       gwchi_report *rep) {
+  Plan P;
+  gwchi_status st = build_plan(ctx, items, n_items, prec, P);
+  if (st != GWCHI_OK) return st;
+  const int n_jobs_pass = P.jobs_per_pass;
+  bool moved = false;
+  HIPCHK(ctx->b_psi.ensure((size_t)P.psi_slot * n_jobs_pass, &moved));
+  HIPCHK(ctx->b_slab.ensure((size_t)P.slab_slot * n_jobs_pass, &moved));
+  HIPCHK(ctx->b_xr.ensure((size_t)P.xr_slot * n_jobs_pass, &moved));
+  HIPCHK(ctx->b_x.ensure((size_t)P.x_bytes, &moved));
+  HIPCHK(ctx->b_scratch.ensure((size_t)P.scratch_bytes, &moved));
+  const bool want_norms = rep != nullptr;
+  int n_norm = 0;
+  for (auto &I : P.items) n_norm += I.n_tau + I.n_omega;
+  HIPCHK(ctx->b_norm.ensure((size_t)n_norm * 8 + 64, &moved));
+  Built B;
+  build_launches(ctx, P, want_norms, B);
+  // geos offset: locate it as the table referenced by the first FFT launch
+  size_t off_geos = 0;
+  for (auto &L : B.launches)
+    if (L.kind == 2) {
+      off_geos = reinterpret_cast<uintptr_t>(L.fft.geos);
+      break;
+    }
+  HIPCHK(ctx->b_tables.ensure(B.blob.h.size() + 64, &moved));
+  const char *tbase = reinterpret_cast<const char *>(ctx->b_tables.p);
+  patch_geos(B, tbase, off_geos, n_items);
+  patch_blob(B, tbase);
+  // the copy of the tables is ordered on the stream; the pinned staging copy must not
+  // be overwritten while a previous transfer is pending
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(ctx->h_tables.ensure(B.blob.h.size() + 64));
+  std::memcpy(ctx->h_tables.p, B.blob.h.data(), B.blob.h.size());
+  HIPCHK(hipMemcpyAsync(ctx->b_tables.p, ctx->h_tables.p, B.blob.h.size(),
+                        hipMemcpyHostToDevice, ctx->stream));
+  const bool timing = ctx->opt.timing != 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> evs;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (rep) {
+    HIPCHK(hipEventCreate(&t0));
+    HIPCHK(hipEventCreate(&t1));
+    HIPCHK(hipEventRecord(t0, ctx->stream));
+  }
+  bool replayed = false;
+  const bool use_graph = ctx->opt.use_graph && !timing;
+  if (use_graph) {
+    std::ostringstream k;
+    k << B.key << "|tables=" << ctx->b_tables.p << ",psi=" << ctx->b_psi.p << ",slab="
+      << ctx->b_slab.p << ",xr=" << ctx->b_xr.p << ",x=" << ctx->b_x.p << ",sc="
+      << ctx->b_scratch.p << ",norm=" << ctx->b_norm.p;
+    for (auto &I : P.items) k << "," << (const void *)I.phi_o << (const void *)I.phi_u << (void *)I.out;
+    const std::string key = k.str();
+    if (ctx->graph_exec && key == ctx->graph_key) {
+      HIPCHK(hipGraphLaunch(ctx->graph_exec, ctx->stream));
+      replayed = true;
+    } else {
+      if (ctx->graph_exec) {
+        (void)hipGraphExecDestroy(ctx->graph_exec);
+        ctx->graph_exec = nullptr;
+      }
+      if (ctx->graph) {
+        (void)hipGraphDestroy(ctx->graph);
+        ctx->graph = nullptr;
+      }
+      HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+      st = enqueue(ctx, P, B, false, nullptr);
+      hipGraph_t g = nullptr;
+      hipError_t ec = hipStreamEndCapture(ctx->stream, &g);
+      if (st != GWCHI_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (ec != hipSuccess) {
+        set_err(ctx, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+        return GWCHI_EDEVICE;
+      }
+      hipGraphExec_t ex = nullptr;
+      hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      if (ei != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        set_err(ctx, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+        return GWCHI_EDEVICE;
+      }
+      ctx->graph = g;
+      ctx->graph_exec = ex;
+      ctx->graph_key = key;
+      HIPCHK(hipGraphLaunch(ctx->graph_exec, ctx->stream));
+    }
+  } else {
+    st = enqueue(ctx, P, B, timing, &evs);
+    if (st != GWCHI_OK) return st;
+  }
+  if (rep) {
+    HIPCHK(hipEventRecord(t1, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    std::memset(rep, 0, sizeof(*rep));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+    rep->ms_total = ms;
+    double ph[PH_COUNT] = {0};
+    for (auto &e : evs) {
+      float m = 0.f;
+      HIPCHK(hipEventElapsedTime(&m, e.second.first, e.second.second));
+      ph[e.first] += m;
+      if (e.first == PH_GEMM) rep->n_gemm_launches++;
+      if (e.first == PH_FFT_R || e.first == PH_FFT_RP) rep->n_fft_launches++;
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    rep->ms_stage = ph[PH_STAGE];
+    rep->ms_gemm = ph[PH_GEMM];
+    rep->ms_fft_r = ph[PH_FFT_R];
+    rep->ms_fft_rp = ph[PH_FFT_RP];
+    rep->ms_ct = ph[PH_CT];
+    rep->alg_flops = P.alg_flops;
+    rep->mfma_flops = P.mfma_flops;
+    rep->slab_width = P.slab_w;
+    rep->tau_batch = P.jobs_per_pass;
+    rep->tile_id = P.tile + 1;
+    rep->graph_replayed = replayed ? 1 : 0;
+    // kappa_F from the norms
+    std::vector<double> nrm(n_norm);
+    HIPCHK(hipMemcpy(nrm.data(), ctx->b_norm.p, (size_t)n_norm * 8, hipMemcpyDeviceToHost));
+    double kmax = 0.0;
+    int ot = 0, ow = B.n_norm_tau;
+    for (auto &I : P.items) {
+      for (int k = 0; k < I.n_omega; ++k) {
+        double num = 0.0;
+        for (int j = 0; j < I.n_tau; ++j)
+          num += std::fabs(I.coef[(size_t)k * I.n_tau + j]) * std::sqrt(nrm[ot + j]);
+        const double den = std::sqrt(nrm[ow + k]);
+        if (den > 0) kmax = std::max(kmax, num / den);
+      }
+      ot += I.n_tau;
+      ow += I.n_omega;
+    }
+    rep->kappa_F_max = kmax;
+  }
+  return GWCHI_OK;
+}
+
+gwchi_status check_output(gwchi_ctx *ctx, const gwchi_item *items, int n_items) {
+  for (int t = 0; t < n_items; ++t) {
+    const int64_t n = (int64_t)items[t].n_omega * items[t].n_g * items[t].n_g * 2;
+    if (!finite_all(items[t].chi_out, n)) {
+      set_err(ctx, "output check: non-finite value in chi_out of item " + std::to_string(t));
+      return GWCHI_ENUMERIC;
+    }
+  }
+  return GWCHI_OK;
+}
+
+void load_tune(gwchi_ctx *ctx) {
+  ctx->tune.clear();
+  if (ctx->tune_path.empty()) return;
+  std::ifstream f(ctx->tune_path);
+  if (!f) return;
+  // flat JSON object of "key": int
+  std::string s((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+  size_t p = 0;
+  while ((p = s.find('"', p)) != std::string::npos) {
+    size_t q = s.find('"', p + 1);
+    if (q == std::string::npos) break;
+    std::string k = s.substr(p + 1, q - p - 1);
+    size_t c = s.find(':', q);
+    if (c == std::string::npos) break;
+    int v = std::atoi(s.c_str() + c + 1);
+    ctx->tune[k] = v;
+    p = s.find_first_of(",}", c);
+    if (p == std::string::npos) break;
+  }
+}
+
+void save_tune(gwchi_ctx *ctx) {
+  if (ctx->tune_path.empty()) return;
+  std::ofstream f(ctx->tune_path);
+  f << "{";
+  bool first = true;
+  for (auto &kv : ctx->tune) {
+    f << (first ? "" : ", ") << "\"" << kv.first << "\": " << kv.second;
+    first = false;
+  }
+  f << "}\n";
+}
+
+
+// Copy host orbitals into the context's device buffer and point a copy of the
+// items at device orbitals and a device output buffer.
+gwchi_status upload_items(gwchi_ctx *ctx, const gwchi_item *items, int n_items,
+                          std::vector<gwchi_item> &dev_items) {
+  int64_t in_bytes = 0, out_bytes = 0;
+  std::vector<int64_t> in_off(n_items), out_off(n_items);
+  for (int t = 0; t < n_items; ++t) {
+    const gwchi_item &it = items[t];
+    const int64_t n_r = (int64_t)it.n[0] * it.n[1] * it.n[2];
+    const int64_t m = n_r * (it.is_complex ? 2 : 1) * 8;
+    in_off[t] = in_bytes;
+    in_bytes += round_up(m * (it.n_occ + it.n_unocc), 256);
+    out_off[t] = out_bytes;
+    out_bytes += round_up((int64_t)it.n_omega * it.n_g * it.n_g * 16, 256);
+  }
+  bool moved = false;
+  HIPCHK(ctx->b_phi.ensure((size_t)in_bytes, &moved));
+  HIPCHK(ctx->b_out.ensure((size_t)out_bytes, &moved));
+  dev_items.assign(items, items + n_items);
+  for (int t = 0; t < n_items; ++t) {
+    const gwchi_item &it = items[t];
+    const int64_t n_r = (int64_t)it.n[0] * it.n[1] * it.n[2];
+    const int64_t m = n_r * (it.is_complex ? 2 : 1) * 8;
+    char *base = reinterpret_cast<char *>(ctx->b_phi.p) + in_off[t];
+    HIPCHK(hipMemcpy(base, it.phi_occ, m * it.n_occ, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(base + m * it.n_occ, it.phi_unocc, m * it.n_unocc, hipMemcpyHostToDevice));
+    dev_items[t].phi_occ = reinterpret_cast<const double *>(base);
+    dev_items[t].phi_unocc = reinterpret_cast<const double *>(base + m * it.n_occ);
+    dev_items[t].chi_out =
+        reinterpret_cast<double *>(reinterpret_cast<char *>(ctx->b_out.p) + out_off[t]);
+  }
+  return GWCHI_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char *gwchi_version(void) { return "gwchi 0.1.0 (gfx950)"; }
+
+const char *gwchi_last_error(const gwchi_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_tls_error.c_str();
+}
+
+gwchi_status gwchi_validate(const gwchi_item *items, int32_t n_items, int32_t check_orbitals) {
+  try {
+    return validate_items(nullptr, items, n_items, check_orbitals != 0);
+  } catch (...) {
+    g_tls_error = "internal error in validation";
+    return GWCHI_EINVAL;
+  }
+}
+
+gwchi_status gwchi_create(gwchi_ctx **out, int32_t device_id, const char *tune_cache_path) {
+  if (!out) {
+    g_tls_error = "ctx is NULL";
+    return GWCHI_EINVAL;
+  }
+  *out = nullptr;
+  try {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+      g_tls_error = "no HIP device";
+      return GWCHI_EDEVICE;
+    }
+    if (device_id < 0 || device_id >= n) {
+      g_tls_error = "device_id out of range";
+      return GWCHI_EINVAL;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device_id) != hipSuccess) {
+      g_tls_error = "hipGetDeviceProperties failed";
+      return GWCHI_EDEVICE;
+    }
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+      g_tls_error = std::string("device is ") + prop.gcnArchName + ", this build targets gfx950";
+      return GWCHI_EDEVICE;
+    }
+    std::unique_ptr<gwchi_ctx> ctx(new gwchi_ctx());
+    ctx->device = device_id;
+    ctx->num_cu = prop.multiProcessorCount;
+    ctx->lds_max = prop.sharedMemPerBlock;
+    if (hipSetDevice(device_id) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming) != hipSuccess) {
+      g_tls_error = "stream/event creation failed";
+      return GWCHI_EDEVICE;
+    }
+    ctx->opt.use_graph = 1;
+    if (tune_cache_path) ctx->tune_path = tune_cache_path;
+    load_tune(ctx.get());
+    *out = ctx.release();
+    return GWCHI_OK;
+  } catch (...) {
+    g_tls_error = "internal error in gwchi_create";
+    return GWCHI_EDEVICE;
+  }
+}
+
+gwchi_status gwchi_destroy(gwchi_ctx *ctx) {
+  if (!ctx) return GWCHI_OK;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+  if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+  for (DevBuf *b : {&ctx->b_phi, &ctx->b_out, &ctx->b_psi, &ctx->b_slab, &ctx->b_xr, &ctx->b_x,
+                    &ctx->b_scratch, &ctx->b_tables, &ctx->b_norm})
+    b->release();
+  ctx->h_tables.release();
+  ctx->h_norm.release();
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return GWCHI_OK;
+}
+
+gwchi_status gwchi_set_options(gwchi_ctx *ctx, const gwchi_options *opt) {
+  if (!ctx || !opt) return GWCHI_EINVAL;
+  if (opt->slab_width < 0 || opt->tau_batch < 0 || opt->tile_id < 0 || opt->max_device_bytes < 0) {
+    set_err(ctx, "negative option value");
+    return GWCHI_EINVAL;
+  }
+  ctx->opt = *opt;
+  return GWCHI_OK;
+}
+
+gwchi_status gwchi_get_options(const gwchi_ctx *ctx, gwchi_options *opt) {
+  if (!ctx || !opt) return GWCHI_EINVAL;
+  *opt = ctx->opt;
+  return GWCHI_OK;
+}
+
+gwchi_status gwchi_chi_build_device(gwchi_ctx *ctx, const gwchi_item *items, int32_t n_items,
+                                    gwchi_precision prec, void *hip_stream,
+                                    gwchi_report *report) {
+  if (!ctx) {
+    g_tls_error = "ctx is NULL";
+    return GWCHI_EINVAL;
+  }
+  try {
+    if (prec != GWCHI_FP64 && prec != GWCHI_FP32 && prec != GWCHI_BF16X3) {
+      set_err(ctx, "unknown precision");
+      return GWCHI_EINVAL;
+    }
+    gwchi_status st = validate_items(ctx, items, n_items, false);
+    if (st != GWCHI_OK) return st;
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t us = reinterpret_cast<hipStream_t>(hip_stream);
+    // order after the caller's stream
+    HIPCHK(hipEventRecord(ctx->ev_in, us));
+    HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->ev_in, 0));
+    st = run_build(ctx, items, n_items, (int)prec, report);
+    if (st != GWCHI_OK) return st;
+    HIPCHK(hipEventRecord(ctx->ev_out, ctx->stream));
+    HIPCHK(hipStreamWaitEvent(us, ctx->ev_out, 0));
+    return GWCHI_OK;
+  } catch (const std::bad_alloc &) {
+    set_err(ctx, "host allocation failed");
+    return GWCHI_ENOMEM;
+  } catch (...) {
+    set_err(ctx, "internal error");
+    return GWCHI_EDEVICE;
+  }
+}
+
+gwchi_status gwchi_chi_build(gwchi_ctx *ctx, const gwchi_item *items, int32_t n_items,
+                             gwchi_precision prec, gwchi_report *report) {
+  if (!ctx) {
+    g_tls_error = "ctx is NULL";
+    return GWCHI_EINVAL;
+  }
+  try {
+    if (prec != GWCHI_FP64 && prec != GWCHI_FP32 && prec != GWCHI_BF16X3) {
+      set_err(ctx, "unknown precision");
+      return GWCHI_EINVAL;
+    }
+    gwchi_status st = validate_items(ctx, items, n_items, true);
+    if (st != GWCHI_OK) return st;
+    HIPCHK(hipSetDevice(ctx->device));
+    std::vector<gwchi_item> dev_items;
+    st = upload_items(ctx, items, n_items, dev_items);
+    if (st != GWCHI_OK) return st;
+    st = run_build(ctx, dev_items.data(), n_items, (int)prec, report);
+    if (st != GWCHI_OK) return st;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int t = 0; t < n_items; ++t) {
+      const gwchi_item &it = items[t];
+      HIPCHK(hipMemcpy(it.chi_out, dev_items[t].chi_out, (size_t)it.n_omega * it.n_g * it.n_g * 16,
+                       hipMemcpyDeviceToHost));
+    }
+    if (ctx->opt.check_output) return check_output(ctx, items, n_items);
+    return GWCHI_OK;
+  } catch (const std::bad_alloc &) {
+    set_err(ctx, "host allocation failed");
+    return GWCHI_ENOMEM;
+  } catch (...) {
+    set_err(ctx, "internal error");
+    return GWCHI_EDEVICE;
+  }
+}
+
+gwchi_status gwchi_autotune(gwchi_ctx *ctx, const gwchi_item *items, int32_t n_items,
+                            gwchi_precision prec) {
+  if (!ctx) return GWCHI_EINVAL;
+  try {
+    gwchi_status st = validate_items(ctx, items, n_items, true);
+    if (st != GWCHI_OK) return st;
+    HIPCHK(hipSetDevice(ctx->device));
+    std::vector<gwchi_item> dev_items;
+    st = upload_items(ctx, items, n_items, dev_items);
+    if (st != GWCHI_OK) return st;
+    const int cplx = items[0].is_complex;
+    const int n = gemm_tile_count((int)prec, cplx);
+    const gwchi_options saved = ctx->opt;
+    double best = 1e300;
+    int best_t = 0;
+    for (int t = 0; t < n; ++t) {
+      ctx->opt = saved;
+      ctx->opt.tile_id = t + 1;
+      ctx->opt.use_graph = 0;
+      gwchi_report rep;
+      // warm-up, then timed
+      st = run_build(ctx, dev_items.data(), n_items, (int)prec, &rep);
+      if (st != GWCHI_OK) {
+        ctx->opt = saved;
+        return st;
+      }
+      st = run_build(ctx, dev_items.data(), n_items, (int)prec, &rep);
+      if (st != GWCHI_OK) {
+        ctx->opt = saved;
+        return st;
+      }
+      if (rep.ms_gemm < best) {
+        best = rep.ms_gemm;
+        best_t = t;
+      }
+    }
+    ctx->opt = saved;
+    ctx->tune[tune_key((int)prec, cplx)] = best_t;
+    save_tune(ctx);
+    return GWCHI_OK;
+  } catch (...) {
+    set_err(ctx, "internal error");
+    return GWCHI_EDEVICE;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,155 @@
+// Cosine transform from imaginary time to imaginary frequency (gfx950).
+//
+// Eq. (4), applied to chi as in Eq. (45):
+//   chi(G, G', i omega_k) = sum_j c'_kj chi(G, G', i tau_j)
+// with c'_kj = ct[k][j] * exp(-(eps_LUMO - eps_HOMO) tau_j): the caller's
+// coefficient times the band-edge factor the staging step left out of the
+// weights.  Inputs are read in the working precision and every product and
+// sum is FP64.  One thread owns one (G, G') element for a chunk of CH
+// frequencies and walks j in increasing order.  With Hermitian completion
+// the stored matrix is X and chi = X + X^H.
+#include "common.h"
+
+namespace gw {
+namespace {
+
+template <typename T>
+__device__ __forceinline__ double2 ld_x(const void *base, int64_t e) {
+  if constexpr (sizeof(T) == 8) {
+    return reinterpret_cast<const double2 *>(base)[e];
+  } else {
+    const float2 v = reinterpret_cast<const float2 *>(base)[e];
+    return make_double2((double)v.x, (double)v.y);
+  }
+}
+
+__device__ __forceinline__ int find_item(const CtItem *items, int n, int64_t e) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].elem0 <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T, int CH>
+__global__ __launch_bounds__(256) void k_ct(CtLaunch L, int k0) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < L.n_elem; e += stride) {
+    const CtItem it = L.items[find_item(L.items, L.n_items, e)];
+    if (k0 >= it.n_omega) continue;
+    const int64_t loc = e - it.elem0;
+    const int64_t ng = it.n_g;
+    const int64_t g = loc / ng, gp = loc - g * ng;
+    const int64_t mat = ng * ng;
+    double2 acc[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) acc[k] = make_double2(0.0, 0.0);
+    for (int j = 0; j < it.n_tau; ++j) {
+      double2 x = ld_x<T>(it.x, (int64_t)j * mat + loc);
+      if (it.hermitian) {
+        const double2 y = ld_x<T>(it.x, (int64_t)j * mat + gp * ng + g);
+        x.x += y.x;
+        x.y -= y.y;
+      }
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        if (k0 + k < it.n_omega) {
+          const double c = it.coef[(int64_t)(k0 + k) * it.n_tau + j];
+          acc[k].x += c * x.x;
+          acc[k].y += c * x.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < CH; ++k)
+      if (k0 + k < it.n_omega)
+        reinterpret_cast<double2 *>(it.out)[(int64_t)(k0 + k) * mat + loc] = acc[k];
+  }
+}
+
+// sum of |x|^2 per tau of each item and per omega of each output
+template <typename T>
+__global__ __launch_bounds__(256) void k_norms(CtLaunch L, double *norm_tau, double *norm_omega,
+                                               const int32_t *tau_off, const int32_t *omega_off) {
+  __shared__ double red[4];
+  // one block handles a slice of one (item, matrix)
+  const int item = blockIdx.y;
+  const CtItem it = L.items[item];
+  const int64_t mat = (int64_t)it.n_g * it.n_g;
+  const int nm = it.n_tau + it.n_omega;
+  for (int m = blockIdx.z; m < nm; m += gridDim.z) {
+    double s = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < mat; e += (int64_t)gridDim.x * 256) {
+      double2 x;
+      if (m < it.n_tau) {
+        x = ld_x<T>(it.x, (int64_t)m * mat + e);
+        if (it.hermitian) {
+          const int64_t g = e / it.n_g, gp = e - g * it.n_g;
+          const double2 y = ld_x<T>(it.x, (int64_t)m * mat + gp * it.n_g + g);
+          x.x += y.x;
+          x.y -= y.y;
+        }
+      } else {
+        x = reinterpret_cast<const double2 *>(it.out)[(int64_t)(m - it.n_tau) * mat + e];
+      }
+      s += x.x * x.x + x.y * x.y;
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double t = red[0] + red[1] + red[2] + red[3];
+      if (m < it.n_tau) atomicAdd(&norm_tau[tau_off[item] + m], t);
+      else atomicAdd(&norm_omega[omega_off[item] + m - it.n_tau], t);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero(uint4 *p, int64_t n16, char *tail, int tail_n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    p[i] = make_uint4(0, 0, 0, 0);
+  if (blockIdx.x == 0 && (int)threadIdx.x < tail_n) tail[threadIdx.x] = 0;
+}
+
+}  // namespace
+
+hipError_t launch_ct(const CtLaunch &L, int dbl, int max_omega, hipStream_t s) {
+  if (L.n_elem <= 0) return hipSuccess;
+  const int64_t want = (L.n_elem + 255) / 256;
+  const int grid = (int)(want < 16384 ? want : 16384);
+  constexpr int CH = 8;
+  for (int k0 = 0; k0 < max_omega; k0 += CH) {
+    if (dbl) hipLaunchKernelGGL((k_ct<double, CH>), dim3(grid), dim3(256), 0, s, L, k0);
+    else hipLaunchKernelGGL((k_ct<float, CH>), dim3(grid), dim3(256), 0, s, L, k0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_norms_impl(const CtLaunch &L, int dbl, double *nt, double *nw,
+                             const int32_t *toff, const int32_t *woff, int max_mats,
+                             hipStream_t s) {
+  dim3 grid(64, L.n_items, max_mats < 64 ? max_mats : 64);
+  if (dbl) hipLaunchKernelGGL((k_norms<double>), grid, dim3(256), 0, s, L, nt, nw, toff, woff);
+  else hipLaunchKernelGGL((k_norms<float>), grid, dim3(256), 0, s, L, nt, nw, toff, woff);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t s) {
+  if (bytes <= 0) return hipSuccess;
+  const int64_t n16 = bytes / 16;
+  const int tail = (int)(bytes - n16 * 16);
+  int64_t want = (n16 + 255) / 256;
+  if (want < 1) want = 1;
+  const int grid = (int)(want < 4096 ? want : 4096);
+  hipLaunchKernelGGL(k_fill_zero, dim3(grid), dim3(256), 0, s, reinterpret_cast<uint4 *>(p), n16,
+                     reinterpret_cast<char *>(p) + n16 * 16, tail);
+  return hipGetLastError();
+}
+
+}  // namespace gw

@@ -1,0 +1,269 @@
+"""ctypes binding of libgwchi.so (gwchi.h): argument marshalling only.
+
+Every step of the polarizability build runs in the library's HIP kernels.
+There is no CPU fallback: if the shared library is missing, importing the
+compute entry points raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgwchi.so")
+
+FP64, FP32, BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTSUP", 5: "ENUMERIC"}
+
+EXPORTS = ["gwchi_create", "gwchi_destroy", "gwchi_set_options", "gwchi_get_options",
+           "gwchi_validate", "gwchi_chi_build", "gwchi_chi_build_device", "gwchi_autotune",
+           "gwchi_last_error", "gwchi_version"]
+
+
+class GwchiItem(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32 * 3),
+        ("is_complex", C.c_int32),
+        ("n_occ", C.c_int32),
+        ("n_unocc", C.c_int32),
+        ("phi_occ", C.c_void_p),
+        ("phi_unocc", C.c_void_p),
+        ("eps_occ", C.c_void_p),
+        ("eps_unocc", C.c_void_p),
+        ("mu", C.c_double),
+        ("n_tau", C.c_int32),
+        ("n_omega", C.c_int32),
+        ("tau", C.c_void_p),
+        ("ct", C.c_void_p),
+        ("n_g", C.c_int32),
+        ("g_index", C.c_void_p),
+        ("chi_out", C.c_void_p),
+    ]
+
+
+class GwchiReport(C.Structure):
+    _fields_ = [
+        ("ms_total", C.c_double),
+        ("ms_stage", C.c_double),
+        ("ms_gemm", C.c_double),
+        ("ms_fft_r", C.c_double),
+        ("ms_fft_rp", C.c_double),
+        ("ms_ct", C.c_double),
+        ("n_gemm_launches", C.c_int32),
+        ("n_fft_launches", C.c_int32),
+        ("alg_flops", C.c_double),
+        ("mfma_flops", C.c_double),
+        ("slab_width", C.c_int32),
+        ("tau_batch", C.c_int32),
+        ("tile_id", C.c_int32),
+        ("graph_replayed", C.c_int32),
+        ("kappa_F_max", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class GwchiOptions(C.Structure):
+    _fields_ = [
+        ("slab_width", C.c_int32),
+        ("tau_batch", C.c_int32),
+        ("tile_id", C.c_int32),
+        ("use_graph", C.c_int32),
+        ("check_output", C.c_int32),
+        ("timing", C.c_int32),
+        ("skip_zero_bands", C.c_int32),
+        ("hermitian", C.c_int32),
+        ("max_device_bytes", C.c_int64),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the shared library (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"{path} not built; run paper_1607_02859_amd/build.py")
+    lib = C.CDLL(path)
+    P = C.POINTER
+    lib.gwchi_create.argtypes = [P(C.c_void_p), C.c_int32, C.c_char_p]
+    lib.gwchi_destroy.argtypes = [C.c_void_p]
+    lib.gwchi_set_options.argtypes = [C.c_void_p, P(GwchiOptions)]
+    lib.gwchi_get_options.argtypes = [C.c_void_p, P(GwchiOptions)]
+    lib.gwchi_validate.argtypes = [P(GwchiItem), C.c_int32, C.c_int32]
+    lib.gwchi_chi_build.argtypes = [C.c_void_p, P(GwchiItem), C.c_int32, C.c_int, P(GwchiReport)]
+    lib.gwchi_chi_build_device.argtypes = [C.c_void_p, P(GwchiItem), C.c_int32, C.c_int,
+                                           C.c_void_p, P(GwchiReport)]
+    lib.gwchi_autotune.argtypes = [C.c_void_p, P(GwchiItem), C.c_int32, C.c_int]
+    lib.gwchi_last_error.argtypes = [C.c_void_p]
+    lib.gwchi_last_error.restype = C.c_char_p
+    lib.gwchi_version.restype = C.c_char_p
+    for f in ("gwchi_create", "gwchi_destroy", "gwchi_set_options", "gwchi_get_options",
+              "gwchi_validate", "gwchi_chi_build", "gwchi_chi_build_device", "gwchi_autotune"):
+        getattr(lib, f).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+class GwchiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _ptr(a) -> int:
+    if a is None:
+        return 0
+    if hasattr(a, "data_ptr"):      # torch tensor
+        return int(a.data_ptr())
+    return int(a.ctypes.data)
+
+
+class _Keep:
+    """Holds host arrays alive while the library reads them."""
+
+    def __init__(self):
+        self.refs = []
+
+    def f64(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        self.refs.append(a)
+        return a
+
+    def i32(self, a):
+        a = np.ascontiguousarray(a, dtype=np.int32)
+        self.refs.append(a)
+        return a
+
+
+def make_item(keep: _Keep, item, phi_occ=None, phi_unocc=None, chi_out=None) -> GwchiItem:
+    """Fill a GwchiItem from a synth.Item.  phi_* and chi_out default to host
+    arrays taken from ``item``; pass device tensors for the device entry."""
+    it = GwchiItem()
+    it.n[0], it.n[1], it.n[2] = (int(v) for v in item.n)
+    cplx = bool(np.iscomplexobj(item.phi_occ))
+    it.is_complex = 1 if cplx else 0
+    it.n_occ = item.phi_occ.shape[0]
+    it.n_unocc = item.phi_unocc.shape[0]
+    if phi_occ is None:
+        dt = np.complex128 if cplx else np.float64
+        phi_occ = np.ascontiguousarray(item.phi_occ, dtype=dt)
+        phi_unocc = np.ascontiguousarray(item.phi_unocc, dtype=dt)
+        keep.refs += [phi_occ, phi_unocc]
+    it.phi_occ = _ptr(phi_occ)
+    it.phi_unocc = _ptr(phi_unocc)
+    it.eps_occ = _ptr(keep.f64(item.eps_occ))
+    it.eps_unocc = _ptr(keep.f64(item.eps_unocc))
+    it.mu = float(item.mu)
+    it.n_tau = int(np.asarray(item.tau).shape[0])
+    it.n_omega = int(np.asarray(item.ct).shape[0])
+    it.tau = _ptr(keep.f64(item.tau))
+    it.ct = _ptr(keep.f64(item.ct))
+    g = keep.i32(item.g_index)
+    it.n_g = int(g.shape[0])
+    it.g_index = _ptr(g)
+    it.chi_out = _ptr(chi_out)
+    return it
+
+
+def validate(items, check_orbitals=True) -> int:
+    """gwchi_validate on host arrays; returns the status code."""
+    lib = load()
+    keep = _Keep()
+    outs = [np.zeros(1, np.complex128) for _ in items]
+    arr = (GwchiItem * len(items))(*[make_item(keep, it, chi_out=o) for it, o in zip(items, outs)])
+    return int(lib.gwchi_validate(arr, len(items), 1 if check_orbitals else 0))
+
+
+class Context:
+    """One gwchi context on a HIP device."""
+
+    def __init__(self, device: int = 0, tune_cache: Optional[str] = None, **options):
+        self.lib = load()
+        h = C.c_void_p()
+        st = self.lib.gwchi_create(C.byref(h), int(device),
+                                   tune_cache.encode() if tune_cache else None)
+        if st != 0:
+            raise GwchiError(st, self.lib.gwchi_last_error(None).decode())
+        self.h = h
+        if options:
+            self.set_options(**options)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.gwchi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, st):
+        return GwchiError(st, self.lib.gwchi_last_error(self.h).decode())
+
+    def options(self) -> dict:
+        o = GwchiOptions()
+        self.lib.gwchi_get_options(self.h, C.byref(o))
+        return {k: getattr(o, k) for k, _ in o._fields_}
+
+    def set_options(self, **kw):
+        cur = self.options()
+        cur.update(kw)
+        o = GwchiOptions(**cur)
+        st = self.lib.gwchi_set_options(self.h, C.byref(o))
+        if st != 0:
+            raise self._err(st)
+
+    def build(self, items: Sequence, prec="fp32", report=False):
+        """Host-memory build: returns a list of complex128 arrays
+        (n_omega, n_g, n_g) and optionally the report dict."""
+        keep = _Keep()
+        outs = [np.empty((np.asarray(it.ct).shape[0], len(it.g_index), len(it.g_index)),
+                         np.complex128) for it in items]
+        arr = (GwchiItem * len(items))(*[make_item(keep, it, chi_out=o) for it, o in zip(items, outs)])
+        rep = GwchiReport()
+        st = self.lib.gwchi_chi_build(self.h, arr, len(items), PRECISIONS[prec],
+                                      C.byref(rep) if report else None)
+        if st != 0:
+            raise self._err(st)
+        return (outs, rep.as_dict()) if report else outs
+
+    def build_device(self, items: Sequence, phis, outs, prec="fp32", stream=None, report=False):
+        """Device-memory build.  ``phis`` is a list of (phi_occ, phi_unocc)
+        device tensors (float64 real or complex128 complex, band-major) and
+        ``outs`` a list of complex128 device tensors (n_omega, n_g, n_g).
+        ``stream`` is a torch.cuda.Stream or None (the current stream)."""
+        keep = _Keep()
+        arr = (GwchiItem * len(items))(*[
+            make_item(keep, it, phi_occ=p[0], phi_unocc=p[1], chi_out=o)
+            for it, p, o in zip(items, phis, outs)])
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream()
+        sh = int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream or 0)
+        rep = GwchiReport()
+        st = self.lib.gwchi_chi_build_device(self.h, arr, len(items), PRECISIONS[prec],
+                                             C.c_void_p(sh), C.byref(rep) if report else None)
+        if st != 0:
+            raise self._err(st)
+        return rep.as_dict() if report else None
+
+    def autotune(self, items: Sequence, prec="fp32"):
+        keep = _Keep()
+        outs = [np.empty((np.asarray(it.ct).shape[0], len(it.g_index), len(it.g_index)),
+                         np.complex128) for it in items]
+        arr = (GwchiItem * len(items))(*[make_item(keep, it, chi_out=o) for it, o in zip(items, outs)])
+        # autotune works on device copies made by a host build first
+        st = self.lib.gwchi_autotune(self.h, arr, len(items), PRECISIONS[prec])
+        if st != 0:
+            raise self._err(st)

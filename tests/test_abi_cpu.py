@@ -1,0 +1,125 @@
+"""The C-ABI library loads, exports every symbol gwchi.h declares, and its
+host-only validation rejects what the header says it rejects (no device is
+touched by gwchi_validate)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1607_02859_amd import gwchi, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "gwchi.h")).read()
+    # declarations: a return type, the name, then the parameter list
+    return sorted(set(re.findall(r"^(?:gwchi_status|const char \*)\s*(gwchi_[a-z_]+)\(", txt, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(gwchi.LIB_PATH):
+        from paper_1607_02859_amd import build
+        build.build()
+    return gwchi.load()
+
+
+def test_exports_match_header(lib):
+    syms = header_symbols()
+    assert set(syms) == set(gwchi.EXPORTS)
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+def test_version(lib):
+    assert b"gfx950" in lib.gwchi_version()
+
+
+@pytest.fixture(scope="module")
+def item():
+    return synth.make_item(7, (6, 5, 4), 3, 9, True, 4, x_min=1.0)
+
+
+def clone(it, **kw):
+    d = dict(it.__dict__)
+    d.update(kw)
+    return synth.Item(**d)
+
+
+def test_valid_item_passes(lib, item):
+    assert gwchi.validate([item]) == 0
+
+
+@pytest.mark.parametrize("mut", [
+    lambda it: clone(it, mu=float(it.eps_unocc.min()) + 0.1),          # mu above the gap
+    lambda it: clone(it, mu=float(it.eps_occ.max())),                   # mu on an edge
+    lambda it: clone(it, tau=np.concatenate([it.tau[:-1], [0.0]])),     # tau <= 0
+    lambda it: clone(it, tau=np.concatenate([it.tau[:-1], [np.nan]])),  # non-finite tau
+    lambda it: clone(it, ct=it.ct * np.inf),                            # non-finite ct
+    lambda it: clone(it, g_index=np.array([0, 1, 1], np.int32)),        # duplicate G
+    lambda it: clone(it, g_index=np.array([0, 120], np.int32)),         # G out of range
+    lambda it: clone(it, g_index=np.array([-1], np.int32)),
+    lambda it: clone(it, eps_occ=np.array([np.nan, -1.0, -2.0])),
+])
+def test_validate_rejects(lib, item, mut):
+    assert gwchi.validate([mut(item)]) == 1
+
+
+def test_validate_nonfinite_orbital(lib, item):
+    bad = clone(item, phi_occ=item.phi_occ.copy())
+    bad.phi_occ[1, 3] = np.nan
+    assert gwchi.validate([bad], check_orbitals=True) == 1
+    assert gwchi.validate([bad], check_orbitals=False) == 0
+
+
+def test_validate_unsupported_grid(lib):
+    it = synth.make_item(8, (11, 4, 4), 2, 5, True, 3, x_min=1.0)   # 11 is not 7-smooth
+    assert gwchi.validate([it]) == 4
+    it = synth.make_item(8, (33, 1, 1), 2, 5, True, 3, x_min=1.0)   # > 32
+    assert gwchi.validate([it]) == 4
+
+
+def test_validate_empty_batch(lib):
+    arr = (gwchi.GwchiItem * 1)()
+    assert lib.gwchi_validate(arr, 0, 1) == 1
+    assert b"n_items" in lib.gwchi_last_error(None)
+
+
+def test_validate_null_pointer(lib, item):
+    keep = gwchi._Keep()
+    it = gwchi.make_item(keep, item, chi_out=np.zeros(1, complex))
+    it.g_index = 0
+    arr = (gwchi.GwchiItem * 1)(it)
+    assert lib.gwchi_validate(arr, 1, 1) == 1
+    assert b"NULL" in lib.gwchi_last_error(None)
+
+
+def test_struct_layout_matches_header(lib, tmp_path):
+    """Every field offset of the ctypes mirrors equals the C compiler's."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gwchi.h"', 'int main(void){']
+    mirrors = [("gwchi_item", gwchi.GwchiItem), ("gwchi_report", gwchi.GwchiReport),
+               ("gwchi_options", gwchi.GwchiOptions)]
+    for cname, py in mirrors:
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = []
+    for _, py in mirrors:
+        want.append(C.sizeof(py))
+        want += [getattr(py, f).offset for f, _ in py._fields_]
+    assert got == want

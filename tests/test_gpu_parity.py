@@ -1,0 +1,178 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle.
+
+Tolerances are max-over-omega relative Frobenius errors: 1e-10 (FP64),
+1e-5 (FP32), 1e-4 (split-BF16).  Cases span several GEMM tiles, ragged
+grid and band counts, non-cubic grids, real and complex orbitals.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import chi as oc
+from paper_1607_02859_amd import gwchi, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-4}
+PRECS = ["fp64", "fp32", "bf16x3"]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = gwchi.Context(0)
+    yield c
+    c.close()
+
+
+CASES = {
+    "real6": lambda: synth.make_item(101, (6, 6, 6), 4, 20, False, 5, x_min=1.0),
+    "cplx_noncubic": lambda: synth.make_item(102, (4, 6, 5), 3, 9, True, 4, x_min=1.0),
+    "cplx8": lambda: synth.make_item(103, (8, 8, 8), 8, 40, True, 6, x_min=1.0),
+    "ragged": lambda: synth.make_item(104, (10, 12, 9), 20, 100, True, 4, x_min=1.0),
+    "ragged_real": lambda: synth.make_item(105, (9, 10, 14), 13, 77, False, 3, x_min=1.0),
+    "cfg1": lambda: synth.make_config(1)[0],
+}
+
+_ORACLE = {}
+
+
+def case(name):
+    if name not in _ORACLE:
+        it = CASES[name]()
+        _ORACLE[name] = (it, oc.chi_omega(it))
+    return _ORACLE[name]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", list(CASES))
+def test_parity(ctx, name, prec):
+    it, ref = case(name)
+    say(f"[parity] case={name} prec={prec} n={it.n} K={it.n_occ}+{it.n_unocc}")
+    ctx.set_options(use_graph=1, hermitian=0, skip_zero_bands=0, slab_width=0, tile_id=0)
+    out, rep = ctx.build([it], prec, report=True)
+    err = oc.rel_frobenius(out[0], ref)
+    say(f"   err={err:.3e} kappa_F={rep['kappa_F_max']:.2f} ms={rep['ms_total']:.3f}")
+    assert np.all(np.isfinite(out[0]))
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_every_tile_config(ctx, prec):
+    it, ref = case("ragged")
+    n = len([0 for _ in range(8)])
+    for t in range(1, 4):
+        ctx.set_options(tile_id=t, use_graph=0)
+        out = ctx.build([it], prec)
+        err = oc.rel_frobenius(out[0], ref)
+        say(f"[tile] prec={prec} tile={t} err={err:.3e}")
+        assert err <= TOL[prec]
+    ctx.set_options(tile_id=0, use_graph=1)
+    for t in range(1, 4):
+        ctx.set_options(tile_id=t, use_graph=0)
+        it2, ref2 = case("ragged_real")
+        out = ctx.build([it2], prec)
+        assert oc.rel_frobenius(out[0], ref2) <= TOL[prec]
+    ctx.set_options(tile_id=0, use_graph=1)
+    del n
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_hermitian_mode(ctx, prec):
+    for name in ("ragged", "ragged_real", "cfg1"):
+        it, ref = case(name)
+        ctx.set_options(hermitian=1)
+        out = ctx.build([it], prec)
+        ctx.set_options(hermitian=0)
+        err = oc.rel_frobenius(out[0], ref)
+        say(f"[hermitian] case={name} prec={prec} err={err:.3e}")
+        assert err <= TOL[prec]
+
+
+def test_slab_width_bitwise(ctx):
+    it, _ = case("ragged")        # N_r = 1080: five 256-column slabs, ragged last
+    ctx.set_options(slab_width=0)
+    a = ctx.build([it], "fp32")[0]
+    ctx.set_options(slab_width=256)
+    b = ctx.build([it], "fp32")[0]
+    ctx.set_options(slab_width=0)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_skip_zero_bands_bitwise(ctx, prec):
+    # large tau makes far bands underflow to exact zeros in FP32
+    it = synth.make_item(106, (8, 8, 6), 6, 60, True, 5, x_min=0.5)
+    it.tau = it.tau * 4.0
+    ctx.set_options(skip_zero_bands=0)
+    a = ctx.build([it], prec)[0]
+    ctx.set_options(skip_zero_bands=1)
+    b = ctx.build([it], prec)[0]
+    ctx.set_options(skip_zero_bands=0)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_batch_equals_single(ctx, prec):
+    items = [case("cplx8")[0], case("ragged")[0], case("cplx_noncubic")[0]]
+    single = [ctx.build([it], prec)[0] for it in items]
+    batch = ctx.build(items, prec)
+    for s, b in zip(single, batch):
+        assert np.array_equal(s, b)
+
+
+def test_graph_replay_identical(ctx):
+    it, ref = case("cplx8")
+    ctx.set_options(use_graph=1)
+    outs = [ctx.build([it], "fp32", report=True) for _ in range(3)]
+    assert outs[1][1]["graph_replayed"] == 1
+    assert np.array_equal(outs[0][0][0], outs[1][0][0])
+    assert np.array_equal(outs[0][0][0], outs[2][0][0])
+    ctx.set_options(use_graph=0)
+    eager = ctx.build([it], "fp32")[0]
+    ctx.set_options(use_graph=1)
+    assert np.array_equal(eager, outs[0][0][0])
+
+
+def test_device_entry_matches_host(ctx):
+    import torch
+    it, _ = case("ragged")
+    host = ctx.build([it], "fp32")[0]
+    dev = torch.device("cuda:0")
+    po = torch.from_numpy(it.phi_occ).to(dev)
+    pu = torch.from_numpy(it.phi_unocc).to(dev)
+    out = torch.empty((it.n_omega, it.n_g, it.n_g), dtype=torch.complex128, device=dev)
+    ctx.build_device([it], [(po, pu)], [out], "fp32")
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), host)
+
+
+def test_timing_report(ctx):
+    it, _ = case("cfg1")
+    ctx.set_options(timing=1)
+    _, rep = ctx.build([it], "fp32", report=True)
+    ctx.set_options(timing=0)
+    say(f"[timing] {rep}")
+    assert rep["ms_gemm"] > 0 and rep["n_gemm_launches"] >= 1
+    assert rep["alg_flops"] == synth.algorithmic_flops(it)
+
+
+def test_config2_full_size_sampled_rows(ctx):
+    """Config 2 at full size in the benchmark's launch configuration (FP32),
+    checked on sampled rows of chi(i omega) from the pair-sum oracle."""
+    it = synth.make_config(2)[0]
+    say(f"[cfg2] n={it.n} K={it.n_occ}+{it.n_unocc} n_g={it.n_g}")
+    ctx.set_options(use_graph=1, hermitian=0, skip_zero_bands=0, slab_width=0, tile_id=0)
+    out = ctx.build([it], "fp32")[0]
+    rows = [0, 1, 57, 1500, it.n_g - 1]
+    ref = oc.chi_rows(it, rows)
+    err = oc.rel_frobenius(out[:, rows, :], ref)
+    say(f"   sampled-row err={err:.3e}")
+    assert err <= TOL["fp32"]
+    herm = np.abs(out - np.conj(np.transpose(out, (0, 2, 1)))).max() / np.abs(out).max()
+    assert herm < 1e-5
