@@ -42,7 +42,8 @@ struct MM<P_FP64, C> {
   static constexpr int BPB = C ? 16 : 8;  // bytes per band element
   static constexpr int NACC = 4;
   typedef d4v acc_t;
-  static __device__ __forceinline__ int acc_row(int l, int v) { return 4 * (l >> 4) + v; }
+  // the FP64 16x16 result interleaves rows: value v of lane l is row l/16 + 4v
+  static __device__ __forceinline__ int acc_row(int l, int v) { return (l >> 4) + 4 * v; }
   static __device__ __forceinline__ int acc_col(int l) { return l & 15; }
   static __device__ __forceinline__ int frag_row(int l) { return l & 15; }
 };

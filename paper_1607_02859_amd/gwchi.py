@@ -92,6 +92,13 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise OSError(f"{path} not built; run paper_1607_02859_amd/build.py")
+    # PyTorch-ROCm ships its own HIP runtime with the same soname.  Loading
+    # torch first makes this library bind to that runtime, so that torch
+    # tensors, streams and this library share one HIP runtime in the process.
+    try:
+        import torch  # noqa: F401
+    except Exception:
+        pass
     lib = C.CDLL(path)
     P = C.POINTER
     lib.gwchi_create.argtypes = [P(C.c_void_p), C.c_int32, C.c_char_p]
