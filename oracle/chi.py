@@ -65,7 +65,8 @@ __all__ = [
     "rel_frobenius",
 ]
 
-_WORKERS = max(1, os.cpu_count() or 1)
+# FFT threads: the process's thread budget when one is set, else every core
+_WORKERS = max(1, int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1)
 
 
 def _phi(item, which):

@@ -123,7 +123,7 @@ struct gwchi_ctx {
   std::string graph_key;
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
-  size_t graph_events = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> graph_evs;
 };
 
 namespace {
@@ -938,16 +938,19 @@ gwchi_status run_build(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int
     HIPCHK(hipEventRecord(t0, ctx->stream));
   }
   bool replayed = false;
-  const bool use_graph = ctx->opt.use_graph && !timing;
+  // HIP events recorded inside a captured graph cannot be timed, so the
+  // per-launch timing mode runs the same launch list eagerly.
+  const bool use_graph = ctx->opt.use_graph != 0 && !timing;
   if (use_graph) {
     std::ostringstream k;
-    k << B.key << "|tables=" << ctx->b_tables.p << ",psi=" << ctx->b_psi.p << ",slab="
-      << ctx->b_slab.p << ",xr=" << ctx->b_xr.p << ",x=" << ctx->b_x.p << ",sc="
+    k << B.key << "|timing=" << timing << "|tables=" << ctx->b_tables.p << ",psi=" << ctx->b_psi.p
+      << ",slab=" << ctx->b_slab.p << ",xr=" << ctx->b_xr.p << ",x=" << ctx->b_x.p << ",sc="
       << ctx->b_scratch.p << ",norm=" << ctx->b_norm.p;
     for (auto &I : P.items) k << "," << (const void *)I.phi_o << (const void *)I.phi_u << (void *)I.out;
     const std::string key = k.str();
     if (ctx->graph_exec && key == ctx->graph_key) {
       HIPCHK(hipGraphLaunch(ctx->graph_exec, ctx->stream));
+      evs = ctx->graph_evs;
       replayed = true;
     } else {
       if (ctx->graph_exec) {
@@ -958,6 +961,7 @@ gwchi_status run_build(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int
         (void)hipGraphDestroy(ctx->graph);
         ctx->graph = nullptr;
       }
+      ctx->graph_key.clear();
       HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
       st = enqueue(ctx, P, B, false, nullptr);
       hipGraph_t g = nullptr;
@@ -980,6 +984,7 @@ gwchi_status run_build(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int
       ctx->graph = g;
       ctx->graph_exec = ex;
       ctx->graph_key = key;
+      ctx->graph_evs = evs;
       HIPCHK(hipGraphLaunch(ctx->graph_exec, ctx->stream));
     }
   } else {
