@@ -105,7 +105,8 @@ typedef struct {
   int32_t tau_batch;        /* tau points processed per pass                           */
   int32_t tile_id;          /* GEMM tile configuration used                            */
   int32_t graph_replayed;   /* 1 if the build ran as a replay of a cached hipGraph     */
-  double kappa_F_max;       /* max_k sum_j |c'_kj| ||chi(tau_j)||_F / ||chi(i w_k)||_F */
+  double kappa_F_max;       /* max_k sum_j |c'_kj| ||chi(tau_j)||_F / ||chi(i w_k)||_F,
+                               or -1 when not computed                                 */
 } gwchi_report;
 
 /* Context options.  gwchi_create sets the defaults noted below;
@@ -124,7 +125,10 @@ typedef struct {
   int32_t skip_zero_bands;   /* 1 = drop bands whose scaled orbitals are exactly zero in
                                 the working precision; never on FP64 (default 0)       */
   int32_t hermitian;         /* 1 = compute only the lower block triangle of chi(r,r')
-                                and complete by Hermiticity (default 0)                 */
+                                and complete by Hermiticity (default 1)                 */
+  int32_t kappa;             /* 1 = when a report is requested, also compute the
+                                norms behind kappa_F_max (default 1); 0 = report
+                                kappa_F_max = -1 and skip that pass                     */
   int64_t max_device_bytes;  /* cap on the context's scratch; 0 = 60% of free memory   */
 } gwchi_options;
 

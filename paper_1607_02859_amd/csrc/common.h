@@ -25,11 +25,11 @@ struct Geo {
   int32_t n0, n1, n2;
   int32_t n_r;
   int32_t n_g;
-  int32_t n_disk;          // distinct (k1, k2) columns touched by the sphere
-  int32_t planes;          // planes per LDS group in the FFT kernel
-  int32_t disk_in_lds;     // 1: pencil buffer in LDS, 0: in global scratch
+  int32_t n_disk;          // distinct (k1, k2) pencils touched by the sphere
+  int32_t cols;            // columns per plane-FFT block
+  int32_t planes;          // i0-planes per plane-FFT block
   const int32_t *disk_i12; // [n_disk] k1*n2 + k2
-  const int32_t *slot_dk;  // [n_g] d*n0 + k0 for output slot s
+  const int32_t *slot_of;  // [n_disk][n0] output slot of (pencil d, k0), or -1
 };
 
 // ---------------------------------------------------------------------------
@@ -67,7 +67,8 @@ struct GemmJob {
   int32_t k_o, k_u;         // bands to contract, multiple of the K chunk
   int32_t n_r;
   int32_t s0, w;            // slab column range [s0, s0 + w)
-  void *slab;               // [w][n_r] output (column-major in r)
+  int32_t cg_shift;         // slab columns are grouped by 2^cg_shift
+  void *slab;               // [w / 2^cg_shift][n_r][2^cg_shift] output
 };
 
 struct GemmLaunch {
@@ -79,28 +80,32 @@ struct GemmLaunch {
 
 // ---------------------------------------------------------------------------
 // Sphere FFT over the first index (columns of a slab) or the second
-// (rows of chi(G, r')).
+// (rows of chi(G, r')), in two launches:
+//   planes : per block of `cols` columns and `planes` i0-planes, 2D FFT over
+//            (i1, i2) and gather of the sphere's pencils into tmp;
+//   pencils: per (pencil, 256 columns), FFT over i0 and scatter of the sphere
+//            points to the output.
 // ---------------------------------------------------------------------------
 struct FftJob {
-  const void *in;           // column c of this job starts at in + c * in_col_stride
-  int64_t in_col_stride;    // elements
-  void *out;                // out[slot * out_slot_stride + (col0 + c) * out_col_stride]
-  int64_t out_slot_stride;
-  int64_t out_col_stride;
-  int32_t col0;
+  const void *in;           // element (r, c) at in[r * s_r + c * s_col], or, when
+  int64_t s_r, s_col;       // s_col == 0, column-grouped: in[((c / C) * n_r + r) * C + c % C]
+  void *tmp;                // pencil buffer [(i0 * n_disk + d) * n_cols + c]
+  void *out;                // out[slot * o_slot + (col0 + c) * o_col]
+  int64_t o_slot, o_col;
+  int32_t col0;             // absolute index of column 0 (slab start for the first index)
   int32_t n_cols;
   int32_t geo;
-  int32_t work0;            // first work index of this job in the launch
+  int32_t unit0_planes;     // first plane-FFT block of this job in the launch
+  int32_t unit0_pencils;    // first pencil block of this job in the launch
 };
 
 struct FftLaunch {
   const FftJob *jobs;
   int32_t n_jobs;
-  int32_t n_work;           // total columns
   const Geo *geos;
-  void *scratch;            // global pencil buffers, one slot per block
-  int64_t scratch_slot;     // elements per slot
-  int32_t in_real;          // input columns are real
+  int32_t n_units_planes;
+  int32_t n_units_pencils;
+  int32_t in_real;          // input is real
   int32_t lower_only;       // column c holds only rows r >= col0 + c; others read as zero
 };
 
@@ -108,18 +113,20 @@ struct FftLaunch {
 // Cosine transform (FP64 accumulation) and norms.
 // ---------------------------------------------------------------------------
 struct CtItem {
-  const void *x;            // [n_tau][n_g][n_g] chi(G, G', i tau_j), working precision
+  const void *x;            // [n_tau][n_g][n_g] transposed: x_j[g'][g] = chi(G, G', i tau_j)
   double *out;              // [n_omega][n_g][n_g] complex FP64
   const double *coef;       // [n_omega][n_tau] c'_kj including the edge factor
   int32_t n_g, n_tau, n_omega;
   int32_t hermitian;        // 1: x holds X with chi = X + X^H
   int64_t elem0;            // first flat output element of this item in the launch
+  int32_t tile0;            // first 32x16 output tile of this item in the launch
 };
 
 struct CtLaunch {
   const CtItem *items;
   int32_t n_items;
   int64_t n_elem;           // sum over items of n_g^2
+  int32_t n_tiles;          // sum over items of the 32x16 output tiles
 };
 
 // Host-side launch wrappers (defined in the .hip files).
@@ -131,8 +138,34 @@ int gemm_tile_bm(int prec, int cplx, int tile);
 int gemm_tile_bn(int prec, int cplx, int tile);
 int gemm_tile_kc(int prec, int cplx, int tile);
 const char *gemm_tile_name(int prec, int cplx, int tile);
-hipError_t launch_fft(const FftLaunch &L, int dbl, int sign, int grid, int lds_bytes,
+hipError_t launch_fft(const FftLaunch &L, int dbl, int sign, int lds_bytes, int cubic_n,
                       hipStream_t s);
+
+// Plane-FFT block shape, shared by the planner and the kernels: runs of
+// 128 bytes of adjacent columns, about 256 line transforms per step, at most
+// 80 KB of LDS (two blocks per CU).
+constexpr int fft_lds_bytes(int n1, int n2, int cols, int planes, int elem) {
+  return planes * n1 * n2 * (cols + 1) * elem;
+}
+// three blocks per CU for FP32, two for FP64
+constexpr int fft_lds_budget(int elem) { return elem <= 8 ? 52 * 1024 : 80 * 1024; }
+constexpr int fft_cols(int n1, int n2, int elem) {
+  int cols = 128 / elem;
+  while (cols > 1 && fft_lds_bytes(n1, n2, cols, 1, elem) > fft_lds_budget(elem)) cols /= 2;
+  return cols;
+}
+constexpr int fft_planes(int n0, int n1, int n2, int elem) {
+  const int cols = fft_cols(n1, n2, elem);
+  int planes = 256 / (n1 * cols > 0 ? n1 * cols : 1);
+  if (planes < 1) planes = 1;
+  if (planes > n0) planes = n0;
+  while (planes > 1 && fft_lds_bytes(n1, n2, cols, planes, elem) > fft_lds_budget(elem)) --planes;
+  return planes;
+}
+// cubic grids with a specialised FFT kernel
+constexpr bool fft_specialised(int n) {
+  return n == 12 || n == 16 || n == 18 || n == 20 || n == 24 || n == 28 || n == 32;
+}
 int fft_supported(int n);
 hipError_t launch_ct(const CtLaunch &L, int dbl, int max_omega, hipStream_t s);
 hipError_t launch_norms_impl(const CtLaunch &L, int dbl, double *norm_tau, double *norm_omega,

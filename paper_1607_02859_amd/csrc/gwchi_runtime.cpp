@@ -19,6 +19,7 @@
 #include <numeric>
 #include <sstream>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/gwchi.h"
@@ -94,8 +95,8 @@ struct Launch {
   FftLaunch fft;
   CtLaunch ct;
   int fft_sign = -1;
-  int fft_grid = 0;
   int fft_lds = 0;
+  int fft_cubic = 0;
   int gemm_grid = 0;
   int max_omega = 0;
   int max_mats = 0;
@@ -115,7 +116,7 @@ struct gwchi_ctx {
   std::string err;
   std::string tune_path;
   std::map<std::string, int> tune;   // key -> tile index
-  DevBuf b_phi, b_out, b_psi, b_slab, b_xr, b_x, b_scratch, b_tables, b_norm;
+  DevBuf b_phi, b_out, b_psi, b_slab, b_xr, b_x, b_tmp, b_tables, b_norm;
   HostPinned h_tables, h_norm;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::vector<hipEvent_t> ev_pool;
@@ -242,8 +243,8 @@ struct ItemPlan {
   double homo, lumo;
   std::vector<int32_t> perm_o, perm_u;
   std::vector<double> eps_o, eps_u;
-  std::vector<int32_t> disk_i12, slot_dk;
-  int n_disk = 0, planes = 1, disk_lds = 1;
+  std::vector<int32_t> disk_i12, slot_of;
+  int n_disk = 0, planes = 1, cols = 16, fft_lds = 0;
   std::vector<double> coef;    // [n_omega][n_tau]
   std::vector<double> tau;
   const double *phi_o = nullptr, *phi_u = nullptr;
@@ -266,9 +267,8 @@ struct Plan {
   std::vector<JobPlan> jobs;
   // per-job slot sizes (bytes), uniform across slots (maxima)
   int64_t psi_slot = 0, slab_slot = 0, xr_slot = 0;
-  int64_t x_bytes = 0, scratch_bytes = 0;
-  int64_t scratch_slot_elems = 0;
-  int fft_grid = 0, fft_lds = 0;
+  int64_t x_bytes = 0, tmp_slot = 0;
+  int fft_lds = 0;
   double alg_flops = 0, mfma_flops = 0;
   int cplx_any = 0, real_any = 0;
 };
@@ -358,36 +358,25 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
       for (int j = 0; j < I.n_tau; ++j)
         I.coef[(size_t)k * I.n_tau + j] =
             it.ct[(size_t)k * I.n_tau + j] * std::exp(-(I.lumo - I.homo) * it.tau[j]);
-    // sphere tables
+    // sphere tables: pencils (k1, k2) in first-seen order, slot of (pencil, k0)
     std::map<int, int> dmap;
-    I.slot_dk.resize(I.n_g);
-    for (int s = 0; s < I.n_g; ++s) {
-      const int f = it.g_index[s];
+    std::vector<std::pair<int, int>> dk(I.n_g);
+    for (int g = 0; g < I.n_g; ++g) {
+      const int f = it.g_index[g];
       const int k0 = f / (I.n1 * I.n2);
       const int i12 = f - k0 * I.n1 * I.n2;
       auto ins = dmap.emplace(i12, (int)dmap.size());
-      I.slot_dk[s] = ins.first->second * I.n0 + k0;
+      dk[g] = {ins.first->second, k0};
     }
     I.n_disk = (int)dmap.size();
     I.disk_i12.resize(I.n_disk);
     for (auto &kv : dmap) I.disk_i12[kv.second] = kv.first;
-    // FFT LDS plan
-    const int plane = I.n1 * I.n2;
-    int pmax = std::max(1, 256 / std::max(I.n1, I.n2));
-    pmax = std::min(pmax, I.n0);
-    const int64_t lds = (int64_t)ctx->lds_max - 1024;
-    const int64_t disk_b = (int64_t)I.n_disk * I.n0 * ec;
-    int planes = pmax;
-    while (planes > 1 && (int64_t)planes * plane * ec + disk_b > lds) planes = (planes + 1) / 2;
-    if ((int64_t)planes * plane * ec + disk_b <= lds) {
-      I.planes = planes;
-      I.disk_lds = 1;
-    } else {
-      planes = pmax;
-      while (planes > 1 && (int64_t)planes * plane * ec > lds) planes = (planes + 1) / 2;
-      I.planes = planes;
-      I.disk_lds = 0;
-    }
+    I.slot_of.assign((size_t)I.n_disk * I.n0, -1);
+    for (int g = 0; g < I.n_g; ++g) I.slot_of[(size_t)dk[g].first * I.n0 + dk[g].second] = g;
+    // plane-FFT block shape (same formula as the kernels)
+    I.cols = fft_cols(I.n1, I.n2, ec);
+    I.planes = fft_planes(I.n0, I.n1, I.n2, ec);
+    I.fft_lds = fft_lds_bytes(I.n1, I.n2, I.cols, I.planes, ec);
     I.phi_o = it.phi_occ;
     I.phi_u = it.phi_unocc;
     I.out = it.chi_out;
@@ -417,45 +406,37 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
   }
   // sizes
   int64_t x_total = 0;
-  int64_t psi_max = 0, xr_max = 0;
-  int max_disk_elems = 0;
-  bool any_global_disk = false;
+  int64_t psi_max = 0, xr_max = 0, tmp_max = 0;
+  const int W0 = ctx->opt.slab_width > 0 ? (int)round_up(ctx->opt.slab_width, 256) : 2048;
   for (auto &I : P.items) {
     I.x_off = x_total;
     x_total += round_up((int64_t)I.n_tau * I.n_g * I.n_g * ec, 256);
     psi_max = std::max<int64_t>(psi_max, I.n_r_pad * (I.k_o_pad + I.k_u_pad) * bpb);
     xr_max = std::max<int64_t>(xr_max, (int64_t)I.n_g * I.n_r * ec);
-    if (!I.disk_lds) {
-      any_global_disk = true;
-      max_disk_elems = std::max(max_disk_elems, I.n_disk * I.n0);
-    }
+    const int64_t ncols = std::max<int64_t>(std::min<int64_t>(W0, I.n_r), I.n_g);
+    tmp_max = std::max<int64_t>(tmp_max, (int64_t)I.n0 * I.n_disk * ncols * ec);
   }
   P.x_bytes = x_total;
   P.psi_slot = round_up(psi_max, 256);
   P.xr_slot = round_up(xr_max, 256);
-  P.fft_grid = ctx->num_cu * 2;
-  P.scratch_slot_elems = any_global_disk ? max_disk_elems : 0;
-  P.scratch_bytes = (int64_t)P.fft_grid * P.scratch_slot_elems * ec + 256;
+  P.tmp_slot = round_up(tmp_max, 256);
   int lds_need = 0;
-  for (auto &I : P.items) {
-    int b = I.planes * I.n1 * I.n2 * ec + (I.disk_lds ? I.n_disk * I.n0 * ec : 0);
-    lds_need = std::max(lds_need, b);
-  }
+  for (auto &I : P.items) lds_need = std::max(lds_need, I.fft_lds);
   P.fft_lds = lds_need;
   // budget
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)64 << 30;
   // memory the context already holds counts as available
-  const size_t held = ctx->b_psi.n + ctx->b_slab.n + ctx->b_xr.n + ctx->b_x.n + ctx->b_scratch.n;
+  const size_t held = ctx->b_psi.n + ctx->b_slab.n + ctx->b_xr.n + ctx->b_x.n + ctx->b_tmp.n;
   int64_t budget = ctx->opt.max_device_bytes > 0 ? ctx->opt.max_device_bytes
                                                  : (int64_t)((free_b + held) * 0.6);
-  const int64_t fixed = P.x_bytes + P.scratch_bytes + ((int64_t)64 << 20);
-  int W = ctx->opt.slab_width > 0 ? (int)round_up(ctx->opt.slab_width, 256) : 2048;
+  const int64_t fixed = P.x_bytes + ((int64_t)64 << 20);
+  int W = W0;
   const int n_jobs = (int)P.jobs.size();
   for (;;) {
     const int64_t slab_max = round_up((int64_t)std::min<int64_t>(W, round_up(max_n_r, 256)) *
-                                          max_n_r * es, 256);
-    const int64_t per_job = P.psi_slot + slab_max + P.xr_slot;
+                                          max_n_r * es, 256);   // W is a multiple of any group
+    const int64_t per_job = P.psi_slot + slab_max + P.xr_slot + P.tmp_slot;
     int64_t fit = per_job > 0 ? (budget - fixed) / per_job : 0;
     int want = ctx->opt.tau_batch > 0 ? std::min(ctx->opt.tau_batch, n_jobs) : n_jobs;
     if (fit >= 1) {
@@ -498,6 +479,44 @@ struct Built {
   int n_norm_tau = 0, n_norm_omega = 0;
 };
 
+// Emit FFT launches for a set of jobs, one launch per distinct grid so that
+// cubic grids run the kernels specialised for their size.
+void emit_fft(Built &B, const Plan &P, std::vector<FftJob> &jobs, int phase, int sign,
+              int in_real, int lower_only, size_t off_geos) {
+  std::map<std::tuple<int, int, int>, std::vector<FftJob>> groups;
+  for (auto &f : jobs) {
+    const ItemPlan &I = P.items[f.geo];
+    groups[std::make_tuple(I.n0, I.n1, I.n2)].push_back(f);
+  }
+  for (auto &kv : groups) {
+    std::vector<FftJob> &fj = kv.second;
+    int up = 0, un = 0, lds = 0;
+    for (auto &f : fj) {
+      const ItemPlan &I = P.items[f.geo];
+      f.unit0_planes = up;
+      f.unit0_pencils = un;
+      up += ((f.n_cols + I.cols - 1) / I.cols) * ((I.n0 + I.planes - 1) / I.planes);
+      un += I.n_disk * ((f.n_cols + 255) / 256);
+      lds = std::max(lds, I.fft_lds);
+    }
+    const int n0 = std::get<0>(kv.first), n1 = std::get<1>(kv.first), n2 = std::get<2>(kv.first);
+    Launch F{};
+    F.phase = phase;
+    F.kind = 2;
+    F.fft.jobs = reinterpret_cast<const FftJob *>(B.blob.addv(fj));
+    F.fft.n_jobs = (int)fj.size();
+    F.fft.geos = reinterpret_cast<const Geo *>(off_geos);
+    F.fft.n_units_planes = up;
+    F.fft.n_units_pencils = un;
+    F.fft.in_real = in_real;
+    F.fft.lower_only = lower_only;
+    F.fft_sign = sign;
+    F.fft_lds = lds;
+    F.fft_cubic = (n0 == n1 && n1 == n2) ? n0 : 0;
+    B.launches.push_back(F);
+  }
+}
+
 // Build every launch descriptor.  Pointers into the blob are stored as offsets
 // and patched by patch_blob once the device address of the blob is known.
 void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
@@ -512,6 +531,7 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
   char *slab_base = reinterpret_cast<char *>(ctx->b_slab.p);
   char *xr_base = reinterpret_cast<char *>(ctx->b_xr.p);
   char *x_base = reinterpret_cast<char *>(ctx->b_x.p);
+  char *tmp_base = reinterpret_cast<char *>(ctx->b_tmp.p);
   std::ostringstream key;
   key << "p" << P.prec << "t" << P.tile << "w" << P.slab_w << "b" << P.jobs_per_pass << "h"
       << ctx->opt.hermitian << "n" << want_norms << "|";
@@ -521,7 +541,7 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
   for (int t = 0; t < n_items; ++t) {
     const ItemPlan &I = P.items[t];
     off_i12[t] = B.blob.addv(I.disk_i12);
-    off_sdk[t] = B.blob.addv(I.slot_dk);
+    off_sdk[t] = B.blob.addv(I.slot_of);
     off_perm_o[t] = B.blob.addv(I.perm_o);
     off_perm_u[t] = B.blob.addv(I.perm_u);
     off_eps_o[t] = B.blob.addv(I.eps_o);
@@ -542,10 +562,10 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
     g.n_r = (int32_t)I.n_r;
     g.n_g = I.n_g;
     g.n_disk = I.n_disk;
+    g.cols = I.cols;
     g.planes = I.planes;
-    g.disk_in_lds = I.disk_lds;
     g.disk_i12 = reinterpret_cast<const int32_t *>(off_i12[t]);   // offset, patched
-    g.slot_dk = reinterpret_cast<const int32_t *>(off_sdk[t]);
+    g.slot_of = reinterpret_cast<const int32_t *>(off_sdk[t]);
     geos[t] = g;
   }
   const size_t off_geos = B.blob.addv(geos);
@@ -619,7 +639,6 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
       std::vector<GemmJob> gj;
       std::vector<int4> units;
       std::vector<FftJob> fj;
-      int work = 0;
       for (int q = jb; q < je; ++q) {
         const JobPlan &J = P.jobs[q];
         const ItemPlan &I = P.items[J.item];
@@ -637,6 +656,8 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
         g.n_r = (int32_t)I.n_r;
         g.s0 = (int32_t)s0;
         g.w = w;
+        g.cg_shift = 0;
+        while ((1 << (g.cg_shift + 1)) <= I.cols) ++g.cg_shift;
         g.slab = slab_base + (int64_t)(q - jb) * P.slab_slot;
         const int gi = (int)gj.size();
         gj.push_back(g);
@@ -655,15 +676,15 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
         }
         FftJob f{};
         f.in = g.slab;
-        f.in_col_stride = I.n_r;
+        f.s_r = 1;
+        f.s_col = 0;                       // column-grouped slab
+        f.tmp = tmp_base + (int64_t)(q - jb) * P.tmp_slot;
         f.out = xr_base + (int64_t)(q - jb) * P.xr_slot;
-        f.out_slot_stride = I.n_r;
-        f.out_col_stride = 1;
+        f.o_slot = I.n_r;
+        f.o_col = 1;
         f.col0 = (int32_t)s0;
         f.n_cols = w;
         f.geo = J.item;
-        f.work0 = work;
-        work += w;
         fj.push_back(f);
       }
       if (gj.empty()) continue;
@@ -676,62 +697,34 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
       G.gemm.hermitian = ctx->opt.hermitian;
       G.gemm_grid = (int)units.size();
       B.launches.push_back(G);
-      Launch F{};
-      F.phase = PH_FFT_R;
-      F.kind = 2;
-      F.fft.jobs = reinterpret_cast<const FftJob *>(B.blob.addv(fj));
-      F.fft.n_jobs = (int)fj.size();
-      F.fft.n_work = work;
-      F.fft.geos = reinterpret_cast<const Geo *>(off_geos);
-      F.fft.scratch = ctx->b_scratch.p;
-      F.fft.scratch_slot = P.scratch_slot_elems;
-      F.fft.in_real = cplx ? 0 : 1;
-      F.fft.lower_only = ctx->opt.hermitian;
-      F.fft_sign = -1;
-      F.fft_grid = std::min(work, P.fft_grid);
-      F.fft_lds = P.fft_lds;
-      B.launches.push_back(F);
+      emit_fft(B, P, fj, PH_FFT_R, -1, cplx ? 0 : 1, ctx->opt.hermitian, off_geos);
     }
-    // ---- fft over r'
+    // ---- fft over r': output stored transposed, x_j[g'][g]
     {
       std::vector<FftJob> fj;
-      int work = 0;
       for (int q = jb; q < je; ++q) {
         const JobPlan &J = P.jobs[q];
         const ItemPlan &I = P.items[J.item];
         FftJob f{};
         f.in = xr_base + (int64_t)(q - jb) * P.xr_slot;
-        f.in_col_stride = I.n_r;
+        f.s_r = 1;
+        f.s_col = I.n_r;
+        f.tmp = tmp_base + (int64_t)(q - jb) * P.tmp_slot;
         f.out = x_base + I.x_off + (int64_t)J.j * I.n_g * I.n_g * ec;
-        f.out_slot_stride = 1;
-        f.out_col_stride = I.n_g;
+        f.o_slot = I.n_g;
+        f.o_col = 1;
         f.col0 = 0;
         f.n_cols = I.n_g;
         f.geo = J.item;
-        f.work0 = work;
-        work += I.n_g;
         fj.push_back(f);
       }
-      Launch F{};
-      F.phase = PH_FFT_RP;
-      F.kind = 2;
-      F.fft.jobs = reinterpret_cast<const FftJob *>(B.blob.addv(fj));
-      F.fft.n_jobs = (int)fj.size();
-      F.fft.n_work = work;
-      F.fft.geos = reinterpret_cast<const Geo *>(off_geos);
-      F.fft.scratch = ctx->b_scratch.p;
-      F.fft.scratch_slot = P.scratch_slot_elems;
-      F.fft.in_real = 0;
-      F.fft.lower_only = 0;
-      F.fft_sign = +1;
-      F.fft_grid = std::min(work, P.fft_grid);
-      F.fft_lds = P.fft_lds;
-      B.launches.push_back(F);
+      emit_fft(B, P, fj, PH_FFT_RP, +1, 0, 0, off_geos);
     }
   }
   // ---- cosine transform
   std::vector<CtItem> cts(n_items);
   int64_t elems = 0;
+  int tiles = 0;
   int max_omega = 0, max_mats = 0;
   std::vector<int32_t> toff(n_items), woff(n_items);
   int nt = 0, nw = 0;
@@ -746,7 +739,9 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
     c.n_omega = I.n_omega;
     c.hermitian = ctx->opt.hermitian;
     c.elem0 = elems;
+    c.tile0 = tiles;
     elems += (int64_t)I.n_g * I.n_g;
+    tiles += ((I.n_g + 31) / 32) * ((I.n_g + 15) / 16);
     cts[t] = c;
     max_omega = std::max(max_omega, I.n_omega);
     max_mats = std::max(max_mats, I.n_tau + I.n_omega);
@@ -761,6 +756,7 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
   C.ct.items = reinterpret_cast<const CtItem *>(B.blob.addv(cts));
   C.ct.n_items = n_items;
   C.ct.n_elem = elems;
+  C.ct.n_tiles = tiles;
   C.max_omega = max_omega;
   B.launches.push_back(C);
   B.n_norm_tau = nt;
@@ -834,7 +830,7 @@ void patch_geos(Built &B, const char *base, size_t off_geos, int n_items) {
   Geo *g = reinterpret_cast<Geo *>(B.blob.h.data() + off_geos);
   for (int i = 0; i < n_items; ++i) {
     g[i].disk_i12 = dev(base, g[i].disk_i12);
-    g[i].slot_dk = dev(base, g[i].slot_dk);
+    g[i].slot_of = dev(base, g[i].slot_of);
   }
 }
 
@@ -871,7 +867,7 @@ gwchi_status enqueue(gwchi_ctx *ctx, const Plan &P, Built &B, bool timing,
         HIPCHK(launch_gemm(L.gemm, P.prec, cplx, P.tile, L.gemm_grid, s));
         break;
       case 2:
-        HIPCHK(launch_fft(L.fft, dbl, L.fft_sign, L.fft_grid, L.fft_lds, s));
+        HIPCHK(launch_fft(L.fft, dbl, L.fft_sign, L.fft_lds, L.fft_cubic, s));
         break;
       case 3:
         HIPCHK(launch_ct(L.ct, dbl, L.max_omega, s));
@@ -904,8 +900,8 @@ gwchi_status run_build(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int
   HIPCHK(ctx->b_slab.ensure((size_t)P.slab_slot * n_jobs_pass, &moved));
   HIPCHK(ctx->b_xr.ensure((size_t)P.xr_slot * n_jobs_pass, &moved));
   HIPCHK(ctx->b_x.ensure((size_t)P.x_bytes, &moved));
-  HIPCHK(ctx->b_scratch.ensure((size_t)P.scratch_bytes, &moved));
-  const bool want_norms = rep != nullptr;
+  HIPCHK(ctx->b_tmp.ensure((size_t)P.tmp_slot * n_jobs_pass, &moved));
+  const bool want_norms = rep != nullptr && ctx->opt.kappa != 0;
   int n_norm = 0;
   for (auto &I : P.items) n_norm += I.n_tau + I.n_omega;
   HIPCHK(ctx->b_norm.ensure((size_t)n_norm * 8 + 64, &moved));
@@ -945,7 +941,7 @@ gwchi_status run_build(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int
     std::ostringstream k;
     k << B.key << "|timing=" << timing << "|tables=" << ctx->b_tables.p << ",psi=" << ctx->b_psi.p
       << ",slab=" << ctx->b_slab.p << ",xr=" << ctx->b_xr.p << ",x=" << ctx->b_x.p << ",sc="
-      << ctx->b_scratch.p << ",norm=" << ctx->b_norm.p;
+      << ctx->b_tmp.p << ",norm=" << ctx->b_norm.p;
     for (auto &I : P.items) k << "," << (const void *)I.phi_o << (const void *)I.phi_u << (void *)I.out;
     const std::string key = k.str();
     if (ctx->graph_exec && key == ctx->graph_key) {
@@ -1019,6 +1015,9 @@ gwchi_status run_build(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int
     rep->tau_batch = P.jobs_per_pass;
     rep->tile_id = P.tile + 1;
     rep->graph_replayed = replayed ? 1 : 0;
+    rep->kappa_F_max = -1.0;
+  }
+  if (rep && want_norms) {
     // kappa_F from the norms
     std::vector<double> nrm(n_norm);
     HIPCHK(hipMemcpy(nrm.data(), ctx->b_norm.p, (size_t)n_norm * 8, hipMemcpyDeviceToHost));
@@ -1178,6 +1177,8 @@ gwchi_status gwchi_create(gwchi_ctx **out, int32_t device_id, const char *tune_c
       return GWCHI_EDEVICE;
     }
     ctx->opt.use_graph = 1;
+    ctx->opt.hermitian = 1;
+    ctx->opt.kappa = 1;
     if (tune_cache_path) ctx->tune_path = tune_cache_path;
     load_tune(ctx.get());
     *out = ctx.release();
@@ -1198,7 +1199,7 @@ gwchi_status gwchi_destroy(gwchi_ctx *ctx) {
   if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
   if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
   for (DevBuf *b : {&ctx->b_phi, &ctx->b_out, &ctx->b_psi, &ctx->b_slab, &ctx->b_xr, &ctx->b_x,
-                    &ctx->b_scratch, &ctx->b_tables, &ctx->b_norm})
+                    &ctx->b_tmp, &ctx->b_tables, &ctx->b_norm})
     b->release();
   ctx->h_tables.release();
   ctx->h_norm.release();

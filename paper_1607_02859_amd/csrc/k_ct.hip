@@ -5,9 +5,8 @@
 // with c'_kj = ct[k][j] * exp(-(eps_LUMO - eps_HOMO) tau_j): the caller's
 // coefficient times the band-edge factor the staging step left out of the
 // weights.  Inputs are read in the working precision and every product and
-// sum is FP64.  One thread owns one (G, G') element for a chunk of CH
-// frequencies and walks j in increasing order.  With Hermitian completion
-// the stored matrix is X and chi = X + X^H.
+// sum is FP64; each output element sums j in increasing order.  With
+// Hermitian completion the stored matrix is X and chi = X + X^H.
 #include "common.h"
 
 namespace gw {
@@ -23,49 +22,88 @@ __device__ __forceinline__ double2 ld_x(const void *base, int64_t e) {
   }
 }
 
-__device__ __forceinline__ int find_item(const CtItem *items, int n, int64_t e) {
+__device__ __forceinline__ int find_tile(const CtItem *items, int n, int t) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (items[mid].elem0 <= e) lo = mid;
+    if (items[mid].tile0 <= t) lo = mid;
     else hi = mid - 1;
   }
   return lo;
 }
 
+// One block per 32 (G) x 16 (G') output tile; thread (tx, ty) owns the two
+// elements (a0 + ty + 16 i, b0 + tx), i = 0, 1, for CH frequencies.  The
+// stored matrices are transposed, x_j[g'][g], so each tile of x_j is staged
+// through LDS and read back transposed; output rows are written contiguously.
 template <typename T, int CH>
 __global__ __launch_bounds__(256) void k_ct(CtLaunch L, int k0) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < L.n_elem; e += stride) {
-    const CtItem it = L.items[find_item(L.items, L.n_items, e)];
+  __shared__ double2 t1[16][33];     // x_j[b0 + .][a0 + .]  = X[g][g'] transposed
+  __shared__ double2 t2[32][17];     // x_j[a0 + .][b0 + .]  = X[g'][g] transposed
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;   // ty in [0, 16)
+  for (int t = blockIdx.x; t < L.n_tiles; t += gridDim.x) {
+    const CtItem it = L.items[find_tile(L.items, L.n_items, t)];
     if (k0 >= it.n_omega) continue;
-    const int64_t loc = e - it.elem0;
-    const int64_t ng = it.n_g;
-    const int64_t g = loc / ng, gp = loc - g * ng;
-    const int64_t mat = ng * ng;
-    double2 acc[CH];
+    const int ng = it.n_g;
+    const int ntb = (ng + 15) / 16;
+    const int lt = t - it.tile0;
+    const int a0 = (lt / ntb) * 32, b0 = (lt % ntb) * 16;
+    const int64_t mat = (int64_t)ng * ng;
+    double2 acc[2][CH];
 #pragma unroll
-    for (int k = 0; k < CH; ++k) acc[k] = make_double2(0.0, 0.0);
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int k = 0; k < CH; ++k) acc[i][k] = make_double2(0.0, 0.0);
     for (int j = 0; j < it.n_tau; ++j) {
-      double2 x = ld_x<T>(it.x, (int64_t)j * mat + loc);
-      if (it.hermitian) {
-        const double2 y = ld_x<T>(it.x, (int64_t)j * mat + gp * ng + g);
-        x.x += y.x;
-        x.y -= y.y;
+      const int64_t base = (int64_t)j * mat;
+      // t1[gp][g] = x_j[b0 + gp][a0 + g]: 16 rows of 32
+      for (int q = threadIdx.x; q < 16 * 32; q += 256) {
+        const int r = q >> 5, c = q & 31;
+        const int gp = b0 + r, g = a0 + c;
+        t1[r][c] = (gp < ng && g < ng) ? ld_x<T>(it.x, base + (int64_t)gp * ng + g)
+                                       : make_double2(0.0, 0.0);
       }
-#pragma unroll
-      for (int k = 0; k < CH; ++k) {
-        if (k0 + k < it.n_omega) {
-          const double c = it.coef[(int64_t)(k0 + k) * it.n_tau + j];
-          acc[k].x += c * x.x;
-          acc[k].y += c * x.y;
+      if (it.hermitian) {
+        // t2[g][gp] = x_j[a0 + g][b0 + gp]: 32 rows of 16
+        for (int q = threadIdx.x; q < 32 * 16; q += 256) {
+          const int r = q >> 4, c = q & 15;
+          const int g = a0 + r, gp = b0 + c;
+          t2[r][c] = (gp < ng && g < ng) ? ld_x<T>(it.x, base + (int64_t)g * ng + gp)
+                                         : make_double2(0.0, 0.0);
         }
       }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int gl = ty + 16 * i;       // 0..31
+        double2 x = t1[tx][gl];           // X[g][g'] = x_j[g'][g]
+        if (it.hermitian) {
+          const double2 y = t2[gl][tx];   // X[g'][g] = x_j[g][g']
+          x.x += y.x;
+          x.y -= y.y;
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          if (k0 + k < it.n_omega) {
+            const double c = it.coef[(int64_t)(k0 + k) * it.n_tau + j];
+            acc[i][k].x += c * x.x;
+            acc[i][k].y += c * x.y;
+          }
+        }
+      }
+      __syncthreads();
     }
 #pragma unroll
-    for (int k = 0; k < CH; ++k)
-      if (k0 + k < it.n_omega)
-        reinterpret_cast<double2 *>(it.out)[(int64_t)(k0 + k) * mat + loc] = acc[k];
+    for (int i = 0; i < 2; ++i) {
+      const int g = a0 + ty + 16 * i, gp = b0 + tx;
+      if (g < ng && gp < ng) {
+#pragma unroll
+        for (int k = 0; k < CH; ++k)
+          if (k0 + k < it.n_omega)
+            reinterpret_cast<double2 *>(it.out)[(int64_t)(k0 + k) * mat + (int64_t)g * ng + gp] =
+                acc[i][k];
+      }
+    }
   }
 }
 
@@ -118,10 +156,9 @@ __global__ __launch_bounds__(256) void k_fill_zero(uint4 *p, int64_t n16, char *
 }  // namespace
 
 hipError_t launch_ct(const CtLaunch &L, int dbl, int max_omega, hipStream_t s) {
-  if (L.n_elem <= 0) return hipSuccess;
-  const int64_t want = (L.n_elem + 255) / 256;
-  const int grid = (int)(want < 16384 ? want : 16384);
-  constexpr int CH = 8;
+  if (L.n_tiles <= 0) return hipSuccess;
+  const int grid = L.n_tiles < 65536 ? L.n_tiles : 65536;
+  constexpr int CH = 16;
   for (int k0 = 0; k0 < max_omega; k0 += CH) {
     if (dbl) hipLaunchKernelGGL((k_ct<double, CH>), dim3(grid), dim3(256), 0, s, L, k0);
     else hipLaunchKernelGGL((k_ct<float, CH>), dim3(grid), dim3(256), 0, s, L, k0);

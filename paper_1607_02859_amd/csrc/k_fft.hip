@@ -2,20 +2,23 @@
 //
 // Sec. II.C step (i), Eqs. (43)-(44): chi is transformed to reciprocal space
 // one index at a time and only plane waves inside the cutoff sphere are
-// kept.  Here a "column" is one 3D field of N_r = n0*n1*n2 points:
+// kept.  A "column" is one 3D field of N_r = n0*n1*n2 points:
 //   first index  (sign -1): column r' of a slab of chi(r, r')  -> chi(G, r')
 //   second index (sign +1): row G of chi(G, r')                -> chi(G, G')
 // out(G) = sum_r exp(sign * 2 pi i (k0 i0/n0 + k1 i1/n1 + k2 i2/n2)) f(r),
 // unnormalised, for the caller's list of plane waves.
 //
-// One workgroup transforms one column:
-//   1. groups of i0-planes are loaded into LDS and transformed along i2 and
-//      i1 (one thread per line, register FFT);
-//   2. only the (k1, k2) pencils that the sphere touches are kept, in a
-//      pencil buffer [d][i0] (LDS when it fits, else a per-block slot of
-//      global scratch);
-//   3. each pencil is transformed along i0 and the sphere points are
-//      written in output-slot order.
+// Two launches per transform:
+//   k_fft_planes : a block loads `cols` adjacent columns x `planes` i0-planes
+//                  into LDS (columns innermost, so global reads and the tmp
+//                  writes are contiguous runs of `cols` elements), transforms
+//                  along i2 and i1 (one thread per line, register FFT) and
+//                  keeps only the (k1, k2) pencils the sphere touches:
+//                  tmp[(i0 * n_disk + d) * n_cols + c];
+//   k_fft_pencils: a block owns one pencil d and 256 adjacent columns (one
+//                  per thread), transforms along i0 in registers and writes
+//                  the sphere points of that pencil; consecutive threads
+//                  write consecutive columns.
 // Line transforms are compile-time mixed-radix (4, 2, 3, 5, 7) decimation in
 // time, with twiddles as compile-time constants (exact for quarter turns).
 #include <type_traits>
@@ -163,60 +166,193 @@ __device__ __noinline__ void line_fft(cx<T> *p, int stride, int n) {
   }
 }
 
-template <typename T, int SIGN>
-__global__ __launch_bounds__(256) void k_fft(FftLaunch L) {
+// LDS index of element (p, i1, i2, column cc) in a plane block: grid points
+// in row-major order, each holding `cols` columns padded to cols + 1 elements,
+// so that both column-contiguous and point-contiguous accesses spread over
+// the LDS banks.
+__device__ __forceinline__ int lds_idx(int p, int i1, int i2, int cc, int n1, int n2, int cols) {
+  return ((p * n1 + i1) * n2 + i2) * (cols + 1) + cc;
+}
+
+__device__ __forceinline__ int find_job(const FftJob *jobs, int n, int u, bool pencils) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int u0 = pencils ? jobs[mid].unit0_pencils : jobs[mid].unit0_planes;
+    if (u0 <= u) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// in-place line transform: compile-time length when NC > 0, else dispatched
+template <int NC, int SIGN, typename T>
+__device__ __forceinline__ void line(cx<T> *p, int stride, int n) {
+  if constexpr (NC > 0) {
+    line_n<NC, SIGN, T>(p, stride);
+  } else {
+    line_fft<SIGN, T>(p, stride, n);
+  }
+}
+
+// NC > 0: every job of the launch has the cubic grid NC^3 (sizes, block shape
+// and line lengths are compile-time); NC == 0: sizes from the geometry table.
+template <typename T, int SIGN, int NC>
+__global__ __launch_bounds__(256) void k_fft_planes(FftLaunch L) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
+  cx<T> *buf = reinterpret_cast<cx<T> *>(smem);
   const int tid = threadIdx.x;
-  for (int w = blockIdx.x; w < L.n_work; w += gridDim.x) {
-    int lo = 0, hi = L.n_jobs - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (L.jobs[mid].work0 <= w) lo = mid;
-      else hi = mid - 1;
-    }
-    const FftJob J = L.jobs[lo];
-    const int c = w - J.work0;
+  constexpr int EC = (int)sizeof(cx<T>);
+  for (int u = blockIdx.x; u < L.n_units_planes; u += gridDim.x) {
+    const FftJob J = L.jobs[find_job(L.jobs, L.n_jobs, u, false)];
     const Geo G = L.geos[J.geo];
-    const int n0 = G.n0, n1 = G.n1, n2 = G.n2;
-    const int plane = n1 * n2, D = G.n_disk;
-    cx<T> *pl = reinterpret_cast<cx<T> *>(smem);
-    cx<T> *disk = G.disk_in_lds
-                      ? pl + (int64_t)G.planes * plane
-                      : reinterpret_cast<cx<T> *>(L.scratch) + (int64_t)blockIdx.x * L.scratch_slot;
-    for (int p0 = 0; p0 < n0; p0 += G.planes) {
-      const int np = min(G.planes, n0 - p0);
-      // rows below this flat index are zero (lower-triangle storage of a Hermitian chi)
-      const int rmin = L.lower_only ? (J.col0 + c) - p0 * plane : 0;
-      if (L.in_real) {
-        const T *in = reinterpret_cast<const T *>(J.in) + (int64_t)c * J.in_col_stride +
-                      (int64_t)p0 * plane;
-        for (int idx = tid; idx < np * plane; idx += 256)
-          pl[idx] = idx >= rmin ? cx<T>{in[idx], (T)0} : cx<T>{(T)0, (T)0};
-      } else {
-        const cx<T> *in = reinterpret_cast<const cx<T> *>(J.in) + (int64_t)c * J.in_col_stride +
-                          (int64_t)p0 * plane;
-        for (int idx = tid; idx < np * plane; idx += 256)
-          pl[idx] = idx >= rmin ? in[idx] : cx<T>{(T)0, (T)0};
+    const int n0 = NC ? NC : G.n0, n1 = NC ? NC : G.n1, n2 = NC ? NC : G.n2;
+    const int C = NC ? fft_cols(NC, NC, EC) : G.cols;
+    const int P = NC ? fft_planes(NC, NC, NC, EC) : G.planes;
+    const int D = G.n_disk;
+    const int plane = n1 * n2;
+    const int npg = (n0 + P - 1) / P;
+    const int lu = u - J.unit0_planes;
+    const int cg = lu / npg, pg = lu - cg * npg;
+    const int c0 = cg * C, p0 = pg * P;
+    const int np = min(P, n0 - p0);
+    // load np planes of C columns
+    const int total = np * plane * C;
+    if (J.s_col == 0) {
+      // column-grouped input: the block's C columns over these planes are one
+      // contiguous run, element (rl, cc) at ((cg * n_r) + r) * C + cc
+      const int64_t gbase = (int64_t)cg * (n0 * plane) * C;
+      for (int idx = tid; idx < total; idx += 256) {
+        const int cc = idx % C, rl = idx / C;
+        const int c = c0 + cc;
+        const int64_t r = (int64_t)p0 * plane + rl;
+        cx<T> v = {(T)0, (T)0};
+        if (c < J.n_cols && !(L.lower_only && r < J.col0 + c)) {
+          const int64_t e = gbase + r * C + cc;
+          if (L.in_real) v.x = reinterpret_cast<const T *>(J.in)[e];
+          else v = reinterpret_cast<const cx<T> *>(J.in)[e];
+        }
+        const int p = rl / plane, q = rl - p * plane;
+        const int i1 = q / n2, i2 = q - i1 * n2;
+        buf[lds_idx(p, i1, i2, cc, n1, n2, C)] = v;
       }
-      __syncthreads();
-      for (int ln = tid; ln < np * n1; ln += 256) line_fft<SIGN, T>(pl + ln * n2, 1, n2);
-      __syncthreads();
-      for (int ln = tid; ln < np * n2; ln += 256) {
-        const int p = ln / n2, i2 = ln - p * n2;
-        line_fft<SIGN, T>(pl + p * plane + i2, n2, n1);
+    } else {
+      // each column contiguous in r: rl fastest
+      const int span = np * plane;
+      for (int idx = tid; idx < total; idx += 256) {
+        const int cc = idx / span, rl = idx - cc * span;
+        const int c = c0 + cc;
+        const int64_t r = (int64_t)p0 * plane + rl;
+        cx<T> v = {(T)0, (T)0};
+        if (c < J.n_cols && !(L.lower_only && r < J.col0 + c)) {
+          const int64_t e = r * J.s_r + (int64_t)c * J.s_col;
+          if (L.in_real) v.x = reinterpret_cast<const T *>(J.in)[e];
+          else v = reinterpret_cast<const cx<T> *>(J.in)[e];
+        }
+        const int p = rl / plane, q = rl - p * plane;
+        const int i1 = q / n2, i2 = q - i1 * n2;
+        buf[lds_idx(p, i1, i2, cc, n1, n2, C)] = v;
       }
-      __syncthreads();
-      for (int idx = tid; idx < np * D; idx += 256) {
-        const int p = idx / D, d = idx - p * D;
-        disk[(int64_t)d * n0 + p0 + p] = pl[p * plane + G.disk_i12[d]];
-      }
-      __syncthreads();
     }
-    for (int d = tid; d < D; d += 256) line_fft<SIGN, T>(disk + (int64_t)d * n0, 1, n0);
     __syncthreads();
-    cx<T> *out = reinterpret_cast<cx<T> *>(J.out) + (int64_t)(J.col0 + c) * J.out_col_stride;
-    for (int s = tid; s < G.n_g; s += 256) out[(int64_t)s * J.out_slot_stride] = disk[G.slot_dk[s]];
+    // along i2: lines (p, i1, cc), stride C
+    for (int ln = tid; ln < np * n1 * C; ln += 256) {
+      const int cc = ln % C, rest = ln / C;
+      const int p = rest / n1, i1 = rest - p * n1;
+      line<NC, SIGN, T>(buf + lds_idx(p, i1, 0, cc, n1, n2, C), C + 1, n2);
+    }
     __syncthreads();
+    // along i1: lines (p, i2, cc), stride one padded row
+    for (int ln = tid; ln < np * n2 * C; ln += 256) {
+      const int cc = ln % C, rest = ln / C;
+      const int p = rest / n2, i2 = rest - p * n2;
+      line<NC, SIGN, T>(buf + lds_idx(p, 0, i2, cc, n1, n2, C), n2 * (C + 1), n1);
+    }
+    __syncthreads();
+    // keep the sphere's pencils
+    cx<T> *tmp = reinterpret_cast<cx<T> *>(J.tmp);
+    for (int idx = tid; idx < np * D * C; idx += 256) {
+      const int cc = idx % C, rest = idx / C;
+      const int p = rest / D, d = rest - p * D;
+      const int c = c0 + cc;
+      if (c < J.n_cols) {
+        const int i12 = G.disk_i12[d];
+        const int i1 = i12 / n2, i2 = i12 - i1 * n2;
+        tmp[((int64_t)(p0 + p) * D + d) * J.n_cols + c] = buf[lds_idx(p, i1, i2, cc, n1, n2, C)];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int N, int SIGN, typename T>
+__device__ __forceinline__ void pencil_n(const FftJob &J, const Geo &G, int d, int c) {
+  const cx<T> *tmp = reinterpret_cast<const cx<T> *>(J.tmp);
+  cx<T> v[N], o[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = tmp[((int64_t)i * G.n_disk + d) * J.n_cols + c];
+  reg_fft<N, SIGN, T, 1>(v, o);
+  cx<T> *out = reinterpret_cast<cx<T> *>(J.out) + (int64_t)(J.col0 + c) * J.o_col;
+  const int32_t *so = G.slot_of + (int64_t)d * N;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const int s = so[k];
+    if (s >= 0) out[(int64_t)s * J.o_slot] = o[k];
+  }
+}
+
+template <typename T, int SIGN, int NC>
+__global__ __launch_bounds__(256) void k_fft_pencils(FftLaunch L) {
+  for (int u = blockIdx.x; u < L.n_units_pencils; u += gridDim.x) {
+    const FftJob J = L.jobs[find_job(L.jobs, L.n_jobs, u, true)];
+    const Geo G = L.geos[J.geo];
+    const int nch = (J.n_cols + 255) / 256;
+    const int lu = u - J.unit0_pencils;
+    const int d = lu / nch, ch = lu - d * nch;
+    const int c = ch * 256 + threadIdx.x;
+    if (c >= J.n_cols) continue;
+    if constexpr (NC > 0) {
+      pencil_n<NC, SIGN, T>(J, G, d, c);
+    } else {
+      switch (G.n0) {
+#define GW_PEN(N)                             \
+  case N:                                     \
+    pencil_n<N, SIGN, T>(J, G, d, c);         \
+    break;
+        GW_FFT_SIZES(GW_PEN)
+#undef GW_PEN
+        default:
+          break;
+      }
+    }
+  }
+}
+
+template <typename T, int S, int NC>
+hipError_t launch_fft_t(const FftLaunch &L, int lds_bytes, hipStream_t s) {
+  const int g1 = L.n_units_planes < 65536 ? L.n_units_planes : 65536;
+  const int g2 = L.n_units_pencils < 65536 ? L.n_units_pencils : 65536;
+  hipError_t e = hipFuncSetAttribute((const void *)k_fft_planes<T, S, NC>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  if (e != hipSuccess) return e;
+  if (g1 > 0) hipLaunchKernelGGL((k_fft_planes<T, S, NC>), dim3(g1), dim3(256), lds_bytes, s, L);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (g2 > 0) hipLaunchKernelGGL((k_fft_pencils<T, S, NC>), dim3(g2), dim3(256), 0, s, L);
+  return hipGetLastError();
+}
+
+template <typename T, int S>
+hipError_t launch_fft_n(const FftLaunch &L, int lds_bytes, int n, hipStream_t s) {
+  switch (n) {
+    case 12: return launch_fft_t<T, S, 12>(L, lds_bytes, s);
+    case 16: return launch_fft_t<T, S, 16>(L, lds_bytes, s);
+    case 18: return launch_fft_t<T, S, 18>(L, lds_bytes, s);
+    case 20: return launch_fft_t<T, S, 20>(L, lds_bytes, s);
+    case 24: return launch_fft_t<T, S, 24>(L, lds_bytes, s);
+    case 28: return launch_fft_t<T, S, 28>(L, lds_bytes, s);
+    case 32: return launch_fft_t<T, S, 32>(L, lds_bytes, s);
+    default: return launch_fft_t<T, S, 0>(L, lds_bytes, s);
   }
 }
 
@@ -233,22 +369,13 @@ int fft_supported(int n) {
   }
 }
 
-hipError_t launch_fft(const FftLaunch &L, int dbl, int sign, int grid, int lds_bytes,
+hipError_t launch_fft(const FftLaunch &L, int dbl, int sign, int lds_bytes, int cubic_n,
                       hipStream_t s) {
-  if (L.n_work <= 0) return hipSuccess;
-  const void *k;
-  if (dbl) k = sign < 0 ? (const void *)k_fft<double, -1> : (const void *)k_fft<double, 1>;
-  else k = sign < 0 ? (const void *)k_fft<float, -1> : (const void *)k_fft<float, 1>;
-  hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-  if (e != hipSuccess) return e;
-  if (dbl) {
-    if (sign < 0) hipLaunchKernelGGL((k_fft<double, -1>), dim3(grid), dim3(256), lds_bytes, s, L);
-    else hipLaunchKernelGGL((k_fft<double, 1>), dim3(grid), dim3(256), lds_bytes, s, L);
-  } else {
-    if (sign < 0) hipLaunchKernelGGL((k_fft<float, -1>), dim3(grid), dim3(256), lds_bytes, s, L);
-    else hipLaunchKernelGGL((k_fft<float, 1>), dim3(grid), dim3(256), lds_bytes, s, L);
-  }
-  return hipGetLastError();
+  const int n = fft_specialised(cubic_n) ? cubic_n : 0;
+  if (dbl) return sign < 0 ? launch_fft_n<double, -1>(L, lds_bytes, n, s)
+                           : launch_fft_n<double, 1>(L, lds_bytes, n, s);
+  return sign < 0 ? launch_fft_n<float, -1>(L, lds_bytes, n, s)
+                  : launch_fft_n<float, 1>(L, lds_bytes, n, s);
 }
 
 }  // namespace gw

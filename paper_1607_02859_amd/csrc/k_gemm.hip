@@ -6,7 +6,9 @@
 //   acc_u(r, r') = sum_a Psi_u(r, a) conj(Psi_u(r', a))   = G_unocc / edge factor
 //   chi(r, r')   = -acc_o(r, r') * conj(acc_u(r, r'))      (Eqs. (14)-(15))
 // Neither Green's function leaves the registers: only chi is written, into
-// the slab buffer [w][n_r] (column r' - s0, row r).
+// the slab buffer grouped by columns, [column group][n_r][columns in group]
+// with groups of 128 bytes, so that the lanes of one MFMA result row store
+// contiguous runs and the FFT over r reads each group as one block.
 //
 // A complex product a * conj(b) is built from real MFMAs:
 //   re += a.re b.re + a.im b.im,   im += a.im b.re - a.re b.im.
@@ -353,7 +355,9 @@ struct Gemm {
         sfor<0, WTN>([&](auto jj) {
           constexpr int j = decltype(jj)::value;
           const int col = c0 + (wc * WTN + j) * M::MB + M::acc_col(l);
-          const int64_t cb = (int64_t)(col - job.s0) * n_r;
+          const int cl = col - job.s0;
+          const int sh = job.cg_shift;
+          const int64_t cb = ((int64_t)(cl >> sh) * n_r << sh) + (cl & ((1 << sh) - 1));
           sfor<0, M::NACC>([&](auto vv) {
             constexpr int v = decltype(vv)::value;
             const int row = r0 + (wr * WTM + i) * M::MB + M::acc_row(l, v);
@@ -365,11 +369,11 @@ struct Gemm {
                 const double oim = ao.im[i][j][v], uim = au.im[i][j][v];
                 double2 x = make_double2(-(ore * ure + oim * uim), -(oim * ure - ore * uim));
                 if (diag) x = make_double2(0.5 * x.x, 0.0);
-                if (ok) reinterpret_cast<double2 *>(job.slab)[cb + row] = x;
+                if (ok) reinterpret_cast<double2 *>(job.slab)[cb + ((int64_t)row << sh)] = x;
               } else {
                 double x = -(ore * ure);
                 if (diag) x *= 0.5;
-                if (ok) reinterpret_cast<double *>(job.slab)[cb + row] = x;
+                if (ok) reinterpret_cast<double *>(job.slab)[cb + ((int64_t)row << sh)] = x;
               }
             } else {
               const float ore = ao.re[i][j][v], ure = au.re[i][j][v];
@@ -377,11 +381,11 @@ struct Gemm {
                 const float oim = ao.im[i][j][v], uim = au.im[i][j][v];
                 float2 x = make_float2(-(ore * ure + oim * uim), -(oim * ure - ore * uim));
                 if (diag) x = make_float2(0.5f * x.x, 0.0f);
-                if (ok) reinterpret_cast<float2 *>(job.slab)[cb + row] = x;
+                if (ok) reinterpret_cast<float2 *>(job.slab)[cb + ((int64_t)row << sh)] = x;
               } else {
                 float x = -(ore * ure);
                 if (diag) x *= 0.5f;
-                if (ok) reinterpret_cast<float *>(job.slab)[cb + row] = x;
+                if (ok) reinterpret_cast<float *>(job.slab)[cb + ((int64_t)row << sh)] = x;
               }
             }
           });
