@@ -33,6 +33,16 @@ TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-4}
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # MI355X dense MFMA
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3->f32"}
 SAMPLE_ROWS = (0, 1, 57, 1500, 2968)
+WORKLOADS = {
+    1: "gamma-only real 12^3 grid, 16+112 bands, 6 tau/omega, 389 plane waves",
+    2: "gamma-only complex 24^3 grid, 64+960 bands, 12 tau/omega, 2048-column r' slabs, "
+       "2969 plane waves",
+    3: "8 k-points, complex 24^3 grid, occ 48-64 / unocc 700-1000 per k, 16 tau/omega, "
+       "2969 plane waves, one batched build",
+    4: "complex 32^3 grid, 128+2048 bands, 16 tau/omega, 2048-column r' slabs, 7123 plane waves",
+    5: "32 real systems, 16^3-28^3 grids, 16/256-96/1536 bands, gaps 0.1-10 eV, 20 tau/omega, "
+       "one batched build",
+}
 
 
 def log(*a):
@@ -70,6 +80,8 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
     ap.add_argument("--hermitian", type=int, default=1)
     ap.add_argument("--skip-zero-bands", type=int, default=0)
+    ap.add_argument("--config", type=int, default=2,
+                    help="workload configuration (2 is the headline; 1, 3, 4, 5 for the record)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -80,35 +92,37 @@ def main():
     from paper_1607_02859_amd import gwchi, synth
 
     dev = torch.device("cuda:0")
-    item = synth.make_config(2)[0]
-    log(f"[bench] workload n={item.n} K={item.n_occ}+{item.n_unocc} n_tau={item.n_tau} "
-        f"n_g={item.n_g}")
-    po = torch.from_numpy(item.phi_occ).to(dev)
-    pu = torch.from_numpy(item.phi_unocc).to(dev)
-    out = torch.empty((item.n_omega, item.n_g, item.n_g), dtype=torch.complex128, device=dev)
+    items = synth.make_config(args.config)
+    item = items[0]
+    log(f"[bench] config {args.config}: {len(items)} item(s), first n={item.n} "
+        f"K={item.n_occ}+{item.n_unocc} n_tau={item.n_tau} n_g={item.n_g}")
+    phis = [(torch.from_numpy(it.phi_occ).to(dev), torch.from_numpy(it.phi_unocc).to(dev))
+            for it in items]
+    outs = [torch.empty((it.n_omega, it.n_g, it.n_g), dtype=torch.complex128, device=dev)
+            for it in items]
     ctx = gwchi.Context(0)
     ctx.set_options(use_graph=1, timing=1, slab_width=2048, hermitian=args.hermitian,
                     skip_zero_bands=args.skip_zero_bands, kappa=0)
     stream = torch.cuda.current_stream()
-    alg = synth.algorithmic_flops(item)
+    alg = sum(synth.algorithmic_flops(it) for it in items)
 
     ref_rows = None
     if not args.no_check:
         from oracle import chi as oc
         t0 = time.perf_counter()
-        ref_rows = oc.chi_rows(item, list(SAMPLE_ROWS))
+        rows = [r for r in SAMPLE_ROWS if r < item.n_g]
+        ref_rows = oc.chi_rows(item, rows)
         log(f"[bench] oracle sampled rows in {time.perf_counter() - t0:.1f} s")
 
     paths = {}
     for prec in args.precisions.split(","):
         for _ in range(args.warmup):
-            ctx.build_device([item], [(po, pu)], [out], prec, stream=stream, report=True)
+            ctx.build_device(items, phis, outs, prec, stream=stream, report=True)
         torch.cuda.synchronize()
         reps = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            reps.append(ctx.build_device([item], [(po, pu)], [out], prec, stream=stream,
-                                         report=True))
+            reps.append(ctx.build_device(items, phis, outs, prec, stream=stream, report=True))
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / args.steps
         ms_step = 1e3 * wall
@@ -116,7 +130,7 @@ def main():
         n_launch = reps[-1]["n_gemm_launches"]
         p = {
             "ms_per_step": ms_step,
-            "ms_per_tau": ms_step / item.n_tau,
+            "ms_per_tau": ms_step / max(it.n_tau for it in items),
             "tflops": alg / wall / 1e12,
             "gemm_ms_per_step": gemm_ms,
             "gemm_launches_per_step": n_launch,
@@ -132,24 +146,24 @@ def main():
             "tile_id": reps[-1]["tile_id"],
         }
         if ref_rows is not None:
-            got = out.cpu().numpy()[:, list(SAMPLE_ROWS), :]
+            got = outs[0].cpu().numpy()[:, rows, :]
             num = np.sqrt((np.abs(got - ref_rows) ** 2).reshape(item.n_omega, -1).sum(1))
             den = np.sqrt((np.abs(ref_rows) ** 2).reshape(item.n_omega, -1).sum(1))
             p["err_vs_oracle_sampled_rows"] = float((num / den).max())
             p["within_tol"] = bool(p["err_vs_oracle_sampled_rows"] <= TOL[prec])
         # kappa_F of this result (norm pass outside the timed steps)
         ctx.set_options(kappa=1)
-        p["kappa_F"] = ctx.build_device([item], [(po, pu)], [out], prec, stream=stream,
+        p["kappa_F"] = ctx.build_device(items, phis, outs, prec, stream=stream,
                                         report=True)["kappa_F_max"]
         ctx.set_options(kappa=0)
         # the same build replayed from the captured hipGraph (no per-launch events)
         ctx.set_options(timing=0)
         for _ in range(max(1, args.warmup)):
-            ctx.build_device([item], [(po, pu)], [out], prec, stream=stream)
+            ctx.build_device(items, phis, outs, prec, stream=stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            ctx.build_device([item], [(po, pu)], [out], prec, stream=stream)
+            ctx.build_device(items, phis, outs, prec, stream=stream)
         torch.cuda.synchronize()
         p["ms_per_step_graph"] = 1e3 * (time.perf_counter() - t0) / args.steps
         ctx.set_options(timing=1)
@@ -174,8 +188,7 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[head],
         "data": "synthetic",
-        "config": {"workload": "gamma-only complex 24^3 grid, 64+960 bands, 12 tau/omega, "
-                               "2048-column r' slabs, 2969 plane waves",
+        "config": {"workload": WORKLOADS[args.config],
                    "precision": head, "hermitian": args.hermitian,
                    "skip_zero_bands": args.skip_zero_bands},
         "ms_per_tau": H["ms_per_tau"],
@@ -200,7 +213,7 @@ def main():
         "avg_launch_ms": H["gemm_ms_per_launch"],
         "launches_per_step": H["gemm_launches_per_step"],
     }
-    if not args.no_cpu:
+    if not args.no_cpu and args.config == 2:
         res["cpu_baseline"] = cpu_baseline(item, 6)
     ctx.close()
     print(json.dumps(res), flush=True)

@@ -113,19 +113,20 @@ struct FftLaunch {
 // Cosine transform (FP64 accumulation) and norms.
 // ---------------------------------------------------------------------------
 struct CtItem {
-  const void *x;            // [n_tau][n_g][n_g] transposed: x_j[g'][g] = chi(G, G', i tau_j)
+  const void *x;            // [n_tau_x][n_g][n_g] transposed: x_j[g'][g] = chi(G, G', i tau_{j0+j})
   double *out;              // [n_omega][n_g][n_g] complex FP64
   const double *coef;       // [n_omega][n_tau] c'_kj including the edge factor
   int32_t n_g, n_tau, n_omega;
+  int32_t j0, n_tau_x;      // taus held in x: j0 .. j0 + n_tau_x - 1
   int32_t hermitian;        // 1: x holds X with chi = X + X^H
-  int64_t elem0;            // first flat output element of this item in the launch
+  int32_t accumulate;       // 1: continue the sums already in out (taus before j0)
+  int32_t item;             // index of the item in the call (norm tables)
   int32_t tile0;            // first 32x16 output tile of this item in the launch
 };
 
 struct CtLaunch {
   const CtItem *items;
   int32_t n_items;
-  int64_t n_elem;           // sum over items of n_g^2
   int32_t n_tiles;          // sum over items of the 32x16 output tiles
 };
 
@@ -168,9 +169,10 @@ constexpr bool fft_specialised(int n) {
 }
 int fft_supported(int n);
 hipError_t launch_ct(const CtLaunch &L, int dbl, int max_omega, hipStream_t s);
-hipError_t launch_norms_impl(const CtLaunch &L, int dbl, double *norm_tau, double *norm_omega,
-                             const int32_t *tau_off, const int32_t *omega_off, int max_mats,
-                             hipStream_t s);
+// mode 0: |chi(tau_j)|_F^2 of the taus held in x; mode 1: |chi(i omega_k)|_F^2 of out
+hipError_t launch_norms_impl(const CtLaunch &L, int dbl, int mode, double *norm_tau,
+                             double *norm_omega, const int32_t *tau_off,
+                             const int32_t *omega_off, int max_mats, hipStream_t s);
 hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t s);
 
 }  // namespace gw

@@ -42,7 +42,7 @@ struct DevBuf {
       p = nullptr;
       n = 0;
     }
-    size_t want = bytes + bytes / 8 + 256;
+    size_t want = (bytes + 4095) / 4096 * 4096 + 4096;
     hipError_t e = hipMalloc(&p, want);
     if (e != hipSuccess) {
       p = nullptr;
@@ -102,6 +102,7 @@ struct Launch {
   int max_mats = 0;
   void *fill_ptr = nullptr;
   int64_t fill_bytes = 0;
+  int norm_mode = 0;
   const int32_t *toff = nullptr, *woff = nullptr;
 };
 
@@ -249,25 +250,27 @@ struct ItemPlan {
   std::vector<double> tau;
   const double *phi_o = nullptr, *phi_u = nullptr;
   double *out = nullptr;
-  int64_t x_off = 0;           // byte offset in b_x
   int job0 = 0;
 };
 
 struct JobPlan {
   int item, j;
   int k_o_eff, k_u_eff;
+  int pass = 0;
+  // byte offsets of this job's slots in the pass-local buffers
+  int64_t o_psi = 0, o_slab = 0, o_xr = 0, o_tmp = 0, o_x = 0;
 };
 
 struct Plan {
   int prec = 0;
   int tile = 0, bm = 0, bn = 0, kc = 0;
   int slab_w = 2048;
-  int jobs_per_pass = 1;
   std::vector<ItemPlan> items;
   std::vector<JobPlan> jobs;
-  // per-job slot sizes (bytes), uniform across slots (maxima)
-  int64_t psi_slot = 0, slab_slot = 0, xr_slot = 0;
-  int64_t x_bytes = 0, tmp_slot = 0;
+  std::vector<int> pass_begin;      // first job of each pass, plus the end
+  // buffer sizes: maxima over passes of the packed job slots
+  int64_t psi_bytes = 0, slab_bytes = 0, xr_bytes = 0, tmp_bytes = 0, x_bytes = 0;
+  int max_jobs_pass = 0;
   int fft_lds = 0;
   double alg_flops = 0, mfma_flops = 0;
   int cplx_any = 0, real_any = 0;
@@ -318,7 +321,6 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
   const int es = elem_slab(prec, cplx);
   const int bpb = bpb_of(prec, cplx);
   P.items.resize(n_items);
-  int64_t max_n_r = 0;
   for (int t = 0; t < n_items; ++t) {
     const gwchi_item &it = items[t];
     ItemPlan &I = P.items[t];
@@ -327,7 +329,6 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
     I.n2 = it.n[2];
     I.n_r = (int64_t)I.n0 * I.n1 * I.n2;
     I.n_r_pad = round_up(I.n_r, kRowPad);
-    max_n_r = std::max(max_n_r, I.n_r);
     I.cplx = it.is_complex;
     I.k_o = it.n_occ;
     I.k_u = it.n_unocc;
@@ -404,45 +405,75 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
       P.jobs.push_back(J);
     }
   }
-  // sizes
-  int64_t x_total = 0;
-  int64_t psi_max = 0, xr_max = 0, tmp_max = 0;
-  const int W0 = ctx->opt.slab_width > 0 ? (int)round_up(ctx->opt.slab_width, 256) : 2048;
-  for (auto &I : P.items) {
-    I.x_off = x_total;
-    x_total += round_up((int64_t)I.n_tau * I.n_g * I.n_g * ec, 256);
-    psi_max = std::max<int64_t>(psi_max, I.n_r_pad * (I.k_o_pad + I.k_u_pad) * bpb);
-    xr_max = std::max<int64_t>(xr_max, (int64_t)I.n_g * I.n_r * ec);
-    const int64_t ncols = std::max<int64_t>(std::min<int64_t>(W0, I.n_r), I.n_g);
-    tmp_max = std::max<int64_t>(tmp_max, (int64_t)I.n0 * I.n_disk * ncols * ec);
-  }
-  P.x_bytes = x_total;
-  P.psi_slot = round_up(psi_max, 256);
-  P.xr_slot = round_up(xr_max, 256);
-  P.tmp_slot = round_up(tmp_max, 256);
   int lds_need = 0;
   for (auto &I : P.items) lds_need = std::max(lds_need, I.fft_lds);
   P.fft_lds = lds_need;
-  // budget
+  // Pack jobs into passes.  Each job owns slots for its scaled operands, its
+  // slab, chi(G, r'), the pencil scratch and chi(tau_j); consecutive jobs of
+  // one item keep consecutive chi(tau) slots, which the cosine transform reads.
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)64 << 30;
-  // memory the context already holds counts as available
+  // scratch the context already holds is released before a larger plan allocates
   const size_t held = ctx->b_psi.n + ctx->b_slab.n + ctx->b_xr.n + ctx->b_x.n + ctx->b_tmp.n;
-  int64_t budget = ctx->opt.max_device_bytes > 0 ? ctx->opt.max_device_bytes
-                                                 : (int64_t)((free_b + held) * 0.6);
-  const int64_t fixed = P.x_bytes + ((int64_t)64 << 20);
-  int W = W0;
+  const int64_t budget = ctx->opt.max_device_bytes > 0 ? ctx->opt.max_device_bytes
+                                                       : (int64_t)((free_b + held) * 0.6);
+  const int64_t fixed = (int64_t)64 << 20;
   const int n_jobs = (int)P.jobs.size();
+  const int want = ctx->opt.tau_batch > 0 ? std::min(ctx->opt.tau_batch, n_jobs) : n_jobs;
+  int W = ctx->opt.slab_width > 0 ? (int)round_up(ctx->opt.slab_width, 256) : 2048;
   for (;;) {
-    const int64_t slab_max = round_up((int64_t)std::min<int64_t>(W, round_up(max_n_r, 256)) *
-                                          max_n_r * es, 256);   // W is a multiple of any group
-    const int64_t per_job = P.psi_slot + slab_max + P.xr_slot + P.tmp_slot;
-    int64_t fit = per_job > 0 ? (budget - fixed) / per_job : 0;
-    int want = ctx->opt.tau_batch > 0 ? std::min(ctx->opt.tau_batch, n_jobs) : n_jobs;
-    if (fit >= 1) {
+    auto sizes = [&](const ItemPlan &I, int64_t *b) {
+      const int64_t wmax = std::min<int64_t>(W, I.n_r);
+      b[0] = round_up(I.n_r_pad * (I.k_o_pad + I.k_u_pad) * bpb, 256);
+      b[1] = round_up(round_up(wmax, I.cols) * I.n_r * es, 256);
+      b[2] = round_up((int64_t)I.n_g * I.n_r * ec, 256);
+      b[3] = round_up((int64_t)I.n0 * I.n_disk * std::max<int64_t>(wmax, I.n_g) * ec, 256);
+      b[4] = (int64_t)I.n_g * I.n_g * ec;
+    };
+    bool ok = true;
+    P.pass_begin.assign(1, 0);
+    P.psi_bytes = P.slab_bytes = P.xr_bytes = P.tmp_bytes = P.x_bytes = 0;
+    P.max_jobs_pass = 0;
+    int64_t acc[5] = {0, 0, 0, 0, 0};
+    int in_pass = 0;
+    for (int q = 0; q < n_jobs && ok; ++q) {
+      JobPlan &J = P.jobs[q];
+      const ItemPlan &I = P.items[J.item];
+      int64_t b[5];
+      sizes(I, b);
+      const int64_t job = b[0] + b[1] + b[2] + b[3] + b[4];
+      const int64_t used = acc[0] + acc[1] + acc[2] + acc[3] + acc[4];
+      // a new item's chi(tau) block starts 256-aligned
+      const bool new_item = in_pass == 0 || P.jobs[q - 1].item != J.item;
+      const int64_t xalign = new_item ? round_up(acc[4], 256) - acc[4] : 0;
+      if (in_pass > 0 && (in_pass >= want || fixed + used + xalign + job > budget)) {
+        P.pass_begin.push_back(q);
+        for (int k = 0; k < 5; ++k) acc[k] = 0;
+        in_pass = 0;
+      }
+      if (fixed + job > budget) {
+        ok = false;
+        break;
+      }
+      if (in_pass == 0 || P.jobs[q - 1].item != J.item) acc[4] = round_up(acc[4], 256);
+      J.pass = (int)P.pass_begin.size() - 1;
+      J.o_psi = acc[0];
+      J.o_slab = acc[1];
+      J.o_xr = acc[2];
+      J.o_tmp = acc[3];
+      J.o_x = acc[4];
+      for (int k = 0; k < 5; ++k) acc[k] += b[k];
+      ++in_pass;
+      P.psi_bytes = std::max(P.psi_bytes, acc[0]);
+      P.slab_bytes = std::max(P.slab_bytes, acc[1]);
+      P.xr_bytes = std::max(P.xr_bytes, acc[2]);
+      P.tmp_bytes = std::max(P.tmp_bytes, acc[3]);
+      P.x_bytes = std::max(P.x_bytes, round_up(acc[4], 256));
+      P.max_jobs_pass = std::max(P.max_jobs_pass, in_pass);
+    }
+    if (ok) {
+      P.pass_begin.push_back(n_jobs);
       P.slab_w = W;
-      P.slab_slot = slab_max;
-      P.jobs_per_pass = (int)std::min<int64_t>(want, fit);
       break;
     }
     if (W <= 256 || ctx->opt.slab_width > 0) {
@@ -533,8 +564,10 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
   char *x_base = reinterpret_cast<char *>(ctx->b_x.p);
   char *tmp_base = reinterpret_cast<char *>(ctx->b_tmp.p);
   std::ostringstream key;
-  key << "p" << P.prec << "t" << P.tile << "w" << P.slab_w << "b" << P.jobs_per_pass << "h"
-      << ctx->opt.hermitian << "n" << want_norms << "|";
+  key << "p" << P.prec << "t" << P.tile << "w" << P.slab_w << "h" << ctx->opt.hermitian << "n"
+      << want_norms << "|";
+  for (int b : P.pass_begin) key << b << ",";
+  key << "|";
   // geometry tables
   std::vector<size_t> off_i12(n_items), off_sdk(n_items), off_perm_o(n_items),
       off_perm_u(n_items), off_eps_o(n_items), off_eps_u(n_items), off_coef(n_items);
@@ -569,15 +602,31 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
     geos[t] = g;
   }
   const size_t off_geos = B.blob.addv(geos);
-  // record which blob words hold offsets to patch: we patch by re-walking below
-  // (simple: every device pointer into the blob is written as blob offset + marker)
-  const int n_jobs = (int)P.jobs.size();
-  const int per_pass = P.jobs_per_pass;
-  B.n_passes = (n_jobs + per_pass - 1) / per_pass;
+  B.n_passes = (int)P.pass_begin.size() - 1;
   int max_slabs = 0;
   for (auto &I : P.items) max_slabs = std::max<int>(max_slabs, (int)((I.n_r + P.slab_w - 1) / P.slab_w));
+  // norms: per-tau offsets (filled per pass), per-omega offsets (after the last pass)
+  std::vector<int32_t> toff(n_items), woff(n_items);
+  int nt = 0, nw = 0;
+  for (int t = 0; t < n_items; ++t) {
+    toff[t] = nt;
+    woff[t] = nw;
+    nt += P.items[t].n_tau;
+    nw += P.items[t].n_omega;
+  }
+  B.n_norm_tau = nt;
+  B.n_norm_omega = nw;
+  const size_t off_toff = B.blob.addv(toff), off_woff = B.blob.addv(woff);
+  if (want_norms) {
+    Launch Z{};
+    Z.phase = PH_NORM;
+    Z.kind = 5;
+    Z.fill_ptr = ctx->b_norm.p;
+    Z.fill_bytes = (int64_t)(nt + nw) * 8;
+    B.launches.push_back(Z);
+  }
   for (int ps = 0; ps < B.n_passes; ++ps) {
-    const int jb = ps * per_pass, je = std::min(n_jobs, jb + per_pass);
+    const int jb = P.pass_begin[ps], je = P.pass_begin[ps + 1];
     // ---- stage: one op per (item in pass, occ|unocc)
     {
       std::vector<StageOp> ops;
@@ -606,7 +655,7 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
           std::vector<void *> pl;
           std::vector<double> tl;
           for (int q = jj; q < je2; ++q) {
-            char *slot = psi_base + (int64_t)(q - jb) * P.psi_slot;
+            char *slot = psi_base + P.jobs[q].o_psi;
             const int64_t o_bytes = I.n_r_pad * I.k_o_pad * bpb_of(P.prec, cplx);
             pl.push_back(side == 0 ? slot : slot + o_bytes);
             tl.push_back(I.tau[P.jobs[q].j]);
@@ -645,7 +694,7 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
         const int64_t s0 = (int64_t)s * P.slab_w;
         if (s0 >= I.n_r) continue;
         const int w = (int)std::min<int64_t>(P.slab_w, I.n_r - s0);
-        char *slot = psi_base + (int64_t)(q - jb) * P.psi_slot;
+        char *slot = psi_base + J.o_psi;
         GemmJob g{};
         g.psi_o = slot;
         g.psi_u = slot + I.n_r_pad * I.k_o_pad * bpb_of(P.prec, cplx);
@@ -658,7 +707,7 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
         g.w = w;
         g.cg_shift = 0;
         while ((1 << (g.cg_shift + 1)) <= I.cols) ++g.cg_shift;
-        g.slab = slab_base + (int64_t)(q - jb) * P.slab_slot;
+        g.slab = slab_base + J.o_slab;
         const int gi = (int)gj.size();
         gj.push_back(g);
         const int nrt = (int)((I.n_r + P.bm - 1) / P.bm);
@@ -678,8 +727,8 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
         f.in = g.slab;
         f.s_r = 1;
         f.s_col = 0;                       // column-grouped slab
-        f.tmp = tmp_base + (int64_t)(q - jb) * P.tmp_slot;
-        f.out = xr_base + (int64_t)(q - jb) * P.xr_slot;
+        f.tmp = tmp_base + J.o_tmp;
+        f.out = xr_base + J.o_xr;
         f.o_slot = I.n_r;
         f.o_col = 1;
         f.col0 = (int32_t)s0;
@@ -706,11 +755,11 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
         const JobPlan &J = P.jobs[q];
         const ItemPlan &I = P.items[J.item];
         FftJob f{};
-        f.in = xr_base + (int64_t)(q - jb) * P.xr_slot;
+        f.in = xr_base + J.o_xr;
         f.s_r = 1;
         f.s_col = I.n_r;
-        f.tmp = tmp_base + (int64_t)(q - jb) * P.tmp_slot;
-        f.out = x_base + I.x_off + (int64_t)J.j * I.n_g * I.n_g * ec;
+        f.tmp = tmp_base + J.o_tmp;
+        f.out = x_base + J.o_x;
         f.o_slot = I.n_g;
         f.o_col = 1;
         f.col0 = 0;
@@ -720,61 +769,81 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
       }
       emit_fft(B, P, fj, PH_FFT_RP, +1, 0, 0, off_geos);
     }
+    // ---- cosine transform of this pass's taus, per item; an item whose taus
+    // span passes continues its FP64 sums from the previous pass's output
+    {
+      std::vector<CtItem> cts;
+      int tiles = 0, max_omega = 0, max_mats = 0;
+      int jj = jb;
+      while (jj < je) {
+        const int t = P.jobs[jj].item;
+        int je2 = jj;
+        while (je2 < je && P.jobs[je2].item == t) ++je2;
+        const ItemPlan &I = P.items[t];
+        CtItem c{};
+        c.x = x_base + P.jobs[jj].o_x;
+        c.out = I.out;
+        c.coef = reinterpret_cast<const double *>(off_coef[t]);
+        c.n_g = I.n_g;
+        c.n_tau = I.n_tau;
+        c.j0 = P.jobs[jj].j;
+        c.n_tau_x = je2 - jj;
+        c.n_omega = I.n_omega;
+        c.hermitian = ctx->opt.hermitian;
+        c.accumulate = c.j0 > 0 ? 1 : 0;
+        c.item = t;
+        c.tile0 = tiles;
+        tiles += ((I.n_g + 31) / 32) * ((I.n_g + 15) / 16);
+        max_omega = std::max(max_omega, I.n_omega);
+        max_mats = std::max(max_mats, je2 - jj);
+        cts.push_back(c);
+        jj = je2;
+      }
+      Launch C{};
+      C.phase = PH_CT;
+      C.kind = 3;
+      C.ct.items = reinterpret_cast<const CtItem *>(B.blob.addv(cts));
+      C.ct.n_items = (int)cts.size();
+      C.ct.n_tiles = tiles;
+      C.max_omega = max_omega;
+      B.launches.push_back(C);
+      if (want_norms) {
+        Launch N{};
+        N.phase = PH_NORM;
+        N.kind = 4;
+        N.ct = C.ct;
+        N.norm_mode = 0;
+        N.max_mats = max_mats;
+        N.toff = reinterpret_cast<const int32_t *>(off_toff);
+        N.woff = reinterpret_cast<const int32_t *>(off_woff);
+        B.launches.push_back(N);
+      }
+    }
   }
-  // ---- cosine transform
-  std::vector<CtItem> cts(n_items);
-  int64_t elems = 0;
-  int tiles = 0;
-  int max_omega = 0, max_mats = 0;
-  std::vector<int32_t> toff(n_items), woff(n_items);
-  int nt = 0, nw = 0;
-  for (int t = 0; t < n_items; ++t) {
-    const ItemPlan &I = P.items[t];
-    CtItem c{};
-    c.x = x_base + I.x_off;
-    c.out = I.out;
-    c.coef = reinterpret_cast<const double *>(off_coef[t]);
-    c.n_g = I.n_g;
-    c.n_tau = I.n_tau;
-    c.n_omega = I.n_omega;
-    c.hermitian = ctx->opt.hermitian;
-    c.elem0 = elems;
-    c.tile0 = tiles;
-    elems += (int64_t)I.n_g * I.n_g;
-    tiles += ((I.n_g + 31) / 32) * ((I.n_g + 15) / 16);
-    cts[t] = c;
-    max_omega = std::max(max_omega, I.n_omega);
-    max_mats = std::max(max_mats, I.n_tau + I.n_omega);
-    toff[t] = nt;
-    woff[t] = nw;
-    nt += I.n_tau;
-    nw += I.n_omega;
-  }
-  Launch C{};
-  C.phase = PH_CT;
-  C.kind = 3;
-  C.ct.items = reinterpret_cast<const CtItem *>(B.blob.addv(cts));
-  C.ct.n_items = n_items;
-  C.ct.n_elem = elems;
-  C.ct.n_tiles = tiles;
-  C.max_omega = max_omega;
-  B.launches.push_back(C);
-  B.n_norm_tau = nt;
-  B.n_norm_omega = nw;
   if (want_norms) {
-    Launch Z{};
-    Z.phase = PH_NORM;
-    Z.kind = 5;
-    Z.fill_ptr = ctx->b_norm.p;
-    Z.fill_bytes = (int64_t)(nt + nw) * 8;
-    B.launches.push_back(Z);
+    // norms of the finished outputs: one entry per item over its omegas
+    std::vector<CtItem> cts;
+    int max_omega = 0;
+    for (int t = 0; t < n_items; ++t) {
+      const ItemPlan &I = P.items[t];
+      CtItem c{};
+      c.out = I.out;
+      c.n_g = I.n_g;
+      c.n_tau = I.n_tau;
+      c.n_omega = I.n_omega;
+      c.item = t;
+      cts.push_back(c);
+      max_omega = std::max(max_omega, I.n_omega);
+    }
     Launch N{};
     N.phase = PH_NORM;
     N.kind = 4;
-    N.ct = C.ct;
-    N.max_mats = max_mats;
-    N.toff = reinterpret_cast<const int32_t *>(B.blob.addv(toff));
-    N.woff = reinterpret_cast<const int32_t *>(B.blob.addv(woff));
+    N.ct.items = reinterpret_cast<const CtItem *>(B.blob.addv(cts));
+    N.ct.n_items = n_items;
+    N.norm_mode = 1;
+    N.max_mats = max_omega;
+    N.toff = reinterpret_cast<const int32_t *>(off_toff);
+    N.woff = reinterpret_cast<const int32_t *>(off_woff);
     B.launches.push_back(N);
   }
   B.key = key.str();
@@ -873,7 +942,7 @@ gwchi_status enqueue(gwchi_ctx *ctx, const Plan &P, Built &B, bool timing,
         HIPCHK(launch_ct(L.ct, dbl, L.max_omega, s));
         break;
       case 4:
-        HIPCHK(launch_norms_impl(L.ct, dbl, reinterpret_cast<double *>(ctx->b_norm.p),
+        HIPCHK(launch_norms_impl(L.ct, dbl, L.norm_mode, reinterpret_cast<double *>(ctx->b_norm.p),
                                  reinterpret_cast<double *>(ctx->b_norm.p) + B.n_norm_tau,
                                  L.toff, L.woff, L.max_mats, s));
         break;
@@ -894,13 +963,21 @@ gwchi_status run_build(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int
   Plan P;
   gwchi_status st = build_plan(ctx, items, n_items, prec, P);
   if (st != GWCHI_OK) return st;
-  const int n_jobs_pass = P.jobs_per_pass;
+  // every buffer and table below may still be read by the previous build
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  {
+    // scratch for the plan; when any buffer must grow, drop all of them first so
+    // that old and new never coexist
+    DevBuf *bufs[5] = {&ctx->b_psi, &ctx->b_slab, &ctx->b_xr, &ctx->b_tmp, &ctx->b_x};
+    const int64_t need[5] = {P.psi_bytes, P.slab_bytes, P.xr_bytes, P.tmp_bytes, P.x_bytes};
+    bool grow = false;
+    for (int k = 0; k < 5; ++k) grow |= (size_t)need[k] > bufs[k]->n;
+    if (grow) {
+      for (int k = 0; k < 5; ++k) bufs[k]->release();
+      for (int k = 0; k < 5; ++k) HIPCHK(bufs[k]->ensure((size_t)need[k], nullptr));
+    }
+  }
   bool moved = false;
-  HIPCHK(ctx->b_psi.ensure((size_t)P.psi_slot * n_jobs_pass, &moved));
-  HIPCHK(ctx->b_slab.ensure((size_t)P.slab_slot * n_jobs_pass, &moved));
-  HIPCHK(ctx->b_xr.ensure((size_t)P.xr_slot * n_jobs_pass, &moved));
-  HIPCHK(ctx->b_x.ensure((size_t)P.x_bytes, &moved));
-  HIPCHK(ctx->b_tmp.ensure((size_t)P.tmp_slot * n_jobs_pass, &moved));
   const bool want_norms = rep != nullptr && ctx->opt.kappa != 0;
   int n_norm = 0;
   for (auto &I : P.items) n_norm += I.n_tau + I.n_omega;
@@ -918,9 +995,6 @@ gwchi_status run_build(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int
   const char *tbase = reinterpret_cast<const char *>(ctx->b_tables.p);
   patch_geos(B, tbase, off_geos, n_items);
   patch_blob(B, tbase);
-  // the copy of the tables is ordered on the stream; the pinned staging copy must not
-  // be overwritten while a previous transfer is pending
-  HIPCHK(hipStreamSynchronize(ctx->stream));
   HIPCHK(ctx->h_tables.ensure(B.blob.h.size() + 64));
   std::memcpy(ctx->h_tables.p, B.blob.h.data(), B.blob.h.size());
   HIPCHK(hipMemcpyAsync(ctx->b_tables.p, ctx->h_tables.p, B.blob.h.size(),
@@ -1012,7 +1086,7 @@ gwchi_status run_build(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int
     rep->alg_flops = P.alg_flops;
     rep->mfma_flops = P.mfma_flops;
     rep->slab_width = P.slab_w;
-    rep->tau_batch = P.jobs_per_pass;
+    rep->tau_batch = P.max_jobs_pass;
     rep->tile_id = P.tile + 1;
     rep->graph_replayed = replayed ? 1 : 0;
     rep->kappa_F_max = -1.0;
@@ -1100,6 +1174,8 @@ gwchi_status upload_items(gwchi_ctx *ctx, const gwchi_item *items, int n_items,
     out_bytes += round_up((int64_t)it.n_omega * it.n_g * it.n_g * 16, 256);
   }
   bool moved = false;
+  if ((size_t)in_bytes > ctx->b_phi.n || (size_t)out_bytes > ctx->b_out.n)
+    HIPCHK(hipStreamSynchronize(ctx->stream));
   HIPCHK(ctx->b_phi.ensure((size_t)in_bytes, &moved));
   HIPCHK(ctx->b_out.ensure((size_t)out_bytes, &moved));
   dev_items.assign(items, items + n_items);

@@ -51,10 +51,17 @@ __global__ __launch_bounds__(256) void k_ct(CtLaunch L, int k0) {
     const int64_t mat = (int64_t)ng * ng;
     double2 acc[2][CH];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i) {
+      const int g = a0 + ty + 16 * i, gp = b0 + tx;
+      const bool in = g < ng && gp < ng;
 #pragma unroll
-      for (int k = 0; k < CH; ++k) acc[i][k] = make_double2(0.0, 0.0);
-    for (int j = 0; j < it.n_tau; ++j) {
+      for (int k = 0; k < CH; ++k)
+        acc[i][k] = (it.accumulate && in && k0 + k < it.n_omega)
+                        ? reinterpret_cast<const double2 *>(it.out)[(int64_t)(k0 + k) * mat +
+                                                                    (int64_t)g * ng + gp]
+                        : make_double2(0.0, 0.0);
+    }
+    for (int j = 0; j < it.n_tau_x; ++j) {
       const int64_t base = (int64_t)j * mat;
       // t1[gp][g] = x_j[b0 + gp][a0 + g]: 16 rows of 32
       for (int q = threadIdx.x; q < 16 * 32; q += 256) {
@@ -85,7 +92,7 @@ __global__ __launch_bounds__(256) void k_ct(CtLaunch L, int k0) {
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
           if (k0 + k < it.n_omega) {
-            const double c = it.coef[(int64_t)(k0 + k) * it.n_tau + j];
+            const double c = it.coef[(int64_t)(k0 + k) * it.n_tau + it.j0 + j];
             acc[i][k].x += c * x.x;
             acc[i][k].y += c * x.y;
           }
@@ -107,21 +114,22 @@ __global__ __launch_bounds__(256) void k_ct(CtLaunch L, int k0) {
   }
 }
 
-// sum of |x|^2 per tau of each item and per omega of each output
+// sum of |x|^2: mode 0 over the taus held in x (with Hermitian completion
+// when set), mode 1 over the omegas of out; one atomic add per block and matrix
 template <typename T>
-__global__ __launch_bounds__(256) void k_norms(CtLaunch L, double *norm_tau, double *norm_omega,
-                                               const int32_t *tau_off, const int32_t *omega_off) {
+__global__ __launch_bounds__(256) void k_norms(CtLaunch L, int mode, double *norm_tau,
+                                               double *norm_omega, const int32_t *tau_off,
+                                               const int32_t *omega_off) {
   __shared__ double red[4];
-  // one block handles a slice of one (item, matrix)
-  const int item = blockIdx.y;
-  const CtItem it = L.items[item];
+  const CtItem it = L.items[blockIdx.y];
   const int64_t mat = (int64_t)it.n_g * it.n_g;
-  const int nm = it.n_tau + it.n_omega;
+  const int nm = mode == 0 ? it.n_tau_x : it.n_omega;
   for (int m = blockIdx.z; m < nm; m += gridDim.z) {
     double s = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < mat; e += (int64_t)gridDim.x * 256) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < mat;
+         e += (int64_t)gridDim.x * 256) {
       double2 x;
-      if (m < it.n_tau) {
+      if (mode == 0) {
         x = ld_x<T>(it.x, (int64_t)m * mat + e);
         if (it.hermitian) {
           const int64_t g = e / it.n_g, gp = e - g * it.n_g;
@@ -130,7 +138,7 @@ __global__ __launch_bounds__(256) void k_norms(CtLaunch L, double *norm_tau, dou
           x.y -= y.y;
         }
       } else {
-        x = reinterpret_cast<const double2 *>(it.out)[(int64_t)(m - it.n_tau) * mat + e];
+        x = reinterpret_cast<const double2 *>(it.out)[(int64_t)m * mat + e];
       }
       s += x.x * x.x + x.y * x.y;
     }
@@ -139,8 +147,8 @@ __global__ __launch_bounds__(256) void k_norms(CtLaunch L, double *norm_tau, dou
     __syncthreads();
     if (threadIdx.x == 0) {
       const double t = red[0] + red[1] + red[2] + red[3];
-      if (m < it.n_tau) atomicAdd(&norm_tau[tau_off[item] + m], t);
-      else atomicAdd(&norm_omega[omega_off[item] + m - it.n_tau], t);
+      if (mode == 0) atomicAdd(&norm_tau[tau_off[it.item] + it.j0 + m], t);
+      else atomicAdd(&norm_omega[omega_off[it.item] + m], t);
     }
     __syncthreads();
   }
@@ -168,12 +176,13 @@ hipError_t launch_ct(const CtLaunch &L, int dbl, int max_omega, hipStream_t s) {
   return hipSuccess;
 }
 
-hipError_t launch_norms_impl(const CtLaunch &L, int dbl, double *nt, double *nw,
+hipError_t launch_norms_impl(const CtLaunch &L, int dbl, int mode, double *nt, double *nw,
                              const int32_t *toff, const int32_t *woff, int max_mats,
                              hipStream_t s) {
+  if (L.n_items <= 0 || max_mats <= 0) return hipSuccess;
   dim3 grid(64, L.n_items, max_mats < 64 ? max_mats : 64);
-  if (dbl) hipLaunchKernelGGL((k_norms<double>), grid, dim3(256), 0, s, L, nt, nw, toff, woff);
-  else hipLaunchKernelGGL((k_norms<float>), grid, dim3(256), 0, s, L, nt, nw, toff, woff);
+  if (dbl) hipLaunchKernelGGL((k_norms<double>), grid, dim3(256), 0, s, L, mode, nt, nw, toff, woff);
+  else hipLaunchKernelGGL((k_norms<float>), grid, dim3(256), 0, s, L, mode, nt, nw, toff, woff);
   return hipGetLastError();
 }
 

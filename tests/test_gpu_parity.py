@@ -176,3 +176,38 @@ def test_config2_full_size_sampled_rows(ctx):
     assert err <= TOL["fp32"]
     herm = np.abs(out - np.conj(np.transpose(out, (0, 2, 1)))).max() / np.abs(out).max()
     assert herm < 1e-5
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_multi_pass_bitwise(ctx, prec):
+    """Jobs split over several passes (an item's taus straddling passes, the
+    cosine transform continuing its sums) give the single-pass result bit for
+    bit, and stay within tolerance of the oracle."""
+    items = [case("cplx8")[0], case("ragged")[0]]
+    ctx.set_options(tau_batch=0, use_graph=1)
+    one = ctx.build(items, prec)
+    ctx.set_options(tau_batch=3)
+    many, rep = ctx.build(items, prec, report=True)
+    ctx.set_options(tau_batch=0)
+    assert rep["tau_batch"] == 3
+    for a, b in zip(one, many):
+        assert np.array_equal(a, b)
+    assert oc.rel_frobenius(many[1], case("ragged")[1]) <= TOL[prec]
+
+
+def test_small_memory_budget(ctx):
+    """A device-memory cap forces narrower slabs and more passes; the result is
+    unchanged.  A cap below one job is reported as ENOMEM."""
+    it, ref = case("ragged")
+    ctx.set_options(max_device_bytes=0)
+    a = ctx.build([it], "fp32")[0]
+    ctx.set_options(max_device_bytes=80 << 20)
+    outs, rep = ctx.build([it], "fp32", report=True)
+    b = outs[0]
+    assert rep["tau_batch"] < it.n_tau
+    assert np.array_equal(a, b)
+    ctx.set_options(max_device_bytes=1 << 20)
+    with pytest.raises(gwchi.GwchiError) as e:
+        ctx.build([it], "fp32")
+    assert e.value.status == 2
+    ctx.set_options(max_device_bytes=0)
