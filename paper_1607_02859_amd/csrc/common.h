@@ -76,6 +76,7 @@ struct GemmLaunch {
   const int4 *units;        // (job, r0, c0, 0)
   int32_t n_units;
   int32_t hermitian;        // 1: units are lower-triangle tiles; mask r >= c
+  int32_t *counter;         // ticket counter, zero before the launch; null: grid stride
 };
 
 // ---------------------------------------------------------------------------
@@ -121,18 +122,19 @@ struct CtItem {
   int32_t hermitian;        // 1: x holds X with chi = X + X^H
   int32_t accumulate;       // 1: continue the sums already in out (taus before j0)
   int32_t item;             // index of the item in the call (norm tables)
-  int32_t tile0;            // first 32x16 output tile of this item in the launch
+  int32_t tile0;            // first output tile of this item in the launch
 };
 
 struct CtLaunch {
   const CtItem *items;
   int32_t n_items;
-  int32_t n_tiles;          // sum over items of the 32x16 output tiles
+  int32_t n_tiles;          // sum over items of the output tiles
 };
 
 // Host-side launch wrappers (defined in the .hip files).
 hipError_t launch_stage(const StageLaunch &L, int prec, hipStream_t s);
-hipError_t launch_gemm(const GemmLaunch &L, int prec, int cplx, int tile, int grid,
+// grid <= 0: persistent (resident blocks x num_cu)
+hipError_t launch_gemm(const GemmLaunch &L, int prec, int cplx, int tile, int grid, int num_cu,
                        hipStream_t s);
 int gemm_tile_count(int prec, int cplx);
 int gemm_tile_bm(int prec, int cplx, int tile);
@@ -148,8 +150,8 @@ hipError_t launch_fft(const FftLaunch &L, int dbl, int sign, int lds_bytes, int 
 constexpr int fft_lds_bytes(int n1, int n2, int cols, int planes, int elem) {
   return planes * n1 * n2 * (cols + 1) * elem;
 }
-// three blocks per CU for FP32, two for FP64
-constexpr int fft_lds_budget(int elem) { return elem <= 8 ? 52 * 1024 : 80 * 1024; }
+// at least two blocks per CU
+constexpr int fft_lds_budget(int elem) { return elem <= 8 ? 64 * 1024 : 80 * 1024; }
 constexpr int fft_cols(int n1, int n2, int elem) {
   int cols = 128 / elem;
   while (cols > 1 && fft_lds_bytes(n1, n2, cols, 1, elem) > fft_lds_budget(elem)) cols /= 2;
@@ -168,7 +170,10 @@ constexpr bool fft_specialised(int n) {
   return n == 12 || n == 16 || n == 18 || n == 20 || n == 24 || n == 28 || n == 32;
 }
 int fft_supported(int n);
-hipError_t launch_ct(const CtLaunch &L, int dbl, int max_omega, hipStream_t s);
+// hermitian = 1: x holds X with chi = X + X^H; 32x32 tiles on or below the
+// block diagonal (T (T + 1) / 2 per item, T = ceil(n_g / 32)), each written
+// with its mirror.  hermitian = 0: 32x16 tiles over the full matrix.
+hipError_t launch_ct(const CtLaunch &L, int dbl, int max_omega, int hermitian, hipStream_t s);
 // mode 0: |chi(tau_j)|_F^2 of the taus held in x; mode 1: |chi(i omega_k)|_F^2 of out
 hipError_t launch_norms_impl(const CtLaunch &L, int dbl, int mode, double *norm_tau,
                              double *norm_omega, const int32_t *tau_off,

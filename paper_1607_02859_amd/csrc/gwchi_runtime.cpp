@@ -117,7 +117,7 @@ struct gwchi_ctx {
   std::string err;
   std::string tune_path;
   std::map<std::string, int> tune;   // key -> tile index
-  DevBuf b_phi, b_out, b_psi, b_slab, b_xr, b_x, b_tmp, b_tables, b_norm;
+  DevBuf b_phi, b_out, b_psi, b_slab, b_xr, b_x, b_tmp, b_tables, b_norm, b_ctr;
   HostPinned h_tables, h_norm;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::vector<hipEvent_t> ev_pool;
@@ -377,7 +377,7 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
     // plane-FFT block shape (same formula as the kernels)
     I.cols = fft_cols(I.n1, I.n2, ec);
     I.planes = fft_planes(I.n0, I.n1, I.n2, ec);
-    I.fft_lds = fft_lds_bytes(I.n1, I.n2, I.cols, I.planes, ec);
+    I.fft_lds = fft_lds_bytes(I.n1, I.n2, I.cols, I.planes, ec) + 4 * I.n_disk;
     I.phi_o = it.phi_occ;
     I.phi_u = it.phi_unocc;
     I.out = it.chi_out;
@@ -502,6 +502,7 @@ struct Blob {
 };
 
 struct Built {
+  int n_gemm = 0;             // GEMM launches (one ticket counter each)
   std::vector<Launch> launches;
   Blob blob;
   std::string key;     // structural signature for the graph cache
@@ -684,11 +685,17 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
       B.launches.push_back(L);
     }
     // ---- per slab: gemm + fft over r
+    // jobs with the most bands first, so that the persistent launch ends evenly
+    std::vector<int> order;
+    for (int q = jb; q < je; ++q) order.push_back(q);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      return P.jobs[a].k_o_eff + P.jobs[a].k_u_eff > P.jobs[b].k_o_eff + P.jobs[b].k_u_eff;
+    });
     for (int s = 0; s < max_slabs; ++s) {
       std::vector<GemmJob> gj;
       std::vector<int4> units;
       std::vector<FftJob> fj;
-      for (int q = jb; q < je; ++q) {
+      for (int q : order) {
         const JobPlan &J = P.jobs[q];
         const ItemPlan &I = P.items[J.item];
         const int64_t s0 = (int64_t)s * P.slab_w;
@@ -744,7 +751,14 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
       G.gemm.units = reinterpret_cast<const int4 *>(B.blob.addv(units));
       G.gemm.n_units = (int)units.size();
       G.gemm.hermitian = ctx->opt.hermitian;
-      G.gemm_grid = (int)units.size();
+      if (ctx->opt.persistent) {
+        G.gemm.counter = reinterpret_cast<int32_t *>(ctx->b_ctr.p) + B.n_gemm;
+        G.gemm_grid = 0;
+      } else {
+        G.gemm.counter = nullptr;
+        G.gemm_grid = (int)units.size();
+      }
+      ++B.n_gemm;
       B.launches.push_back(G);
       emit_fft(B, P, fj, PH_FFT_R, -1, cplx ? 0 : 1, ctx->opt.hermitian, off_geos);
     }
@@ -793,7 +807,8 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
         c.accumulate = c.j0 > 0 ? 1 : 0;
         c.item = t;
         c.tile0 = tiles;
-        tiles += ((I.n_g + 31) / 32) * ((I.n_g + 15) / 16);
+        const int tt = (I.n_g + 31) / 32;
+        tiles += ctx->opt.hermitian ? tt * (tt + 1) / 2 : tt * ((I.n_g + 15) / 16);
         max_omega = std::max(max_omega, I.n_omega);
         max_mats = std::max(max_mats, je2 - jj);
         cts.push_back(c);
@@ -846,6 +861,17 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
     N.woff = reinterpret_cast<const int32_t *>(off_woff);
     B.launches.push_back(N);
   }
+  // ticket counters of the persistent GEMM launches start at zero every build
+  // (a fill kernel, which a captured graph replays correctly)
+  if (B.n_gemm > 0 && ctx->opt.persistent) {
+    Launch Z{};
+    Z.phase = PH_STAGE;
+    Z.kind = 5;
+    Z.fill_ptr = ctx->b_ctr.p;
+    Z.fill_bytes = (int64_t)B.n_gemm * 4;
+    B.launches.insert(B.launches.begin(), Z);
+  }
+  key << "|persistent=" << ctx->opt.persistent;
   B.key = key.str();
 }
 
@@ -933,13 +959,13 @@ gwchi_status enqueue(gwchi_ctx *ctx, const Plan &P, Built &B, bool timing,
         HIPCHK(launch_stage(L.stage, P.prec, s));
         break;
       case 1:
-        HIPCHK(launch_gemm(L.gemm, P.prec, cplx, P.tile, L.gemm_grid, s));
+        HIPCHK(launch_gemm(L.gemm, P.prec, cplx, P.tile, L.gemm_grid, ctx->num_cu, s));
         break;
       case 2:
         HIPCHK(launch_fft(L.fft, dbl, L.fft_sign, L.fft_lds, L.fft_cubic, s));
         break;
       case 3:
-        HIPCHK(launch_ct(L.ct, dbl, L.max_omega, s));
+        HIPCHK(launch_ct(L.ct, dbl, L.max_omega, ctx->opt.hermitian, s));
         break;
       case 4:
         HIPCHK(launch_norms_impl(L.ct, dbl, L.norm_mode, reinterpret_cast<double *>(ctx->b_norm.p),
@@ -982,6 +1008,12 @@ gwchi_status run_build(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int
   int n_norm = 0;
   for (auto &I : P.items) n_norm += I.n_tau + I.n_omega;
   HIPCHK(ctx->b_norm.ensure((size_t)n_norm * 8 + 64, &moved));
+  {
+    int max_slabs = 0;
+    for (auto &I : P.items) max_slabs = std::max<int>(max_slabs, (int)((I.n_r + P.slab_w - 1) / P.slab_w));
+    const size_t n_ctr = (size_t)((int)P.pass_begin.size() - 1) * max_slabs + 16;
+    HIPCHK(ctx->b_ctr.ensure(n_ctr * 4, &moved));
+  }
   Built B;
   build_launches(ctx, P, want_norms, B);
   // geos offset: locate it as the table referenced by the first FFT launch
@@ -1254,6 +1286,7 @@ gwchi_status gwchi_create(gwchi_ctx **out, int32_t device_id, const char *tune_c
     }
     ctx->opt.use_graph = 1;
     ctx->opt.hermitian = 1;
+    ctx->opt.persistent = 1;
     ctx->opt.kappa = 1;
     if (tune_cache_path) ctx->tune_path = tune_cache_path;
     load_tune(ctx.get());
@@ -1275,7 +1308,7 @@ gwchi_status gwchi_destroy(gwchi_ctx *ctx) {
   if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
   if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
   for (DevBuf *b : {&ctx->b_phi, &ctx->b_out, &ctx->b_psi, &ctx->b_slab, &ctx->b_xr, &ctx->b_x,
-                    &ctx->b_tmp, &ctx->b_tables, &ctx->b_norm})
+                    &ctx->b_tmp, &ctx->b_tables, &ctx->b_norm, &ctx->b_ctr})
     b->release();
   ctx->h_tables.release();
   ctx->h_norm.release();

@@ -7,6 +7,8 @@
 // weights.  Inputs are read in the working precision and every product and
 // sum is FP64; each output element sums j in increasing order.  With
 // Hermitian completion the stored matrix is X and chi = X + X^H.
+#include <type_traits>
+
 #include "common.h"
 
 namespace gw {
@@ -114,6 +116,115 @@ __global__ __launch_bounds__(256) void k_ct(CtLaunch L, int k0) {
   }
 }
 
+// Hermitian completion: chi(i w_k) is Hermitian and out(b, a) = conj(out(a, b))^T
+// holds exactly (the same sums with conjugated terms), so one block computes a
+// 32x32 tile on or below the block diagonal and writes it and its mirror.
+// 512 threads: thread (tx, ty) owns (a0 + ty + 16 i, b0 + tx), i = 0, 1, for
+// CH frequencies.  The next tau's two input tiles are fetched into registers
+// while the current ones are used from LDS.
+template <typename T, int CH>
+__global__ __launch_bounds__(512) void k_ct_herm(CtLaunch L, int k0) {
+  __shared__ double2 t1[32][33];     // t1[gp][g] = x_j[b0 + gp][a0 + g] = X[g][g']
+  __shared__ double2 t2[32][33];     // t2[g][gp] = x_j[a0 + g][b0 + gp] = X[g'][g]
+  const int tid = threadIdx.x;
+  const int tx = tid & 31, ty = tid >> 5;    // ty in [0, 16)
+  typedef typename std::conditional<sizeof(T) == 8, double2, float2>::type V;
+  for (int t = blockIdx.x; t < L.n_tiles; t += gridDim.x) {
+    const CtItem it = L.items[find_tile(L.items, L.n_items, t)];
+    if (k0 >= it.n_omega) continue;
+    const int ng = it.n_g;
+    const int lt = t - it.tile0;
+    // lower-triangle tile index lt = ta (ta + 1) / 2 + tb, tb <= ta
+    int ta = (int)((sqrt(8.0 * lt + 1.0) - 1.0) * 0.5);
+    while ((ta + 1) * (ta + 2) / 2 <= lt) ++ta;
+    while (ta * (ta + 1) / 2 > lt) --ta;
+    const int tb = lt - ta * (ta + 1) / 2;
+    const int a0 = ta * 32, b0 = tb * 32;
+    const int64_t mat = (int64_t)ng * ng;
+    const V *x = reinterpret_cast<const V *>(it.x);
+    double2 acc[2][CH];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int g = a0 + ty + 16 * i, gp = b0 + tx;
+      const bool in = g < ng && gp < ng;
+#pragma unroll
+      for (int k = 0; k < CH; ++k)
+        acc[i][k] = (it.accumulate && in && k0 + k < it.n_omega)
+                        ? reinterpret_cast<const double2 *>(it.out)[(int64_t)(k0 + k) * mat +
+                                                                    (int64_t)g * ng + gp]
+                        : make_double2(0.0, 0.0);
+    }
+    // element q of a 32x32 tile: row q >> 5, column q & 31
+    V r1[2], r2[2];
+    auto fetch = [&](int j) {
+      const int64_t base = (int64_t)j * mat;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int e = tid + 512 * q, row = e >> 5, col = e & 31;
+        const int g1 = a0 + col, gp1 = b0 + row;     // t1: x_j[gp][g]
+        r1[q] = (g1 < ng && gp1 < ng) ? x[base + (int64_t)gp1 * ng + g1] : V{0, 0};
+        const int g2 = a0 + row, gp2 = b0 + col;     // t2: x_j[g][gp]
+        r2[q] = (g2 < ng && gp2 < ng) ? x[base + (int64_t)g2 * ng + gp2] : V{0, 0};
+      }
+    };
+    if (it.n_tau_x > 0) fetch(0);
+    for (int j = 0; j < it.n_tau_x; ++j) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int e = tid + 512 * q, row = e >> 5, col = e & 31;
+        t1[row][col] = make_double2((double)r1[q].x, (double)r1[q].y);
+        t2[row][col] = make_double2((double)r2[q].x, (double)r2[q].y);
+      }
+      __syncthreads();
+      if (j + 1 < it.n_tau_x) fetch(j + 1);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int gl = ty + 16 * i;
+        const double2 u = t1[tx][gl], w = t2[gl][tx];
+        const double xr = u.x + w.x, xi = u.y - w.y;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          if (k0 + k < it.n_omega) {
+            const double c = it.coef[(int64_t)(k0 + k) * it.n_tau + it.j0 + j];
+            acc[i][k].x += c * xr;
+            acc[i][k].y += c * xi;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    double2 *out = reinterpret_cast<double2 *>(it.out);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int g = a0 + ty + 16 * i, gp = b0 + tx;
+      if (g < ng && gp < ng) {
+#pragma unroll
+        for (int k = 0; k < CH; ++k)
+          if (k0 + k < it.n_omega) out[(int64_t)(k0 + k) * mat + (int64_t)g * ng + gp] = acc[i][k];
+      }
+    }
+    if (ta != tb) {
+      // mirror tile out[k][b0 + .][a0 + .] = conj(acc)^T, transposed through LDS
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        if (k0 + k >= it.n_omega) break;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) t1[ty + 16 * i][tx] = acc[i][k];   // [g_l][gp_l]
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int gpl = ty + 16 * i;
+          const int g = a0 + tx, gp = b0 + gpl;
+          const double2 v = t1[tx][gpl];
+          if (g < ng && gp < ng)
+            out[(int64_t)(k0 + k) * mat + (int64_t)gp * ng + g] = make_double2(v.x, -v.y);
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
 // sum of |x|^2: mode 0 over the taus held in x (with Hermitian completion
 // when set), mode 1 over the omegas of out; one atomic add per block and matrix
 template <typename T>
@@ -161,10 +272,30 @@ __global__ __launch_bounds__(256) void k_fill_zero(uint4 *p, int64_t n16, char *
   if (blockIdx.x == 0 && (int)threadIdx.x < tail_n) tail[threadIdx.x] = 0;
 }
 
+template <typename T>
+hipError_t launch_ct_herm(const CtLaunch &L, int max_omega, hipStream_t s) {
+  const int grid = L.n_tiles < 65536 ? L.n_tiles : 65536;
+  int k0 = 0;
+  while (k0 < max_omega) {
+    const int left = max_omega - k0;
+    if (left <= 4) hipLaunchKernelGGL((k_ct_herm<T, 4>), dim3(grid), dim3(512), 0, s, L, k0);
+    else if (left <= 8) hipLaunchKernelGGL((k_ct_herm<T, 8>), dim3(grid), dim3(512), 0, s, L, k0);
+    else if (left <= 12) hipLaunchKernelGGL((k_ct_herm<T, 12>), dim3(grid), dim3(512), 0, s, L, k0);
+    else if (left <= 16) hipLaunchKernelGGL((k_ct_herm<T, 16>), dim3(grid), dim3(512), 0, s, L, k0);
+    else hipLaunchKernelGGL((k_ct_herm<T, 20>), dim3(grid), dim3(512), 0, s, L, k0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k0 += left <= 4 ? 4 : left <= 8 ? 8 : left <= 12 ? 12 : left <= 16 ? 16 : 20;
+  }
+  return hipSuccess;
+}
+
 }  // namespace
 
-hipError_t launch_ct(const CtLaunch &L, int dbl, int max_omega, hipStream_t s) {
+hipError_t launch_ct(const CtLaunch &L, int dbl, int max_omega, int hermitian, hipStream_t s) {
   if (L.n_tiles <= 0) return hipSuccess;
+  if (hermitian) return dbl ? launch_ct_herm<double>(L, max_omega, s)
+                            : launch_ct_herm<float>(L, max_omega, s);
   const int grid = L.n_tiles < 65536 ? L.n_tiles : 65536;
   constexpr int CH = 16;
   for (int k0 = 0; k0 < max_omega; k0 += CH) {

@@ -216,42 +216,71 @@ __global__ __launch_bounds__(256) void k_fft_planes(FftLaunch L) {
     const int cg = lu / npg, pg = lu - cg * npg;
     const int c0 = cg * C, p0 = pg * P;
     const int np = min(P, n0 - p0);
+    // lower-triangle storage: a block whose planes all lie above the first
+    // stored row of its first column is zero; it is skipped and the pencil
+    // pass reads those planes as zero (same test there)
+    if (L.lower_only && (int64_t)(p0 + np) * plane <= (int64_t)J.col0 + c0) continue;
+    // the sphere's pencil table, kept in LDS for the gather
+    int *s_i12 = reinterpret_cast<int *>(smem + fft_lds_bytes(n1, n2, C, P, EC));
+    for (int d = tid; d < D; d += 256) s_i12[d] = G.disk_i12[d];
     // load np planes of C columns
     const int total = np * plane * C;
-    if (J.s_col == 0) {
-      // column-grouped input: the block's C columns over these planes are one
-      // contiguous run, element (rl, cc) at ((cg * n_r) + r) * C + cc
-      const int64_t gbase = (int64_t)cg * (n0 * plane) * C;
-      for (int idx = tid; idx < total; idx += 256) {
-        const int cc = idx % C, rl = idx / C;
-        const int c = c0 + cc;
-        const int64_t r = (int64_t)p0 * plane + rl;
-        cx<T> v = {(T)0, (T)0};
-        if (c < J.n_cols && !(L.lower_only && r < J.col0 + c)) {
-          const int64_t e = gbase + r * C + cc;
-          if (L.in_real) v.x = reinterpret_cast<const T *>(J.in)[e];
-          else v = reinterpret_cast<const cx<T> *>(J.in)[e];
+    // element idx of the block -> (global offset or -1, LDS index)
+    auto locate = [&](int idx, int64_t &e, int &li) {
+      int cc, rl;
+      if (J.s_col == 0) {       // column-grouped input: one contiguous run
+        cc = idx % C;
+        rl = idx / C;
+      } else {                  // each column contiguous in r
+        const int span = np * plane;
+        cc = idx / span;
+        rl = idx - cc * span;
+      }
+      const int c = c0 + cc;
+      const int64_t r = (int64_t)p0 * plane + rl;
+      e = -1;
+      if (idx < total && c < J.n_cols && !(L.lower_only && r < J.col0 + c))
+        e = J.s_col == 0 ? (int64_t)cg * (n0 * plane) * C + r * C + cc
+                         : r * J.s_r + (int64_t)c * J.s_col;
+      const int p = rl / plane, q = rl - p * plane;
+      const int i1 = q / n2, i2 = q - i1 * n2;
+      li = lds_idx(p, i1, i2, cc, n1, n2, C);
+    };
+    auto fetch = [&](int64_t e) -> cx<T> {
+      cx<T> v = {(T)0, (T)0};
+      if (e >= 0) {
+        if (L.in_real) v.x = reinterpret_cast<const T *>(J.in)[e];
+        else v = reinterpret_cast<const cx<T> *>(J.in)[e];
+      }
+      return v;
+    };
+    if constexpr (NC > 0) {
+      // every global load of the block is issued before the first LDS store
+      constexpr int NL = (fft_planes(NC, NC, NC, EC) * NC * NC * fft_cols(NC, NC, EC) + 255) / 256;
+      cx<T> v[NL];
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        int64_t e;
+        int li;
+        locate(tid + 256 * i, e, li);
+        v[i] = fetch(e);
+      }
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        const int idx = tid + 256 * i;
+        if (idx < total) {
+          int64_t e;
+          int li;
+          locate(idx, e, li);
+          buf[li] = v[i];
         }
-        const int p = rl / plane, q = rl - p * plane;
-        const int i1 = q / n2, i2 = q - i1 * n2;
-        buf[lds_idx(p, i1, i2, cc, n1, n2, C)] = v;
       }
     } else {
-      // each column contiguous in r: rl fastest
-      const int span = np * plane;
       for (int idx = tid; idx < total; idx += 256) {
-        const int cc = idx / span, rl = idx - cc * span;
-        const int c = c0 + cc;
-        const int64_t r = (int64_t)p0 * plane + rl;
-        cx<T> v = {(T)0, (T)0};
-        if (c < J.n_cols && !(L.lower_only && r < J.col0 + c)) {
-          const int64_t e = r * J.s_r + (int64_t)c * J.s_col;
-          if (L.in_real) v.x = reinterpret_cast<const T *>(J.in)[e];
-          else v = reinterpret_cast<const cx<T> *>(J.in)[e];
-        }
-        const int p = rl / plane, q = rl - p * plane;
-        const int i1 = q / n2, i2 = q - i1 * n2;
-        buf[lds_idx(p, i1, i2, cc, n1, n2, C)] = v;
+        int64_t e;
+        int li;
+        locate(idx, e, li);
+        buf[li] = fetch(e);
       }
     }
     __syncthreads();
@@ -276,7 +305,7 @@ __global__ __launch_bounds__(256) void k_fft_planes(FftLaunch L) {
       const int p = rest / D, d = rest - p * D;
       const int c = c0 + cc;
       if (c < J.n_cols) {
-        const int i12 = G.disk_i12[d];
+        const int i12 = s_i12[d];
         const int i1 = i12 / n2, i2 = i12 - i1 * n2;
         tmp[((int64_t)(p0 + p) * D + d) * J.n_cols + c] = buf[lds_idx(p, i1, i2, cc, n1, n2, C)];
       }
@@ -286,11 +315,19 @@ __global__ __launch_bounds__(256) void k_fft_planes(FftLaunch L) {
 }
 
 template <int N, int SIGN, typename T>
-__device__ __forceinline__ void pencil_n(const FftJob &J, const Geo &G, int d, int c) {
+__device__ __forceinline__ void pencil_n(const FftJob &J, const Geo &G, int d, int c,
+                                         int lower_only) {
   const cx<T> *tmp = reinterpret_cast<const cx<T> *>(J.tmp);
+  // planes whose plane-FFT block was skipped as all-zero (see k_fft_planes)
+  const int64_t plane = (int64_t)G.n1 * G.n2;
+  const int64_t zlim = lower_only ? (int64_t)J.col0 + (c / G.cols) * G.cols : -1;
   cx<T> v[N], o[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) v[i] = tmp[((int64_t)i * G.n_disk + d) * J.n_cols + c];
+  for (int i = 0; i < N; ++i) {
+    const int hi = min(N, (i / G.planes + 1) * G.planes);
+    v[i] = (hi * plane <= zlim) ? cx<T>{(T)0, (T)0}
+                                : tmp[((int64_t)i * G.n_disk + d) * J.n_cols + c];
+  }
   reg_fft<N, SIGN, T, 1>(v, o);
   cx<T> *out = reinterpret_cast<cx<T> *>(J.out) + (int64_t)(J.col0 + c) * J.o_col;
   const int32_t *so = G.slot_of + (int64_t)d * N;
@@ -312,12 +349,12 @@ __global__ __launch_bounds__(256) void k_fft_pencils(FftLaunch L) {
     const int c = ch * 256 + threadIdx.x;
     if (c >= J.n_cols) continue;
     if constexpr (NC > 0) {
-      pencil_n<NC, SIGN, T>(J, G, d, c);
+      pencil_n<NC, SIGN, T>(J, G, d, c, L.lower_only);
     } else {
       switch (G.n0) {
 #define GW_PEN(N)                             \
   case N:                                     \
-    pencil_n<N, SIGN, T>(J, G, d, c);         \
+    pencil_n<N, SIGN, T>(J, G, d, c, L.lower_only); \
     break;
         GW_FFT_SIZES(GW_PEN)
 #undef GW_PEN

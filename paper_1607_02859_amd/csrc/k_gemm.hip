@@ -21,7 +21,9 @@
 // A workgroup is 4 waves in a 2x2 arrangement; each wave owns WTM x WTN
 // MFMA blocks.  Operand chunks of KC bands are staged through LDS with a
 // double buffer; the next chunk is fetched into registers while the current
-// one feeds the MFMAs.  Workgroups loop over the unit list (grid stride).
+// one feeds the MFMAs.  The launch is persistent: as many workgroups as are
+// resident take units from the list with an atomic ticket (list ordered with
+// the most bands first), or, without a ticket counter, by grid stride.
 #include <type_traits>
 
 #include "common.h"
@@ -333,11 +335,22 @@ struct Gemm {
     }
   }
 
+  // next unit: an atomic ticket (persistent grid) or the grid stride
+  static __device__ __forceinline__ int next_unit(const GemmLaunch &L, int prev, int *s_u) {
+    if (L.counter == nullptr) return prev < 0 ? (int)blockIdx.x : prev + (int)gridDim.x;
+    if (threadIdx.x == 0) *s_u = atomicAdd(L.counter, 1);
+    __syncthreads();
+    const int u = *s_u;
+    __syncthreads();
+    return u;
+  }
+
   static __device__ __forceinline__ void run(const GemmLaunch &L, char *lds) {
+    __shared__ int s_u;
     const int w = threadIdx.x >> 6;
     const int l = threadIdx.x & 63;
     const int wr = w >> 1, wc = w & 1;
-    for (int u = blockIdx.x; u < L.n_units; u += gridDim.x) {
+    for (int u = next_unit(L, -1, &s_u); u < L.n_units; u = next_unit(L, u, &s_u)) {
       const int4 unit = L.units[u];
       const GemmJob job = L.jobs[unit.x];
       const int r0 = unit.y, c0 = unit.z;
@@ -407,18 +420,24 @@ struct TileCfg {
 };
 
 // Tile menus per (precision, complex).  Index 0 is the default.
+// grid <= 0: persistent launch sized to the resident blocks of the device
 template <int P, bool C, int WTM, int WTN, int KC>
-hipError_t launch_one(const GemmLaunch &L, int grid, hipStream_t s) {
+hipError_t launch_one(const GemmLaunch &L, int grid, int num_cu, hipStream_t s) {
   typedef Tile<P, C, WTM, WTN, KC> T;
   const int lds = 2 * T::BUF;
   auto kern = k_gemm<P, C, WTM, WTN, KC>;
   static bool attr = false;
+  static int per_cu = 0;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
     attr = true;
   }
+  if (grid <= 0) grid = per_cu * num_cu;
+  if (grid > L.n_units) grid = L.n_units;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, s, L);
   return hipGetLastError();
 }
@@ -494,13 +513,13 @@ const char *gemm_tile_name(int prec, int cplx, int tile) {
   return (c && tile >= 0 && tile < n) ? c[tile].name : "?";
 }
 
-hipError_t launch_gemm(const GemmLaunch &L, int prec, int cplx, int tile, int grid,
+hipError_t launch_gemm(const GemmLaunch &L, int prec, int cplx, int tile, int grid, int num_cu,
                        hipStream_t s) {
   if (L.n_units <= 0) return hipSuccess;
   int idx = 0;
 #define GW_TRY(P, C, A, B, K)                                        \
   if (prec == P && (cplx != 0) == C) {                               \
-    if (idx == tile) return launch_one<P, C, A, B, K>(L, grid, s);   \
+    if (idx == tile) return launch_one<P, C, A, B, K>(L, grid, num_cu, s); \
     ++idx;                                                           \
   }
   GW_TILES_FP64_C(GW_TRY)

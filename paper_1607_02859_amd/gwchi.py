@@ -78,6 +78,7 @@ class GwchiOptions(C.Structure):
         ("timing", C.c_int32),
         ("skip_zero_bands", C.c_int32),
         ("hermitian", C.c_int32),
+        ("persistent", C.c_int32),
         ("kappa", C.c_int32),
         ("max_device_bytes", C.c_int64),
     ]

@@ -211,3 +211,34 @@ def test_small_memory_budget(ctx):
         ctx.build([it], "fp32")
     assert e.value.status == 2
     ctx.set_options(max_device_bytes=0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_persistent_matches_one_block_per_tile(ctx, prec):
+    """The persistent ticketed launch computes every tile exactly as a launch
+    with one workgroup per tile."""
+    items = [case("cplx8")[0], case("ragged")[0]]
+    ctx.set_options(persistent=1)
+    a = ctx.build(items, prec)
+    ctx.set_options(persistent=0)
+    b = ctx.build(items, prec)
+    ctx.set_options(persistent=1)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_autotune_writes_and_uses_cache(tmp_path):
+    import json
+    path = str(tmp_path / "tune.json")
+    it, ref = case("ragged")
+    c = gwchi.Context(0, tune_cache=path)
+    c.autotune([it], "fp32")
+    c.close()
+    data = json.load(open(path))
+    say(f"[autotune] {data}")
+    assert 0 <= data["fp32/c"] < 3
+    c2 = gwchi.Context(0, tune_cache=path)
+    out, rep = c2.build([it], "fp32", report=True)
+    c2.close()
+    assert rep["tile_id"] == data["fp32/c"] + 1
+    assert oc.rel_frobenius(out[0], ref) <= TOL["fp32"]
