@@ -49,6 +49,31 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_gemm_gamma_complex_24cubed_hbm_traffic.md")
+
+
+def gemm_traffic(kernel_prefix: str):
+    """HBM bytes per launch of the band-GEMM kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by its
+    reading for a plain copy of known size), or None when that summary was
+    taken on a different k_gemm.hip than the one built here."""
+    import hashlib
+    import re
+    try:
+        txt = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"k_gemm.hip sha256 when measured: `([0-9a-f]+)`", txt)
+    src = os.path.join(ROOT, "paper_1607_02859_amd", "csrc", "k_gemm.hip")
+    if not m or hashlib.sha256(open(src, "rb").read()).hexdigest() != m.group(1):
+        return None
+    for line in txt.splitlines():
+        if line.startswith("| `" + kernel_prefix):
+            cols = [c.strip() for c in line.strip("|").split("|")]
+            return (float(cols[4]) + float(cols[5])) * 1e9
+    return None
+
+
 def cpu_baseline(item, n_tau_sample: int = 1):
     """The oracle (unchanged) on a bounded sample: n_tau_sample tau points of
     the same item through the full space-time path, FP64 on the host."""
@@ -80,6 +105,9 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
     ap.add_argument("--hermitian", type=int, default=1)
     ap.add_argument("--skip-zero-bands", type=int, default=0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="before timing, copy MIB mebibytes device-to-device once (a plain copy "
+                         "of known size against which HBM byte counters are scaled)")
     ap.add_argument("--config", type=int, default=2,
                     help="workload configuration (2 is the headline; 1, 3, 4, 5 for the record)")
     args = ap.parse_args()
@@ -100,6 +128,14 @@ def main():
             for it in items]
     outs = [torch.empty((it.n_omega, it.n_g, it.n_g), dtype=torch.complex128, device=dev)
             for it in items]
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy << 20
+        a = torch.empty(n, dtype=torch.uint8, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     ctx = gwchi.Context(0)
     ctx.set_options(use_graph=1, timing=1, slab_width=2048, hermitian=args.hermitian,
                     skip_zero_bands=args.skip_zero_bands, kappa=0)
@@ -208,7 +244,9 @@ def main():
         "peak": PEAK_TFLOPS[head],
         "unit": "TFLOP/s",
         "frac": achieved / PEAK_TFLOPS[head],
-        "traffic": None,
+        "traffic": gemm_traffic("void k_gemm<1, true,") if (head == "fp32" and args.config == 2)
+        else None,
+        "traffic_source": os.path.relpath(TRAFFIC_PROFILE, ROOT),
         "per_launch_flops": per_launch,
         "avg_launch_ms": H["gemm_ms_per_launch"],
         "launches_per_step": H["gemm_launches_per_step"],
