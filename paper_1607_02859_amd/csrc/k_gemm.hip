@@ -98,25 +98,26 @@ __device__ __forceinline__ uint4 neg_bf8(uint4 q) {
   return q;
 }
 
-template <int P, bool C, int WTM, int WTN, int KC>
+template <int P, bool C, int WTM, int WTN, int KC, int WM>
 struct Tile {
   typedef MM<P, C> M;
-  static constexpr int BM = 2 * WTM * M::MB;
+  static constexpr int NT = 128 * WM;            // threads: WM x 2 waves
+  static constexpr int BM = WM * WTM * M::MB;
   static constexpr int BN = 2 * WTN * M::MB;
   static constexpr int ROWB = KC * M::BPB;        // bytes per operand row per chunk
   static constexpr int R16 = ROWB / 16;           // 16-B vectors per row
   static constexpr int PITCH = ROWB + 16;         // LDS row pitch (padding vs bank conflicts)
   static constexpr int NV = (BM + BN) * R16;      // vectors per chunk
-  static constexpr int VPT = (NV + 255) / 256;    // vectors per thread
+  static constexpr int VPT = (NV + NT - 1) / NT;  // vectors per thread
   static constexpr int BUF = (BM + BN) * PITCH;   // bytes per LDS buffer
   static_assert(ROWB % 16 == 0, "row chunk must be 16-B aligned");
   static_assert(KC % M::KS == 0, "chunk must hold whole MFMA steps");
 };
 
-template <int P, bool C, int WTM, int WTN, int KC>
+template <int P, bool C, int WTM, int WTN, int KC, int WM>
 struct Gemm {
   typedef MM<P, C> M;
-  typedef Tile<P, C, WTM, WTN, KC> T;
+  typedef Tile<P, C, WTM, WTN, KC, WM> T;
   typedef typename M::acc_t acc_t;
 
   struct Acc {
@@ -147,8 +148,8 @@ struct Gemm {
     const int tid = threadIdx.x;
     sfor<0, T::VPT>([&](auto tt) {
       constexpr int t = decltype(tt)::value;
-      const int v = tid + t * 256;
-      if (T::NV % 256 == 0 || v < T::NV) {
+      const int v = tid + t * T::NT;
+      if (T::NV % T::NT == 0 || v < T::NV) {
         const int row = v / T::R16, q = v % T::R16;
         const int grow = row < T::BM ? r0 + row : c0 + (row - T::BM);
         const char *p = base + (int64_t)grow * pitchB + (int64_t)kc0 * M::BPB + q * 16;
@@ -165,8 +166,8 @@ struct Gemm {
     const int tid = threadIdx.x;
     sfor<0, T::VPT>([&](auto tt) {
       constexpr int t = decltype(tt)::value;
-      const int v = tid + t * 256;
-      if (T::NV % 256 == 0 || v < T::NV) {
+      const int v = tid + t * T::NT;
+      if (T::NV % T::NT == 0 || v < T::NV) {
         const int row = v / T::R16, q = v % T::R16;
         *reinterpret_cast<uint4 *>(buf + row * T::PITCH + q * 16) =
             make_uint4(reg.v[4 * t + 0], reg.v[4 * t + 1], reg.v[4 * t + 2], reg.v[4 * t + 3]);
@@ -349,7 +350,7 @@ struct Gemm {
     __shared__ int s_u;
     const int w = threadIdx.x >> 6;
     const int l = threadIdx.x & 63;
-    const int wr = w >> 1, wc = w & 1;
+    const int wr = w >> 1, wc = w & 1;     // WM rows x 2 columns of waves
     for (int u = next_unit(L, -1, &s_u); u < L.n_units; u = next_unit(L, u, &s_u)) {
       const int4 unit = L.units[u];
       const GemmJob job = L.jobs[unit.x];
@@ -408,49 +409,65 @@ struct Gemm {
   }
 };
 
-template <int P, bool C, int WTM, int WTN, int KC>
-__global__ __launch_bounds__(256) void k_gemm(GemmLaunch L) {
+// OCC: workgroups per CU the register allocation must allow; WM: rows of waves
+template <int P, bool C, int WTM, int WTN, int KC, int OCC, int WM>
+__global__ __launch_bounds__(128 * WM, OCC) void k_gemm(GemmLaunch L) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  Gemm<P, C, WTM, WTN, KC>::run(L, lds);
+  Gemm<P, C, WTM, WTN, KC, WM>::run(L, lds);
 }
 
 struct TileCfg {
-  int wtm, wtn, kc;
+  int wtm, wtn, kc, wm;
   const char *name;
 };
 
 // Tile menus per (precision, complex).  Index 0 is the default.
 // grid <= 0: persistent launch sized to the resident blocks of the device
-template <int P, bool C, int WTM, int WTN, int KC>
+template <int P, bool C, int WTM, int WTN, int KC, int OCC, int WM>
 hipError_t launch_one(const GemmLaunch &L, int grid, int num_cu, hipStream_t s) {
-  typedef Tile<P, C, WTM, WTN, KC> T;
+  typedef Tile<P, C, WTM, WTN, KC, WM> T;
   const int lds = 2 * T::BUF;
-  auto kern = k_gemm<P, C, WTM, WTN, KC>;
+  auto kern = k_gemm<P, C, WTM, WTN, KC, OCC, WM>;
   static bool attr = false;
   static int per_cu = 0;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, T::NT, lds);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     attr = true;
   }
   if (grid <= 0) grid = per_cu * num_cu;
   if (grid > L.n_units) grid = L.n_units;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, s, L);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(T::NT), lds, s, L);
   return hipGetLastError();
 }
 
-#define GW_TILES_FP64_C(X) X(P_FP64, true, 2, 2, 16) X(P_FP64, true, 1, 2, 16) X(P_FP64, true, 2, 2, 8)
-#define GW_TILES_FP64_R(X) X(P_FP64, false, 2, 2, 32) X(P_FP64, false, 2, 4, 16) X(P_FP64, false, 4, 4, 16)
-#define GW_TILES_FP32_C(X) X(P_FP32, true, 1, 2, 16) X(P_FP32, true, 2, 2, 16) X(P_FP32, true, 1, 1, 32)
-#define GW_TILES_FP32_R(X) X(P_FP32, false, 2, 2, 32) X(P_FP32, false, 1, 2, 32) X(P_FP32, false, 2, 2, 16)
-#define GW_TILES_BF16_C(X) X(P_BF16X3, true, 2, 2, 16) X(P_BF16X3, true, 1, 2, 32) X(P_BF16X3, true, 2, 1, 32)
-#define GW_TILES_BF16_R(X) X(P_BF16X3, false, 2, 2, 32) X(P_BF16X3, false, 2, 4, 32) X(P_BF16X3, false, 1, 2, 32)
+// (precision, complex, wave tile M, wave tile N, K chunk, workgroups per CU,
+// rows of waves); entry 0 is the default.  Defaults come from timing every
+// entry on the 24^3 complex and the 24^3 real workloads.
+#define GW_TILES_FP64_C(X)                                                                     \
+  X(P_FP64, true, 2, 2, 16, 2, 2) X(P_FP64, true, 1, 2, 16, 1, 4) X(P_FP64, true, 1, 2, 16, 2, 2) \
+  X(P_FP64, true, 2, 1, 16, 2, 2) X(P_FP64, true, 2, 2, 8, 2, 2) X(P_FP64, true, 1, 1, 16, 2, 4)
+#define GW_TILES_FP64_R(X)                                                                     \
+  X(P_FP64, false, 2, 2, 16, 1, 4) X(P_FP64, false, 2, 2, 16, 3, 2) X(P_FP64, false, 2, 2, 32, 2, 2) \
+  X(P_FP64, false, 4, 2, 16, 2, 2) X(P_FP64, false, 2, 4, 16, 1, 2) X(P_FP64, false, 1, 2, 32, 2, 4)
+#define GW_TILES_FP32_C(X)                                                                     \
+  X(P_FP32, true, 1, 2, 16, 1, 4) X(P_FP32, true, 2, 1, 16, 2, 2) X(P_FP32, true, 1, 2, 16, 2, 2) \
+  X(P_FP32, true, 1, 2, 32, 1, 4) X(P_FP32, true, 2, 2, 16, 1, 2) X(P_FP32, true, 1, 1, 32, 2, 4)
+#define GW_TILES_FP32_R(X)                                                                     \
+  X(P_FP32, false, 2, 2, 16, 2, 2) X(P_FP32, false, 2, 2, 32, 2, 2) X(P_FP32, false, 2, 2, 16, 1, 4) \
+  X(P_FP32, false, 1, 2, 32, 3, 2) X(P_FP32, false, 2, 4, 16, 1, 2) X(P_FP32, false, 1, 2, 32, 2, 4)
+#define GW_TILES_BF16_C(X)                                                                     \
+  X(P_BF16X3, true, 1, 2, 16, 1, 4) X(P_BF16X3, true, 2, 2, 16, 1, 2) X(P_BF16X3, true, 1, 2, 32, 1, 4) \
+  X(P_BF16X3, true, 1, 2, 16, 2, 2) X(P_BF16X3, true, 2, 1, 16, 2, 2) X(P_BF16X3, true, 1, 1, 32, 2, 4)
+#define GW_TILES_BF16_R(X)                                                                     \
+  X(P_BF16X3, false, 2, 2, 32, 2, 2) X(P_BF16X3, false, 2, 2, 32, 1, 4) X(P_BF16X3, false, 1, 2, 32, 3, 2) \
+  X(P_BF16X3, false, 2, 2, 16, 2, 2) X(P_BF16X3, false, 2, 4, 32, 1, 2) X(P_BF16X3, false, 1, 2, 32, 2, 4)
 
-#define GW_COUNT(P, C, A, B, K) +1
-#define GW_CFG(P, C, A, B, K) {A, B, K, #P "/" #C "/" #A "x" #B "/k" #K},
+#define GW_COUNT(P, C, A, B, K, O, W) +1
+#define GW_CFG(P, C, A, B, K, O, W) {A, B, K, W, #P "/" #C "/" #A "x" #B "/k" #K "/o" #O "/w" #W},
 
 template <int P, bool C>
 struct Menu;
@@ -495,7 +512,7 @@ int gemm_tile_count(int prec, int cplx) {
 int gemm_tile_bm(int prec, int cplx, int tile) {
   int n = 0;
   const TileCfg *c = menu(prec, cplx, &n);
-  return (c && tile >= 0 && tile < n) ? 2 * c[tile].wtm * mb_of(prec) : 0;
+  return (c && tile >= 0 && tile < n) ? c[tile].wm * c[tile].wtm * mb_of(prec) : 0;
 }
 int gemm_tile_bn(int prec, int cplx, int tile) {
   int n = 0;
@@ -517,9 +534,9 @@ hipError_t launch_gemm(const GemmLaunch &L, int prec, int cplx, int tile, int gr
                        hipStream_t s) {
   if (L.n_units <= 0) return hipSuccess;
   int idx = 0;
-#define GW_TRY(P, C, A, B, K)                                        \
+#define GW_TRY(P, C, A, B, K, O, W)                                  \
   if (prec == P && (cplx != 0) == C) {                               \
-    if (idx == tile) return launch_one<P, C, A, B, K>(L, grid, num_cu, s); \
+    if (idx == tile) return launch_one<P, C, A, B, K, O, W>(L, grid, num_cu, s); \
     ++idx;                                                           \
   }
   GW_TILES_FP64_C(GW_TRY)

@@ -66,14 +66,14 @@ def test_parity(ctx, name, prec):
 def test_every_tile_config(ctx, prec):
     it, ref = case("ragged")
     n = len([0 for _ in range(8)])
-    for t in range(1, 4):
+    for t in range(1, 7):
         ctx.set_options(tile_id=t, use_graph=0)
         out = ctx.build([it], prec)
         err = oc.rel_frobenius(out[0], ref)
         say(f"[tile] prec={prec} tile={t} err={err:.3e}")
         assert err <= TOL[prec]
     ctx.set_options(tile_id=0, use_graph=1)
-    for t in range(1, 4):
+    for t in range(1, 7):
         ctx.set_options(tile_id=t, use_graph=0)
         it2, ref2 = case("ragged_real")
         out = ctx.build([it2], prec)
@@ -236,7 +236,7 @@ def test_autotune_writes_and_uses_cache(tmp_path):
     c.close()
     data = json.load(open(path))
     say(f"[autotune] {data}")
-    assert 0 <= data["fp32/c"] < 3
+    assert 0 <= data["fp32/c"] < 6
     c2 = gwchi.Context(0, tune_cache=path)
     out, rep = c2.build([it], "fp32", report=True)
     c2.close()
