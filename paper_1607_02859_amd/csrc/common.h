@@ -30,6 +30,7 @@ struct Geo {
   int32_t planes;          // i0-planes per plane-FFT block
   const int32_t *disk_i12; // [n_disk] k1*n2 + k2
   const int32_t *slot_of;  // [n_disk][n0] output slot of (pencil d, k0), or -1
+  const int32_t *disk_of;  // [n1*n2] pencil d of (k1, k2), or -1
 };
 
 // ---------------------------------------------------------------------------
@@ -71,12 +72,21 @@ struct GemmJob {
   void *slab;               // [w / 2^cg_shift][n_r][2^cg_shift] output
 };
 
+// Work queues of a persistent launch: units [q_off[q], q_off[q + 1]) form
+// queue q.  Workgroup b starts on queue b % n_queues (workgroups of a launch
+// are dealt to the XCDs in turn, so each queue is served by one XCD and its
+// tiles share operand panels in that XCD's L2) and moves on to the next queue
+// when its own is empty.
+constexpr int kGemmQueues = 8;
+
 struct GemmLaunch {
   const GemmJob *jobs;
   const int4 *units;        // (job, r0, c0, 0)
   int32_t n_units;
   int32_t hermitian;        // 1: units are lower-triangle tiles; mask r >= c
-  int32_t *counter;         // ticket counter, zero before the launch; null: grid stride
+  int32_t *counter;         // n_queues ticket counters, zero before the launch; null: grid stride
+  int32_t n_queues;         // 1 .. kGemmQueues
+  int32_t q_off[kGemmQueues + 1];
 };
 
 // ---------------------------------------------------------------------------
@@ -139,6 +149,7 @@ hipError_t launch_gemm(const GemmLaunch &L, int prec, int cplx, int tile, int gr
 int gemm_tile_count(int prec, int cplx);
 int gemm_tile_bm(int prec, int cplx, int tile);
 int gemm_tile_bn(int prec, int cplx, int tile);
+int gemm_tile_per_cu(int prec, int cplx, int tile);   // resident workgroups per CU
 int gemm_tile_kc(int prec, int cplx, int tile);
 const char *gemm_tile_name(int prec, int cplx, int tile);
 hipError_t launch_fft(const FftLaunch &L, int dbl, int sign, int lds_bytes, int cubic_n,
@@ -168,6 +179,29 @@ constexpr int fft_planes(int n0, int n1, int n2, int elem) {
 // cubic grids with a specialised FFT kernel
 constexpr bool fft_specialised(int n) {
   return n == 12 || n == 16 || n == 18 || n == 20 || n == 24 || n == 28 || n == 32;
+}
+// Plane-FFT block of the specialised cubic kernels (n^3 grid): `cols` adjacent
+// columns x `planes` i0-planes, one thread per line (planes * n * cols <= 512
+// threads), LDS of planes * n * n * cols elements (at most 80 KB), planes
+// dividing n.
+constexpr int fftc_lds_bytes(int n, int cols, int planes, int elem) {
+  return planes * n * n * cols * elem;
+}
+constexpr int fftc_cols(int n, int elem) {
+  int cols = 128 / elem;
+  while (cols > 1 && (fftc_lds_bytes(n, cols, 1, elem) > 80 * 1024 || n * cols > 512)) cols /= 2;
+  return cols;
+}
+constexpr int fftc_planes(int n, int elem) {
+  const int cols = fftc_cols(n, elem);
+  int planes = 1;
+  while (2 * planes * n * cols <= 512 && fftc_lds_bytes(n, cols, 2 * planes, elem) <= 80 * 1024 &&
+         n % (2 * planes) == 0)
+    planes *= 2;
+  return planes;
+}
+constexpr int fftc_threads(int n, int elem) {
+  return fftc_planes(n, elem) * n * fftc_cols(n, elem);
 }
 int fft_supported(int n);
 // hermitian = 1: x holds X with chi = X + X^H; 32x32 tiles on or below the

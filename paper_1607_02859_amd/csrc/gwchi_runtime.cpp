@@ -244,7 +244,7 @@ struct ItemPlan {
   double homo, lumo;
   std::vector<int32_t> perm_o, perm_u;
   std::vector<double> eps_o, eps_u;
-  std::vector<int32_t> disk_i12, slot_of;
+  std::vector<int32_t> disk_i12, slot_of, disk_of;
   int n_disk = 0, planes = 1, cols = 16, fft_lds = 0;
   std::vector<double> coef;    // [n_omega][n_tau]
   std::vector<double> tau;
@@ -374,10 +374,18 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
     for (auto &kv : dmap) I.disk_i12[kv.second] = kv.first;
     I.slot_of.assign((size_t)I.n_disk * I.n0, -1);
     for (int g = 0; g < I.n_g; ++g) I.slot_of[(size_t)dk[g].first * I.n0 + dk[g].second] = g;
+    I.disk_of.assign((size_t)I.n1 * I.n2, -1);
+    for (int d = 0; d < I.n_disk; ++d) I.disk_of[I.disk_i12[d]] = d;
     // plane-FFT block shape (same formula as the kernels)
-    I.cols = fft_cols(I.n1, I.n2, ec);
-    I.planes = fft_planes(I.n0, I.n1, I.n2, ec);
-    I.fft_lds = fft_lds_bytes(I.n1, I.n2, I.cols, I.planes, ec) + 4 * I.n_disk;
+    if (I.n0 == I.n1 && I.n1 == I.n2 && fft_specialised(I.n0)) {
+      I.cols = fftc_cols(I.n0, ec);
+      I.planes = fftc_planes(I.n0, ec);
+      I.fft_lds = fftc_lds_bytes(I.n0, I.cols, I.planes, ec);
+    } else {
+      I.cols = fft_cols(I.n1, I.n2, ec);
+      I.planes = fft_planes(I.n0, I.n1, I.n2, ec);
+      I.fft_lds = fft_lds_bytes(I.n1, I.n2, I.cols, I.planes, ec) + 4 * I.n_disk;
+    }
     I.phi_o = it.phi_occ;
     I.phi_u = it.phi_unocc;
     I.out = it.chi_out;
@@ -570,12 +578,13 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
   for (int b : P.pass_begin) key << b << ",";
   key << "|";
   // geometry tables
-  std::vector<size_t> off_i12(n_items), off_sdk(n_items), off_perm_o(n_items),
+  std::vector<size_t> off_i12(n_items), off_sdk(n_items), off_dof(n_items), off_perm_o(n_items),
       off_perm_u(n_items), off_eps_o(n_items), off_eps_u(n_items), off_coef(n_items);
   for (int t = 0; t < n_items; ++t) {
     const ItemPlan &I = P.items[t];
     off_i12[t] = B.blob.addv(I.disk_i12);
     off_sdk[t] = B.blob.addv(I.slot_of);
+    off_dof[t] = B.blob.addv(I.disk_of);
     off_perm_o[t] = B.blob.addv(I.perm_o);
     off_perm_u[t] = B.blob.addv(I.perm_u);
     off_eps_o[t] = B.blob.addv(I.eps_o);
@@ -600,6 +609,7 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
     g.planes = I.planes;
     g.disk_i12 = reinterpret_cast<const int32_t *>(off_i12[t]);   // offset, patched
     g.slot_of = reinterpret_cast<const int32_t *>(off_sdk[t]);
+    g.disk_of = reinterpret_cast<const int32_t *>(off_dof[t]);
     geos[t] = g;
   }
   const size_t off_geos = B.blob.addv(geos);
@@ -691,9 +701,18 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
       return P.jobs[a].k_o_eff + P.jobs[a].k_u_eff > P.jobs[b].k_o_eff + P.jobs[b].k_u_eff;
     });
+    // Tiles of a job form groups of about one XCD's resident workgroups,
+    // gr x gc tiles (gc a power of two near the square root), so that the
+    // tiles running together on one XCD share few operand panels.  Groups go,
+    // in job order, to the least loaded of the per-XCD queues.
+    const int per_cu = std::max(1, gemm_tile_per_cu(P.prec, cplx, P.tile));
+    const int group = std::max(1, per_cu * ctx->num_cu / kGemmQueues);
+    int gc_want = 1;
+    while (gc_want * gc_want < group) gc_want *= 2;
     for (int s = 0; s < max_slabs; ++s) {
       std::vector<GemmJob> gj;
-      std::vector<int4> units;
+      std::vector<std::vector<int4>> qunits(kGemmQueues);
+      std::vector<double> qwork(kGemmQueues, 0.0);
       std::vector<FftJob> fj;
       for (int q : order) {
         const JobPlan &J = P.jobs[q];
@@ -719,15 +738,24 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
         gj.push_back(g);
         const int nrt = (int)((I.n_r + P.bm - 1) / P.bm);
         const int nct = (w + P.bn - 1) / P.bn;
-        for (int ct = 0; ct < nct; ++ct) {
-          const int c0 = (int)s0 + ct * P.bn;
-          for (int rt = 0; rt < nrt; ++rt) {
-            const int r0 = rt * P.bm;
-            if (ctx->opt.hermitian && r0 + P.bm <= c0) continue;
-            units.push_back(make_int4(gi, r0, c0, 0));
-            const double kk = (double)(J.k_o_eff + J.k_u_eff);
-            P.mfma_flops +=
-                (I.cplx ? 8.0 : 2.0) * P.bm * P.bn * kk * (P.prec == P_BF16X3 ? 3.0 : 1.0);
+        const int gc = std::min(nct, gc_want);
+        const int gr = std::max(1, (group + gc - 1) / gc);
+        const double kk = (double)(J.k_o_eff + J.k_u_eff);
+        for (int cb = 0; cb < nct; cb += gc) {
+          for (int rb = 0; rb < nrt; rb += gr) {
+            std::vector<int4> tiles;
+            for (int rt = rb; rt < std::min(nrt, rb + gr); ++rt)
+              for (int ct = cb; ct < std::min(nct, cb + gc); ++ct) {
+                const int r0 = rt * P.bm, c0 = (int)s0 + ct * P.bn;
+                if (ctx->opt.hermitian && r0 + P.bm <= c0) continue;
+                tiles.push_back(make_int4(gi, r0, c0, 0));
+              }
+            if (tiles.empty()) continue;
+            const int q = (int)(std::min_element(qwork.begin(), qwork.end()) - qwork.begin());
+            qunits[q].insert(qunits[q].end(), tiles.begin(), tiles.end());
+            qwork[q] += kk * (double)tiles.size();
+            P.mfma_flops += (I.cplx ? 8.0 : 2.0) * P.bm * P.bn * kk *
+                            (P.prec == P_BF16X3 ? 3.0 : 1.0) * (double)tiles.size();
           }
         }
         FftJob f{};
@@ -748,11 +776,18 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
       G.phase = PH_GEMM;
       G.kind = 1;
       G.gemm.jobs = reinterpret_cast<const GemmJob *>(B.blob.addv(gj));
+      std::vector<int4> units;
+      G.gemm.n_queues = kGemmQueues;
+      for (int q = 0; q < kGemmQueues; ++q) {
+        G.gemm.q_off[q] = (int32_t)units.size();
+        units.insert(units.end(), qunits[q].begin(), qunits[q].end());
+      }
+      G.gemm.q_off[kGemmQueues] = (int32_t)units.size();
       G.gemm.units = reinterpret_cast<const int4 *>(B.blob.addv(units));
       G.gemm.n_units = (int)units.size();
       G.gemm.hermitian = ctx->opt.hermitian;
       if (ctx->opt.persistent) {
-        G.gemm.counter = reinterpret_cast<int32_t *>(ctx->b_ctr.p) + B.n_gemm;
+        G.gemm.counter = reinterpret_cast<int32_t *>(ctx->b_ctr.p) + B.n_gemm * kGemmQueues;
         G.gemm_grid = 0;
       } else {
         G.gemm.counter = nullptr;
@@ -868,7 +903,7 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
     Z.phase = PH_STAGE;
     Z.kind = 5;
     Z.fill_ptr = ctx->b_ctr.p;
-    Z.fill_bytes = (int64_t)B.n_gemm * 4;
+    Z.fill_bytes = (int64_t)B.n_gemm * kGemmQueues * 4;
     B.launches.insert(B.launches.begin(), Z);
   }
   key << "|persistent=" << ctx->opt.persistent;
@@ -926,6 +961,7 @@ void patch_geos(Built &B, const char *base, size_t off_geos, int n_items) {
   for (int i = 0; i < n_items; ++i) {
     g[i].disk_i12 = dev(base, g[i].disk_i12);
     g[i].slot_of = dev(base, g[i].slot_of);
+    g[i].disk_of = dev(base, g[i].disk_of);
   }
 }
 
@@ -1012,7 +1048,7 @@ gwchi_status run_build(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int
     int max_slabs = 0;
     for (auto &I : P.items) max_slabs = std::max<int>(max_slabs, (int)((I.n_r + P.slab_w - 1) / P.slab_w));
     const size_t n_ctr = (size_t)((int)P.pass_begin.size() - 1) * max_slabs + 16;
-    HIPCHK(ctx->b_ctr.ensure(n_ctr * 4, &moved));
+    HIPCHK(ctx->b_ctr.ensure(n_ctr * kGemmQueues * 4, &moved));
   }
   Built B;
   build_launches(ctx, P, want_norms, B);

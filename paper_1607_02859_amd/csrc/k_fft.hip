@@ -9,8 +9,9 @@
 // unnormalised, for the caller's list of plane waves.
 //
 // Two launches per transform:
-//   k_fft_planes : a block loads `cols` adjacent columns x `planes` i0-planes
-//                  into LDS (columns innermost, so global reads and the tmp
+//   k_fft_planes_c (cubic grids with a specialised size) / k_fft_planes (any
+//                  grid): a block owns `cols` adjacent columns x `planes`
+//                  i0-planes (columns innermost, so global reads and the tmp
 //                  writes are contiguous runs of `cols` elements), transforms
 //                  along i2 and i1 (one thread per line, register FFT) and
 //                  keeps only the (k1, k2) pencils the sphere touches:
@@ -67,6 +68,26 @@ template <typename T>
 struct cx {
   T x, y;
 };
+
+// Loads and stores through global-address-space pointers: they compile to
+// global (not flat) memory instructions, which the compiler keeps in flight
+// across LDS accesses.
+template <typename T>
+__device__ __forceinline__ T ld_g(const T *p, int64_t i) {
+  return ((const __attribute__((address_space(1))) T *)p)[i];
+}
+template <typename T>
+__device__ __forceinline__ cx<T> ld_g(const cx<T> *p, int64_t i) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 x = ((const __attribute__((address_space(1))) v2 *)p)[i];
+  return cx<T>{x.x, x.y};
+}
+template <typename T>
+__device__ __forceinline__ void st_g(cx<T> *p, int64_t i, cx<T> v) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  ((__attribute__((address_space(1))) v2 *)p)[i] = v2{v.x, v.y};
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) {
   return {a.x + b.x, a.y + b.y};
@@ -185,19 +206,9 @@ __device__ __forceinline__ int find_job(const FftJob *jobs, int n, int u, bool p
   return lo;
 }
 
-// in-place line transform: compile-time length when NC > 0, else dispatched
-template <int NC, int SIGN, typename T>
-__device__ __forceinline__ void line(cx<T> *p, int stride, int n) {
-  if constexpr (NC > 0) {
-    line_n<NC, SIGN, T>(p, stride);
-  } else {
-    line_fft<SIGN, T>(p, stride, n);
-  }
-}
-
-// NC > 0: every job of the launch has the cubic grid NC^3 (sizes, block shape
-// and line lengths are compile-time); NC == 0: sizes from the geometry table.
-template <typename T, int SIGN, int NC>
+// Any grid: sizes and block shape from the geometry table, line lengths
+// dispatched at run time.
+template <typename T, int SIGN>
 __global__ __launch_bounds__(256) void k_fft_planes(FftLaunch L) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   cx<T> *buf = reinterpret_cast<cx<T> *>(smem);
@@ -206,9 +217,9 @@ __global__ __launch_bounds__(256) void k_fft_planes(FftLaunch L) {
   for (int u = blockIdx.x; u < L.n_units_planes; u += gridDim.x) {
     const FftJob J = L.jobs[find_job(L.jobs, L.n_jobs, u, false)];
     const Geo G = L.geos[J.geo];
-    const int n0 = NC ? NC : G.n0, n1 = NC ? NC : G.n1, n2 = NC ? NC : G.n2;
-    const int C = NC ? fft_cols(NC, NC, EC) : G.cols;
-    const int P = NC ? fft_planes(NC, NC, NC, EC) : G.planes;
+    const int n0 = G.n0, n1 = G.n1, n2 = G.n2;
+    const int C = G.cols;
+    const int P = G.planes;
     const int D = G.n_disk;
     const int plane = n1 * n2;
     const int npg = (n0 + P - 1) / P;
@@ -254,48 +265,25 @@ __global__ __launch_bounds__(256) void k_fft_planes(FftLaunch L) {
       }
       return v;
     };
-    if constexpr (NC > 0) {
-      // every global load of the block is issued before the first LDS store
-      constexpr int NL = (fft_planes(NC, NC, NC, EC) * NC * NC * fft_cols(NC, NC, EC) + 255) / 256;
-      cx<T> v[NL];
-#pragma unroll
-      for (int i = 0; i < NL; ++i) {
-        int64_t e;
-        int li;
-        locate(tid + 256 * i, e, li);
-        v[i] = fetch(e);
-      }
-#pragma unroll
-      for (int i = 0; i < NL; ++i) {
-        const int idx = tid + 256 * i;
-        if (idx < total) {
-          int64_t e;
-          int li;
-          locate(idx, e, li);
-          buf[li] = v[i];
-        }
-      }
-    } else {
-      for (int idx = tid; idx < total; idx += 256) {
-        int64_t e;
-        int li;
-        locate(idx, e, li);
-        buf[li] = fetch(e);
-      }
+    for (int idx = tid; idx < total; idx += 256) {
+      int64_t e;
+      int li;
+      locate(idx, e, li);
+      buf[li] = fetch(e);
     }
     __syncthreads();
     // along i2: lines (p, i1, cc), stride C
     for (int ln = tid; ln < np * n1 * C; ln += 256) {
       const int cc = ln % C, rest = ln / C;
       const int p = rest / n1, i1 = rest - p * n1;
-      line<NC, SIGN, T>(buf + lds_idx(p, i1, 0, cc, n1, n2, C), C + 1, n2);
+      line_fft<SIGN, T>(buf + lds_idx(p, i1, 0, cc, n1, n2, C), C + 1, n2);
     }
     __syncthreads();
     // along i1: lines (p, i2, cc), stride one padded row
     for (int ln = tid; ln < np * n2 * C; ln += 256) {
       const int cc = ln % C, rest = ln / C;
       const int p = rest / n2, i2 = rest - p * n2;
-      line<NC, SIGN, T>(buf + lds_idx(p, 0, i2, cc, n1, n2, C), n2 * (C + 1), n1);
+      line_fft<SIGN, T>(buf + lds_idx(p, 0, i2, cc, n1, n2, C), n2 * (C + 1), n1);
     }
     __syncthreads();
     // keep the sphere's pencils
@@ -314,6 +302,104 @@ __global__ __launch_bounds__(256) void k_fft_planes(FftLaunch L) {
   }
 }
 
+// Specialised cubic grid NC^3.  A block of fftc_threads(NC) threads owns C
+// adjacent columns x P planes:
+//   step 1: one thread per line (p, i1, column) loads the NC values along i2
+//           straight from global memory, transforms them in registers and
+//           stores the result to LDS, [p][i1][k2][column];
+//   step 2: one thread per line (p, k2, column) reads the NC values along i1,
+//           transforms them and writes the sphere's pencils (k1, k2) to tmp.
+// Lanes run over adjacent columns first, so each group of lanes touches one
+// contiguous run in global memory and in LDS.
+// Register budget: blocks of 256 threads or more keep two blocks per CU
+// (waves per SIMD = 2 * threads / 256); smaller blocks are left unbounded,
+// since their lines of 28 or 32 points would spill.
+constexpr int fftc_min_waves(int nt) { return nt >= 256 ? (nt + 127) / 128 : 1; }
+template <typename T, int SIGN, int NC>
+__global__ __launch_bounds__(fftc_threads(NC, (int)sizeof(cx<T>)),
+                             fftc_min_waves(fftc_threads(NC, (int)sizeof(cx<T>))))
+void k_fft_planes_c(FftLaunch L) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  cx<T> *buf = reinterpret_cast<cx<T> *>(smem);
+  constexpr int EC = (int)sizeof(cx<T>);
+  constexpr int C = fftc_cols(NC, EC);
+  constexpr int P = fftc_planes(NC, EC);
+  constexpr int plane = NC * NC;
+  constexpr int npg = NC / P;
+  const int tid = threadIdx.x;
+  const int cc = tid % C, ln = tid / C;
+  const int a = ln % NC, p = ln / NC;      // step 1: a = i1; step 2: a = k2
+  for (int u = blockIdx.x; u < L.n_units_planes; u += gridDim.x) {
+    const FftJob J = L.jobs[find_job(L.jobs, L.n_jobs, u, false)];
+    const Geo G = L.geos[J.geo];
+    const int D = G.n_disk;
+    const int lu = u - J.unit0_planes;
+    const int cg = lu / npg, pg = lu - cg * npg;
+    const int c0 = cg * C, p0 = pg * P;
+    // lower-triangle storage: a block whose planes all lie above the first
+    // stored row of its first column is zero; it is skipped and the pencil
+    // pass reads those planes as zero (same test there)
+    if (L.lower_only && (int64_t)(p0 + P) * plane <= (int64_t)J.col0 + c0) continue;
+    const int c = c0 + cc;
+    const bool col_ok = c < J.n_cols;
+    // step 1: line (p, i1 = a, c) along i2
+    {
+      const int64_t r0 = (int64_t)(p0 + p) * plane + (int64_t)a * NC;
+      int64_t e0, es;
+      if (J.s_col == 0) {        // column-grouped input, groups of C columns
+        e0 = ((int64_t)cg * G.n_r + r0) * C + cc;
+        es = C;
+      } else {
+        e0 = r0 * J.s_r + (int64_t)c * J.s_col;
+        es = J.s_r;
+      }
+      const int64_t zlim = L.lower_only ? (int64_t)J.col0 + c : -1;
+      // every load is issued unconditionally (element 0 stands in for the
+      // masked ones), so that all NC loads are in flight together
+      cx<T> v[NC], o[NC];
+      if (L.in_real) {
+        const T *in = reinterpret_cast<const T *>(J.in);
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+          const bool ok = col_ok && r0 + i >= zlim;
+          const T x = ld_g(in, ok ? e0 + i * es : 0);
+          v[i] = cx<T>{ok ? x : (T)0, (T)0};
+        }
+      } else {
+        const cx<T> *in = reinterpret_cast<const cx<T> *>(J.in);
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+          const bool ok = col_ok && r0 + i >= zlim;
+          const cx<T> x = ld_g(in, ok ? e0 + i * es : 0);
+          v[i] = ok ? x : cx<T>{(T)0, (T)0};
+        }
+      }
+      reg_fft<NC, SIGN, T, 1>(v, o);
+#pragma unroll
+      for (int k = 0; k < NC; ++k) buf[((p * NC + a) * NC + k) * C + cc] = o[k];
+    }
+    __syncthreads();
+    // step 2: line (p, k2 = a, c) along i1, then the sphere's pencils; the
+    // pencil indices are loaded first, so that none waits behind a store
+    {
+      int dk[NC];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) dk[k] = ld_g(G.disk_of, k * NC + a);
+      cx<T> v[NC], o[NC];
+#pragma unroll
+      for (int i = 0; i < NC; ++i) v[i] = buf[((p * NC + i) * NC + a) * C + cc];
+      reg_fft<NC, SIGN, T, 1>(v, o);
+      if (col_ok) {
+        cx<T> *tmp = reinterpret_cast<cx<T> *>(J.tmp) + (int64_t)(p0 + p) * D * J.n_cols + c;
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+          if (dk[k] >= 0) st_g(tmp, (int64_t)dk[k] * J.n_cols, o[k]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <int N, int SIGN, typename T>
 __device__ __forceinline__ void pencil_n(const FftJob &J, const Geo &G, int d, int c,
                                          int lower_only) {
@@ -321,21 +407,24 @@ __device__ __forceinline__ void pencil_n(const FftJob &J, const Geo &G, int d, i
   // planes whose plane-FFT block was skipped as all-zero (see k_fft_planes)
   const int64_t plane = (int64_t)G.n1 * G.n2;
   const int64_t zlim = lower_only ? (int64_t)J.col0 + (c / G.cols) * G.cols : -1;
+  // output slots first and every load unconditional (element 0 stands in for
+  // the skipped planes), so that no load waits behind another or a store
+  int so[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) so[k] = ld_g(G.slot_of, (int64_t)d * N + k);
   cx<T> v[N], o[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     const int hi = min(N, (i / G.planes + 1) * G.planes);
-    v[i] = (hi * plane <= zlim) ? cx<T>{(T)0, (T)0}
-                                : tmp[((int64_t)i * G.n_disk + d) * J.n_cols + c];
+    const bool ok = hi * plane > zlim;
+    const cx<T> x = ld_g(tmp, ok ? ((int64_t)i * G.n_disk + d) * J.n_cols + c : 0);
+    v[i] = ok ? x : cx<T>{(T)0, (T)0};
   }
   reg_fft<N, SIGN, T, 1>(v, o);
   cx<T> *out = reinterpret_cast<cx<T> *>(J.out) + (int64_t)(J.col0 + c) * J.o_col;
-  const int32_t *so = G.slot_of + (int64_t)d * N;
 #pragma unroll
-  for (int k = 0; k < N; ++k) {
-    const int s = so[k];
-    if (s >= 0) out[(int64_t)s * J.o_slot] = o[k];
-  }
+  for (int k = 0; k < N; ++k)
+    if (so[k] >= 0) st_g(out, (int64_t)so[k] * J.o_slot, o[k]);
 }
 
 template <typename T, int SIGN, int NC>
@@ -369,10 +458,22 @@ template <typename T, int S, int NC>
 hipError_t launch_fft_t(const FftLaunch &L, int lds_bytes, hipStream_t s) {
   const int g1 = L.n_units_planes < 65536 ? L.n_units_planes : 65536;
   const int g2 = L.n_units_pencils < 65536 ? L.n_units_pencils : 65536;
-  hipError_t e = hipFuncSetAttribute((const void *)k_fft_planes<T, S, NC>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-  if (e != hipSuccess) return e;
-  if (g1 > 0) hipLaunchKernelGGL((k_fft_planes<T, S, NC>), dim3(g1), dim3(256), lds_bytes, s, L);
+  hipError_t e;
+  if constexpr (NC > 0) {
+    constexpr int EC = (int)sizeof(cx<T>);
+    constexpr int lds = fftc_lds_bytes(NC, fftc_cols(NC, EC), fftc_planes(NC, EC), EC);
+    (void)lds_bytes;
+    e = hipFuncSetAttribute((const void *)k_fft_planes_c<T, S, NC>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    if (g1 > 0)
+      hipLaunchKernelGGL((k_fft_planes_c<T, S, NC>), dim3(g1), dim3(fftc_threads(NC, EC)), lds, s, L);
+  } else {
+    e = hipFuncSetAttribute((const void *)k_fft_planes<T, S>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (e != hipSuccess) return e;
+    if (g1 > 0) hipLaunchKernelGGL((k_fft_planes<T, S>), dim3(g1), dim3(256), lds_bytes, s, L);
+  }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (g2 > 0) hipLaunchKernelGGL((k_fft_pencils<T, S, NC>), dim3(g2), dim3(256), 0, s, L);

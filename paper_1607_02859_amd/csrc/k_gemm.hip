@@ -18,12 +18,13 @@
 //   BF16X3 v_mfma_f32_32x32x16_bf16 (32x32 blocks, 16 bands per step), each
 //          real product as hi*hi + hi*lo + lo*hi with FP32 accumulation.
 //
-// A workgroup is 4 waves in a 2x2 arrangement; each wave owns WTM x WTN
-// MFMA blocks.  Operand chunks of KC bands are staged through LDS with a
-// double buffer; the next chunk is fetched into registers while the current
-// one feeds the MFMAs.  The launch is persistent: as many workgroups as are
-// resident take units from the list with an atomic ticket (list ordered with
-// the most bands first), or, without a ticket counter, by grid stride.
+// A workgroup is WM x 2 waves; each wave owns WTM x WTN MFMA blocks.
+// Operand chunks of KC bands are staged through LDS with a double buffer; the
+// next chunk is fetched into registers while the current one feeds the MFMAs.
+// The launch is persistent: as many workgroups as are resident take units
+// with atomic tickets from per-XCD queues of compact tile groups (so that the
+// tiles running together on one XCD share operand panels in its L2), or,
+// without ticket counters, by grid stride.
 #include <type_traits>
 
 #include "common.h"
@@ -336,10 +337,30 @@ struct Gemm {
     }
   }
 
-  // next unit: an atomic ticket (persistent grid) or the grid stride
-  static __device__ __forceinline__ int next_unit(const GemmLaunch &L, int prev, int *s_u) {
+  // next unit: an atomic ticket on the workgroup's current queue, moving to
+  // the following queues once it is empty (persistent grid), or the grid
+  // stride.  *s_q holds the current queue; a return of n_units ends the loop.
+  static __device__ __forceinline__ int next_unit(const GemmLaunch &L, int prev, int *s_u,
+                                                  int *s_q) {
     if (L.counter == nullptr) return prev < 0 ? (int)blockIdx.x : prev + (int)gridDim.x;
-    if (threadIdx.x == 0) *s_u = atomicAdd(L.counter, 1);
+    if (threadIdx.x == 0) {
+      const int nq = L.n_queues;
+      int q = prev < 0 ? (int)(blockIdx.x % (unsigned)nq) : *s_q;
+      int u = L.n_units;
+      for (int tries = 0; tries < nq; ++tries) {
+        const int b = L.q_off[q], e = L.q_off[q + 1];
+        if (b < e) {
+          const int t = atomicAdd(L.counter + q, 1);
+          if (t < e - b) {
+            u = b + t;
+            break;
+          }
+        }
+        q = q + 1 == nq ? 0 : q + 1;
+      }
+      *s_q = q;
+      *s_u = u;
+    }
     __syncthreads();
     const int u = *s_u;
     __syncthreads();
@@ -347,11 +368,12 @@ struct Gemm {
   }
 
   static __device__ __forceinline__ void run(const GemmLaunch &L, char *lds) {
-    __shared__ int s_u;
+    __shared__ int s_u, s_q;
     const int w = threadIdx.x >> 6;
     const int l = threadIdx.x & 63;
     const int wr = w >> 1, wc = w & 1;     // WM rows x 2 columns of waves
-    for (int u = next_unit(L, -1, &s_u); u < L.n_units; u = next_unit(L, u, &s_u)) {
+    for (int u = next_unit(L, -1, &s_u, &s_q); u < L.n_units;
+         u = next_unit(L, u, &s_u, &s_q)) {
       const int4 unit = L.units[u];
       const GemmJob job = L.jobs[unit.x];
       const int r0 = unit.y, c0 = unit.z;
@@ -423,24 +445,35 @@ struct TileCfg {
 
 // Tile menus per (precision, complex).  Index 0 is the default.
 // grid <= 0: persistent launch sized to the resident blocks of the device
+// Resident workgroups per CU (occupancy query, once per tile; sets the LDS
+// size attribute first).  0 on error.
+template <int P, bool C, int WTM, int WTN, int KC, int OCC, int WM>
+int per_cu_of() {
+  typedef Tile<P, C, WTM, WTN, KC, WM> T;
+  const int lds = 2 * T::BUF;
+  auto kern = k_gemm<P, C, WTM, WTN, KC, OCC, WM>;
+  static int per_cu = -1;
+  if (per_cu < 0) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
+      return 0;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, T::NT, lds) != hipSuccess || n < 1)
+      n = 1;
+    per_cu = n;
+  }
+  return per_cu;
+}
+
 template <int P, bool C, int WTM, int WTN, int KC, int OCC, int WM>
 hipError_t launch_one(const GemmLaunch &L, int grid, int num_cu, hipStream_t s) {
   typedef Tile<P, C, WTM, WTN, KC, WM> T;
   const int lds = 2 * T::BUF;
-  auto kern = k_gemm<P, C, WTM, WTN, KC, OCC, WM>;
-  static bool attr = false;
-  static int per_cu = 0;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, T::NT, lds);
-    if (e != hipSuccess || per_cu < 1) per_cu = 1;
-    attr = true;
-  }
+  const int per_cu = per_cu_of<P, C, WTM, WTN, KC, OCC, WM>();
+  if (per_cu == 0) return hipErrorInvalidValue;
   if (grid <= 0) grid = per_cu * num_cu;
   if (grid > L.n_units) grid = L.n_units;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(T::NT), lds, s, L);
+  hipLaunchKernelGGL((k_gemm<P, C, WTM, WTN, KC, OCC, WM>), dim3(grid), dim3(T::NT), lds, s, L);
   return hipGetLastError();
 }
 
@@ -528,6 +561,23 @@ const char *gemm_tile_name(int prec, int cplx, int tile) {
   int n = 0;
   const TileCfg *c = menu(prec, cplx, &n);
   return (c && tile >= 0 && tile < n) ? c[tile].name : "?";
+}
+
+int gemm_tile_per_cu(int prec, int cplx, int tile) {
+  int idx = 0;
+#define GW_TRY(P, C, A, B, K, O, W)                           \
+  if (prec == P && (cplx != 0) == C) {                        \
+    if (idx == tile) return per_cu_of<P, C, A, B, K, O, W>(); \
+    ++idx;                                                    \
+  }
+  GW_TILES_FP64_C(GW_TRY)
+  GW_TILES_FP64_R(GW_TRY)
+  GW_TILES_FP32_C(GW_TRY)
+  GW_TILES_FP32_R(GW_TRY)
+  GW_TILES_BF16_C(GW_TRY)
+  GW_TILES_BF16_R(GW_TRY)
+#undef GW_TRY
+  return 0;
 }
 
 hipError_t launch_gemm(const GemmLaunch &L, int prec, int cplx, int tile, int grid, int num_cu,
