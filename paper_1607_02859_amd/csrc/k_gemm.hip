@@ -19,8 +19,9 @@
 //          real product as hi*hi + hi*lo + lo*hi with FP32 accumulation.
 //
 // A workgroup is WM x 2 waves; each wave owns WTM x WTN MFMA blocks.
-// Operand chunks of KC bands are staged through LDS with a double buffer; the
-// next chunk is fetched into registers while the current one feeds the MFMAs.
+// Operand chunks of KC bands go from global memory straight into a ring of
+// LDS stages (direct loads, swizzled 16-byte slots), several chunks ahead of
+// the MFMAs.
 // The launch is persistent: as many workgroups as are resident take units
 // with atomic tickets from per-XCD queues of compact tile groups (so that the
 // tiles running together on one XCD share operand panels in its L2), or,
@@ -45,6 +46,7 @@ struct MM<P_FP64, C> {
   static constexpr int MB = 16;         // block edge
   static constexpr int KS = 4;          // bands per MFMA step
   static constexpr int BPB = C ? 16 : 8;  // bytes per band element
+  static constexpr int KR = C ? 4 : 8;  // bands per read round (16-byte slots)
   static constexpr int NACC = 4;
   typedef d4v acc_t;
   // the FP64 16x16 result interleaves rows: value v of lane l is row l/16 + 4v
@@ -58,6 +60,7 @@ struct MM<P_FP32, C> {
   static constexpr int MB = 32;
   static constexpr int KS = 2;
   static constexpr int BPB = C ? 8 : 4;
+  static constexpr int KR = C ? 4 : 8;
   static constexpr int NACC = 16;
   typedef f16v acc_t;
   static __device__ __forceinline__ int acc_row(int l, int v) {
@@ -72,6 +75,7 @@ struct MM<P_BF16X3, C> {
   static constexpr int MB = 32;
   static constexpr int KS = 16;
   static constexpr int BPB = C ? 8 : 4;   // 2 B x (4 or 2) parts
+  static constexpr int KR = 16;
   static constexpr int NACC = 16;
   typedef f16v acc_t;
   static __device__ __forceinline__ int acc_row(int l, int v) {
@@ -99,26 +103,48 @@ __device__ __forceinline__ uint4 neg_bf8(uint4 q) {
   return q;
 }
 
-template <int P, bool C, int WTM, int WTN, int KC, int WM>
+// Workgroup tile: WM x 2 waves, each owning WTM x WTN MFMA blocks; K is
+// consumed in chunks of KC bands.  The operand rows of one chunk (BM rows of
+// the tile, then BN rows of its columns) sit in LDS as rows of ROWB bytes made
+// of 16-byte slots; slot s of row r is stored at slot s ^ swz(r), so that the
+// lanes reading one slot of consecutive rows fall on distinct banks.  The LDS
+// holds a ring of ST chunks, filled by direct global-to-LDS loads (1 KB per
+// wave instruction) ST - 1 chunks ahead of the MFMAs.
+template <int P, bool C, int WTM, int WTN, int KC, int WM, int OCC>
 struct Tile {
   typedef MM<P, C> M;
-  static constexpr int NT = 128 * WM;            // threads: WM x 2 waves
+  static constexpr int NW = 2 * WM;                // waves
+  static constexpr int NT = 64 * NW;               // threads
   static constexpr int BM = WM * WTM * M::MB;
   static constexpr int BN = 2 * WTN * M::MB;
-  static constexpr int ROWB = KC * M::BPB;        // bytes per operand row per chunk
-  static constexpr int R16 = ROWB / 16;           // 16-B vectors per row
-  static constexpr int PITCH = ROWB + 16;         // LDS row pitch (padding vs bank conflicts)
-  static constexpr int NV = (BM + BN) * R16;      // vectors per chunk
-  static constexpr int VPT = (NV + NT - 1) / NT;  // vectors per thread
-  static constexpr int BUF = (BM + BN) * PITCH;   // bytes per LDS buffer
-  static_assert(ROWB % 16 == 0, "row chunk must be 16-B aligned");
-  static_assert(KC % M::KS == 0, "chunk must hold whole MFMA steps");
+  static constexpr int ROWB = KC * M::BPB;         // bytes per operand row per chunk
+  static constexpr int SPR = ROWB / 16;            // 16-byte slots per row
+  static constexpr int BUF = (BM + BN) * ROWB;     // bytes per stage
+  static constexpr int NB = BUF / 1024;            // 1 KB wave loads per stage
+  static constexpr int LPW = NB / NW;              // of which each wave issues
+  // stages: as many as fit the workgroup's share of the CU's 160 KB, at most 4
+  static constexpr int WG_PER_CU = (2 * OCC) / WM > 1 ? (2 * OCC) / WM : 1;
+  static constexpr int ST0 = (160 * 1024 / WG_PER_CU) / BUF;
+  static constexpr int ST = ST0 > 4 ? 4 : ST0;
+  static_assert(ROWB % 16 == 0 && BUF % 1024 == 0 && NB % NW == 0,
+                "a stage must split into whole 1 KB loads per wave");
+  static_assert(ST >= 2, "two stages must fit");
+  static_assert(KC % M::KR == 0, "chunk must hold whole read rounds");
+  static_assert(SPR == 1 || SPR == 2 || SPR == 4 || SPR % 8 == 0, "row of 1, 2, 4 or 8k slots");
+  static __device__ __forceinline__ int swz(int r) {
+    if constexpr (SPR >= 8) return r & 7;
+    else if constexpr (SPR == 4) return (r >> 1) & 3;
+    else if constexpr (SPR == 2) return (r >> 2) & 1;
+    else return 0;
+  }
+  // byte offset of (row, logical slot) in a stage
+  static __device__ __forceinline__ int at(int r, int s) { return r * ROWB + ((s ^ swz(r)) << 4); }
 };
 
-template <int P, bool C, int WTM, int WTN, int KC, int WM>
+template <int P, bool C, int WTM, int WTN, int KC, int WM, int OCC>
 struct Gemm {
   typedef MM<P, C> M;
-  typedef Tile<P, C, WTM, WTN, KC, WM> T;
+  typedef Tile<P, C, WTM, WTN, KC, WM, OCC> T;
   typedef typename M::acc_t acc_t;
 
   struct Acc {
@@ -136,64 +162,55 @@ struct Gemm {
     });
   }
 
-  // global -> registers for chunk starting at band kc0
-  // prefetch registers as one vector value, so that they stay in VGPRs
-  typedef uint32_t regv_t __attribute__((ext_vector_type(4 * T::VPT)));
-  struct Regs {
-    regv_t v;
-  };
-
-  // global -> registers for the chunk starting at band kc0
-  static __device__ __forceinline__ void fetch(Regs &reg, const char *base, int64_t pitchB,
-                                               int r0, int c0, int kc0) {
-    const int tid = threadIdx.x;
-    sfor<0, T::VPT>([&](auto tt) {
+  // Direct global -> LDS loads: wave w issues the 1 KB blocks w, w + NW, ...
+  // of a stage; lane l of block b fills bytes 16 l .. 16 l + 15 of it, which
+  // hold logical slot ((16 l) % ROWB / 16) ^ swz(row) of that row.
+  // Per-lane byte offset of load t within an operand of row pitch pitchB:
+  static __device__ __forceinline__ uint32_t dma_off(int t, int r0, int c0, uint32_t pitchB) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int byte = (w + t * T::NW) * 1024 + l * 16;
+    const int row = byte / T::ROWB, p = (byte % T::ROWB) >> 4;
+    const int s = p ^ T::swz(row);
+    const int grow = row < T::BM ? r0 + row : c0 + (row - T::BM);
+    return (uint32_t)grow * pitchB + (uint32_t)(s << 4);
+  }
+  // the loads of one chunk: base points at the chunk's first band of row 0
+  static __device__ __forceinline__ void issue(const char *base, const uint32_t (&off)[T::LPW],
+                                               char *buf) {
+    const int w = threadIdx.x >> 6;
+    sfor<0, T::LPW>([&](auto tt) {
       constexpr int t = decltype(tt)::value;
-      const int v = tid + t * T::NT;
-      if (T::NV % T::NT == 0 || v < T::NV) {
-        const int row = v / T::R16, q = v % T::R16;
-        const int grow = row < T::BM ? r0 + row : c0 + (row - T::BM);
-        const char *p = base + (int64_t)grow * pitchB + (int64_t)kc0 * M::BPB + q * 16;
-        const uint4 x = *reinterpret_cast<const uint4 *>(p);
-        reg.v[4 * t + 0] = x.x;
-        reg.v[4 * t + 1] = x.y;
-        reg.v[4 * t + 2] = x.z;
-        reg.v[4 * t + 3] = x.w;
-      }
+      __builtin_amdgcn_global_load_lds(
+          (const __attribute__((address_space(1))) void *)(base + off[t]),
+          (__attribute__((address_space(3))) void *)(buf + (w + t * T::NW) * 1024), 16, 0, 0);
     });
   }
 
-  static __device__ __forceinline__ void store(const Regs &reg, char *buf) {
-    const int tid = threadIdx.x;
-    sfor<0, T::VPT>([&](auto tt) {
-      constexpr int t = decltype(tt)::value;
-      const int v = tid + t * T::NT;
-      if (T::NV % T::NT == 0 || v < T::NV) {
-        const int row = v / T::R16, q = v % T::R16;
-        *reinterpret_cast<uint4 *>(buf + row * T::PITCH + q * 16) =
-            make_uint4(reg.v[4 * t + 0], reg.v[4 * t + 1], reg.v[4 * t + 2], reg.v[4 * t + 3]);
-      }
-    });
+  template <typename V>
+  static __device__ __forceinline__ V ld(const char *buf, int r, int s) {
+    return *reinterpret_cast<const V *>(buf + T::at(r, s));
   }
 
-  // one chunk of KC bands from LDS into the accumulators
+  // One chunk of KC bands from LDS into the accumulators.  Every lane reads
+  // whole 16-byte slots; a slot holding several bands feeds as many MFMA steps
+  // (the MFMA's k index is the lane group, and A and B use the same
+  // band-to-(step, group) assignment, so every band enters the sum once).
   static __device__ __forceinline__ void compute(Acc &acc, const char *buf, int wr, int wc) {
     const int l = threadIdx.x & 63;
-    const char *A = buf + (wr * WTM * M::MB) * T::PITCH;
-    const char *B = buf + (T::BM + wc * WTN * M::MB) * T::PITCH;
-    const int fr = M::frag_row(l);
+    const int ra = wr * WTM * M::MB + M::frag_row(l);
+    const int rb = T::BM + wc * WTN * M::MB + M::frag_row(l);
 #pragma unroll
-    for (int kb = 0; kb < KC; kb += M::KS) {
+    for (int kb = 0; kb < KC; kb += M::KR) {
       if constexpr (P == P_FP64) {
-        const int band = kb + (l >> 4);
+        const int g = l >> 4;
         if constexpr (C) {
+          // one band per slot: 4 bands, one step
+          const int s = kb + g;
           double2 a[WTM], b[WTN];
 #pragma unroll
-          for (int i = 0; i < WTM; ++i)
-            a[i] = *reinterpret_cast<const double2 *>(A + (i * 16 + fr) * T::PITCH + band * 16);
+          for (int i = 0; i < WTM; ++i) a[i] = ld<double2>(buf, ra + i * 16, s);
 #pragma unroll
-          for (int j = 0; j < WTN; ++j)
-            b[j] = *reinterpret_cast<const double2 *>(B + (j * 16 + fr) * T::PITCH + band * 16);
+          for (int j = 0; j < WTN; ++j) b[j] = ld<double2>(buf, rb + j * 16, s);
 #pragma unroll
           for (int i = 0; i < WTM; ++i)
 #pragma unroll
@@ -204,67 +221,78 @@ struct Gemm {
               acc.im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[i].x, b[j].y, acc.im[i][j], 0, 0, 0);
             }
         } else {
-          double a[WTM], b[WTN];
+          // two bands per slot: 8 bands, two steps
+          const int s = (kb >> 1) + g;
+          double2 a[WTM], b[WTN];
 #pragma unroll
-          for (int i = 0; i < WTM; ++i)
-            a[i] = *reinterpret_cast<const double *>(A + (i * 16 + fr) * T::PITCH + band * 8);
+          for (int i = 0; i < WTM; ++i) a[i] = ld<double2>(buf, ra + i * 16, s);
 #pragma unroll
-          for (int j = 0; j < WTN; ++j)
-            b[j] = *reinterpret_cast<const double *>(B + (j * 16 + fr) * T::PITCH + band * 8);
-#pragma unroll
-          for (int i = 0; i < WTM; ++i)
-#pragma unroll
-            for (int j = 0; j < WTN; ++j)
-              acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc.re[i][j], 0, 0, 0);
-        }
-      } else if constexpr (P == P_FP32) {
-        const int band = kb + (l >> 5);
-        if constexpr (C) {
-          float2 a[WTM], b[WTN];
-#pragma unroll
-          for (int i = 0; i < WTM; ++i)
-            a[i] = *reinterpret_cast<const float2 *>(A + (i * 32 + fr) * T::PITCH + band * 8);
-#pragma unroll
-          for (int j = 0; j < WTN; ++j)
-            b[j] = *reinterpret_cast<const float2 *>(B + (j * 32 + fr) * T::PITCH + band * 8);
+          for (int j = 0; j < WTN; ++j) b[j] = ld<double2>(buf, rb + j * 16, s);
 #pragma unroll
           for (int i = 0; i < WTM; ++i)
 #pragma unroll
             for (int j = 0; j < WTN; ++j) {
-              acc.re[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].x, b[j].x, acc.re[i][j], 0, 0, 0);
-              acc.re[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].y, b[j].y, acc.re[i][j], 0, 0, 0);
-              acc.im[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].y, b[j].x, acc.im[i][j], 0, 0, 0);
-              acc.im[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[i].x, b[j].y, acc.im[i][j], 0, 0, 0);
+              acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, acc.re[i][j], 0, 0, 0);
+              acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].y, acc.re[i][j], 0, 0, 0);
+            }
+        }
+      } else if constexpr (P == P_FP32) {
+        const int g = l >> 5;
+        if constexpr (C) {
+          // two bands (re, im, re, im) per slot: 4 bands, two steps
+          const int s = (kb >> 1) + g;
+          float4 a[WTM], b[WTN];
+#pragma unroll
+          for (int i = 0; i < WTM; ++i) a[i] = ld<float4>(buf, ra + i * 32, s);
+#pragma unroll
+          for (int j = 0; j < WTN; ++j) b[j] = ld<float4>(buf, rb + j * 32, s);
+#pragma unroll
+          for (int i = 0; i < WTM; ++i)
+#pragma unroll
+            for (int j = 0; j < WTN; ++j) {
+              f16v &re = acc.re[i][j];
+              f16v &im = acc.im[i][j];
+              re = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].x, b[j].x, re, 0, 0, 0);
+              re = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].y, b[j].y, re, 0, 0, 0);
+              im = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].y, b[j].x, im, 0, 0, 0);
+              im = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[i].x, b[j].y, im, 0, 0, 0);
+              re = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].z, b[j].z, re, 0, 0, 0);
+              re = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].w, b[j].w, re, 0, 0, 0);
+              im = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].w, b[j].z, im, 0, 0, 0);
+              im = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[i].z, b[j].w, im, 0, 0, 0);
             }
         } else {
-          float a[WTM], b[WTN];
+          // four bands per slot: 8 bands, four steps
+          const int s = (kb >> 2) + g;
+          float4 a[WTM], b[WTN];
+#pragma unroll
+          for (int i = 0; i < WTM; ++i) a[i] = ld<float4>(buf, ra + i * 32, s);
+#pragma unroll
+          for (int j = 0; j < WTN; ++j) b[j] = ld<float4>(buf, rb + j * 32, s);
 #pragma unroll
           for (int i = 0; i < WTM; ++i)
-            a[i] = *reinterpret_cast<const float *>(A + (i * 32 + fr) * T::PITCH + band * 4);
 #pragma unroll
-          for (int j = 0; j < WTN; ++j)
-            b[j] = *reinterpret_cast<const float *>(B + (j * 32 + fr) * T::PITCH + band * 4);
-#pragma unroll
-          for (int i = 0; i < WTM; ++i)
-#pragma unroll
-            for (int j = 0; j < WTN; ++j)
-              acc.re[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc.re[i][j], 0, 0, 0);
+            for (int j = 0; j < WTN; ++j) {
+              f16v &re = acc.re[i][j];
+              re = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].x, b[j].x, re, 0, 0, 0);
+              re = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].y, b[j].y, re, 0, 0, 0);
+              re = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].z, b[j].z, re, 0, 0, 0);
+              re = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].w, b[j].w, re, 0, 0, 0);
+            }
         }
       } else {
-        // split-BF16: 8-band group g, parts of 16 B each
-        const int g = (kb >> 3) + (l >> 5);
+        // split-BF16: 8-band group grp, parts of one 16-byte slot each
+        const int grp = (kb >> 3) + (l >> 5);
         if constexpr (C) {
           uint4 a[WTM][4], b[WTN][4];
 #pragma unroll
           for (int i = 0; i < WTM; ++i)
 #pragma unroll
-            for (int p = 0; p < 4; ++p)
-              a[i][p] = *reinterpret_cast<const uint4 *>(A + (i * 32 + fr) * T::PITCH + g * 64 + p * 16);
+            for (int p = 0; p < 4; ++p) a[i][p] = ld<uint4>(buf, ra + i * 32, 4 * grp + p);
 #pragma unroll
           for (int j = 0; j < WTN; ++j)
 #pragma unroll
-            for (int p = 0; p < 4; ++p)
-              b[j][p] = *reinterpret_cast<const uint4 *>(B + (j * 32 + fr) * T::PITCH + g * 64 + p * 16);
+            for (int p = 0; p < 4; ++p) b[j][p] = ld<uint4>(buf, rb + j * 32, 4 * grp + p);
 #pragma unroll
           for (int i = 0; i < WTM; ++i) {
             const bf8v arh = as_bf8(a[i][0]), arl = as_bf8(a[i][1]);
@@ -297,13 +325,11 @@ struct Gemm {
 #pragma unroll
           for (int i = 0; i < WTM; ++i)
 #pragma unroll
-            for (int p = 0; p < 2; ++p)
-              a[i][p] = *reinterpret_cast<const uint4 *>(A + (i * 32 + fr) * T::PITCH + g * 32 + p * 16);
+            for (int p = 0; p < 2; ++p) a[i][p] = ld<uint4>(buf, ra + i * 32, 2 * grp + p);
 #pragma unroll
           for (int j = 0; j < WTN; ++j)
 #pragma unroll
-            for (int p = 0; p < 2; ++p)
-              b[j][p] = *reinterpret_cast<const uint4 *>(B + (j * 32 + fr) * T::PITCH + g * 32 + p * 16);
+            for (int p = 0; p < 2; ++p) b[j][p] = ld<uint4>(buf, rb + j * 32, 2 * grp + p);
 #pragma unroll
           for (int i = 0; i < WTM; ++i)
 #pragma unroll
@@ -318,23 +344,16 @@ struct Gemm {
     }
   }
 
-  static __device__ __forceinline__ void phase(Acc &acc, char *lds, const void *psi, int ld,
-                                               int k, int r0, int c0, int wr, int wc) {
-    const int nchunks = k / KC;
-    if (nchunks <= 0) return;
-    const char *base = reinterpret_cast<const char *>(psi);
-    const int64_t pitchB = (int64_t)ld * M::BPB;
-    Regs reg;
-    fetch(reg, base, pitchB, r0, c0, 0);
-    store(reg, lds);
-    __syncthreads();
-    for (int c = 0; c < nchunks; ++c) {
-      const bool more = c + 1 < nchunks;
-      if (more) fetch(reg, base, pitchB, r0, c0, (c + 1) * KC);
-      compute(acc, lds + (c & 1) * T::BUF, wr, wc);
-      if (more) store(reg, lds + ((c + 1) & 1) * T::BUF);
-      __syncthreads();
-    }
+  // wait until at most N vector-memory operations of this wave are in flight
+  // (the LDS writes of direct loads count until they land), then the
+  // workgroup barrier; no fence, so later stages' loads stay in flight
+  template <int N>
+  static __device__ __forceinline__ void wait_then_barrier() {
+    static_assert(N >= 0 && N < 64, "vmcnt has 6 bits");
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
   }
 
   // next unit: an atomic ticket on the workgroup's current queue, moving to
@@ -362,26 +381,73 @@ struct Gemm {
       *s_u = u;
     }
     __syncthreads();
-    const int u = *s_u;
+    // the same for every lane: keeps the unit's job fields in scalar registers
+    const int u = __builtin_amdgcn_readfirstlane(*s_u);
     __syncthreads();
     return u;
   }
 
-  static __device__ __forceinline__ void run(const GemmLaunch &L, char *lds) {
+  static __device__ __forceinline__ void run(const GemmLaunch &L) {
+    // one LDS array per stage, so that the compiler sees which stage each
+    // access touches and lets loads into other stages stay in flight
+    __shared__ __attribute__((aligned(1024))) char st0[T::BUF], st1[T::BUF];
+    __shared__ __attribute__((aligned(1024))) char st2[T::ST > 2 ? T::BUF : 16];
+    __shared__ __attribute__((aligned(1024))) char st3[T::ST > 3 ? T::BUF : 16];
+    auto stage = [&](auto ss) -> char * {
+      constexpr int s = decltype(ss)::value;
+      if constexpr (s == 0) return st0;
+      else if constexpr (s == 1) return st1;
+      else if constexpr (s == 2) return st2;
+      else return st3;
+    };
     __shared__ int s_u, s_q;
     const int w = threadIdx.x >> 6;
     const int l = threadIdx.x & 63;
     const int wr = w >> 1, wc = w & 1;     // WM rows x 2 columns of waves
+    constexpr int ST = T::ST;
     for (int u = next_unit(L, -1, &s_u, &s_q); u < L.n_units;
          u = next_unit(L, u, &s_u, &s_q)) {
       const int4 unit = L.units[u];
       const GemmJob job = L.jobs[unit.x];
       const int r0 = unit.y, c0 = unit.z;
+      const char *base_o = reinterpret_cast<const char *>(job.psi_o);
+      const char *base_u = reinterpret_cast<const char *>(job.psi_u);
+      uint32_t off_o[T::LPW], off_u[T::LPW];
+      sfor<0, T::LPW>([&](auto tt) {
+        constexpr int t = decltype(tt)::value;
+        off_o[t] = dma_off(t, r0, c0, (uint32_t)job.ld_o * M::BPB);
+        off_u[t] = dma_off(t, r0, c0, (uint32_t)job.ld_u * M::BPB);
+      });
+      // one pipelined pass over the n chunks of an operand into acc
+      auto pipe = [&](Acc &acc, const char *base, const uint32_t (&off)[T::LPW], int n) {
+        constexpr int CB = KC * M::BPB;      // bytes per chunk in a row
+        sfor<0, ST - 1>([&](auto ss) {
+          if (decltype(ss)::value < n) issue(base + (size_t)decltype(ss)::value * CB, off, stage(ss));
+        });
+        for (int cb = 0; cb < n; cb += ST) {
+          sfor<0, ST>([&](auto ss) {
+            constexpr int s = decltype(ss)::value;
+            const int c = cb + s;
+            if (c < n) {
+              // chunk c has landed in every wave (later chunks may be in flight)
+              if (c + ST - 2 < n) wait_then_barrier<T::LPW * (ST - 2)>();
+              else wait_then_barrier<0>();
+              // refill the stage of chunk c - 1, which every wave has finished
+              if (c + ST - 1 < n)
+                issue(base + (size_t)(c + ST - 1) * CB, off,
+                      stage(std::integral_constant<int, (s + ST - 1) % ST>{}));
+              compute(acc, stage(ss), wr, wc);
+            }
+          });
+        }
+        // every wave is done with the stages before the next prologue refills them
+        __syncthreads();
+      };
       Acc ao, au;
       zero(ao);
       zero(au);
-      phase(ao, lds, job.psi_o, job.ld_o, job.k_o, r0, c0, wr, wc);
-      phase(au, lds, job.psi_u, job.ld_u, job.k_u, r0, c0, wr, wc);
+      pipe(ao, base_o, off_o, job.k_o / KC);
+      pipe(au, base_u, off_u, job.k_u / KC);
       // epilogue: chi = -acc_o * conj(acc_u), column-major slab
       const int n_r = job.n_r;
       const int cend = job.s0 + job.w;
@@ -431,11 +497,11 @@ struct Gemm {
   }
 };
 
-// OCC: workgroups per CU the register allocation must allow; WM: rows of waves
+// OCC: minimum waves per SIMD the register allocation must allow; WM: rows
+// of waves
 template <int P, bool C, int WTM, int WTN, int KC, int OCC, int WM>
 __global__ __launch_bounds__(128 * WM, OCC) void k_gemm(GemmLaunch L) {
-  extern __shared__ __attribute__((aligned(16))) char lds[];
-  Gemm<P, C, WTM, WTN, KC, WM>::run(L, lds);
+  Gemm<P, C, WTM, WTN, KC, WM, OCC>::run(L);
 }
 
 struct TileCfg {
@@ -445,20 +511,15 @@ struct TileCfg {
 
 // Tile menus per (precision, complex).  Index 0 is the default.
 // grid <= 0: persistent launch sized to the resident blocks of the device
-// Resident workgroups per CU (occupancy query, once per tile; sets the LDS
-// size attribute first).  0 on error.
+// Resident workgroups per CU (occupancy query, once per tile; at least 1).
 template <int P, bool C, int WTM, int WTN, int KC, int OCC, int WM>
 int per_cu_of() {
-  typedef Tile<P, C, WTM, WTN, KC, WM> T;
-  const int lds = 2 * T::BUF;
+  typedef Tile<P, C, WTM, WTN, KC, WM, OCC> T;
   auto kern = k_gemm<P, C, WTM, WTN, KC, OCC, WM>;
   static int per_cu = -1;
   if (per_cu < 0) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
-      return 0;
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, T::NT, lds) != hipSuccess || n < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, T::NT, 0) != hipSuccess || n < 1)
       n = 1;
     per_cu = n;
   }
@@ -467,13 +528,11 @@ int per_cu_of() {
 
 template <int P, bool C, int WTM, int WTN, int KC, int OCC, int WM>
 hipError_t launch_one(const GemmLaunch &L, int grid, int num_cu, hipStream_t s) {
-  typedef Tile<P, C, WTM, WTN, KC, WM> T;
-  const int lds = 2 * T::BUF;
+  typedef Tile<P, C, WTM, WTN, KC, WM, OCC> T;
   const int per_cu = per_cu_of<P, C, WTM, WTN, KC, OCC, WM>();
-  if (per_cu == 0) return hipErrorInvalidValue;
   if (grid <= 0) grid = per_cu * num_cu;
   if (grid > L.n_units) grid = L.n_units;
-  hipLaunchKernelGGL((k_gemm<P, C, WTM, WTN, KC, OCC, WM>), dim3(grid), dim3(T::NT), lds, s, L);
+  hipLaunchKernelGGL((k_gemm<P, C, WTM, WTN, KC, OCC, WM>), dim3(grid), dim3(T::NT), 0, s, L);
   return hipGetLastError();
 }
 
@@ -484,17 +543,17 @@ hipError_t launch_one(const GemmLaunch &L, int grid, int num_cu, hipStream_t s) 
   X(P_FP64, true, 2, 2, 16, 2, 2) X(P_FP64, true, 1, 2, 16, 1, 4) X(P_FP64, true, 1, 2, 16, 2, 2) \
   X(P_FP64, true, 2, 1, 16, 2, 2) X(P_FP64, true, 2, 2, 8, 2, 2) X(P_FP64, true, 1, 1, 16, 2, 4)
 #define GW_TILES_FP64_R(X)                                                                     \
-  X(P_FP64, false, 2, 2, 16, 1, 4) X(P_FP64, false, 2, 2, 16, 3, 2) X(P_FP64, false, 2, 2, 32, 2, 2) \
-  X(P_FP64, false, 4, 2, 16, 2, 2) X(P_FP64, false, 2, 4, 16, 1, 2) X(P_FP64, false, 1, 2, 32, 2, 4)
+  X(P_FP64, false, 2, 2, 16, 3, 2) X(P_FP64, false, 4, 2, 16, 2, 2) X(P_FP64, false, 2, 2, 32, 2, 2) \
+  X(P_FP64, false, 2, 4, 16, 1, 2) X(P_FP64, false, 2, 2, 16, 1, 4) X(P_FP64, false, 1, 2, 32, 2, 4)
 #define GW_TILES_FP32_C(X)                                                                     \
-  X(P_FP32, true, 1, 2, 16, 1, 4) X(P_FP32, true, 2, 1, 16, 2, 2) X(P_FP32, true, 1, 2, 16, 2, 2) \
-  X(P_FP32, true, 1, 2, 32, 1, 4) X(P_FP32, true, 2, 2, 16, 1, 2) X(P_FP32, true, 1, 1, 32, 2, 4)
+  X(P_FP32, true, 1, 2, 32, 1, 4) X(P_FP32, true, 1, 2, 16, 2, 2) X(P_FP32, true, 1, 2, 16, 1, 4) \
+  X(P_FP32, true, 2, 1, 16, 2, 2) X(P_FP32, true, 2, 2, 16, 1, 2) X(P_FP32, true, 1, 1, 32, 2, 4)
 #define GW_TILES_FP32_R(X)                                                                     \
   X(P_FP32, false, 2, 2, 16, 2, 2) X(P_FP32, false, 2, 2, 32, 2, 2) X(P_FP32, false, 2, 2, 16, 1, 4) \
   X(P_FP32, false, 1, 2, 32, 3, 2) X(P_FP32, false, 2, 4, 16, 1, 2) X(P_FP32, false, 1, 2, 32, 2, 4)
 #define GW_TILES_BF16_C(X)                                                                     \
-  X(P_BF16X3, true, 1, 2, 16, 1, 4) X(P_BF16X3, true, 2, 2, 16, 1, 2) X(P_BF16X3, true, 1, 2, 32, 1, 4) \
-  X(P_BF16X3, true, 1, 2, 16, 2, 2) X(P_BF16X3, true, 2, 1, 16, 2, 2) X(P_BF16X3, true, 1, 1, 32, 2, 4)
+  X(P_BF16X3, true, 1, 2, 32, 1, 4) X(P_BF16X3, true, 2, 1, 16, 2, 2) X(P_BF16X3, true, 1, 2, 16, 2, 2) \
+  X(P_BF16X3, true, 1, 2, 16, 1, 4) X(P_BF16X3, true, 2, 2, 16, 1, 2) X(P_BF16X3, true, 1, 1, 32, 2, 4)
 #define GW_TILES_BF16_R(X)                                                                     \
   X(P_BF16X3, false, 2, 2, 32, 2, 2) X(P_BF16X3, false, 2, 2, 32, 1, 4) X(P_BF16X3, false, 1, 2, 32, 3, 2) \
   X(P_BF16X3, false, 2, 2, 16, 2, 2) X(P_BF16X3, false, 2, 4, 32, 1, 2) X(P_BF16X3, false, 1, 2, 32, 2, 4)
