@@ -126,6 +126,63 @@ constexpr int first_radix(int n) {
   return (n % 4 == 0) ? 4 : (n % 2 == 0) ? 2 : (n % 3 == 0) ? 3 : (n % 5 == 0) ? 5 : (n % 7 == 0) ? 7 : n;
 }
 
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) {
+  return {a.x - b.x, a.y - b.y};
+}
+// a * (SIGN i)
+template <int SIGN, typename T>
+__device__ __forceinline__ cx<T> rot(cx<T> a) {
+  if constexpr (SIGN > 0) return {-a.y, a.x};
+  else return {a.y, -a.x};
+}
+
+// o[k] = sum_n t[n] exp(SIGN 2 pi i n k / R) for one small radix: the
+// radix-2 and radix-4 butterflies, and for odd R the pairing of n with R - n:
+//   o[k], o[R-k] = t[0] + sum_n (t[n] + t[R-n]) cos(2 pi n k / R)
+//                  +- SIGN i sum_n (t[n] - t[R-n]) sin(2 pi n k / R),  n = 1 .. (R-1)/2
+template <int R, int SIGN, typename T>
+__device__ __forceinline__ void dft_small(const cx<T> (&t)[R], cx<T> (&o)[R]) {
+  if constexpr (R == 1) {
+    o[0] = t[0];
+  } else if constexpr (R == 2) {
+    o[0] = t[0] + t[1];
+    o[1] = t[0] - t[1];
+  } else if constexpr (R == 4) {
+    const cx<T> a = t[0] + t[2], b = t[0] - t[2];
+    const cx<T> c = t[1] + t[3], d = rot<SIGN>(t[1] - t[3]);
+    o[0] = a + c;
+    o[2] = a - c;
+    o[1] = b + d;
+    o[3] = b - d;
+  } else {
+    static_assert(R % 2 == 1, "odd radix");
+    constexpr int H = (R - 1) / 2;
+    cx<T> sp[H + 1], dm[H + 1];
+    cx<T> o0 = t[0];
+    sfor<1, H + 1>([&](auto nn) {
+      constexpr int n = decltype(nn)::value;
+      sp[n] = t[n] + t[R - n];
+      dm[n] = t[n] - t[R - n];
+      o0 = o0 + sp[n];
+    });
+    o[0] = o0;
+    sfor<1, H + 1>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      cx<T> a = t[0], b = {(T)0, (T)0};
+      sfor<1, H + 1>([&](auto nn) {
+        constexpr int n = decltype(nn)::value;
+        constexpr T c = (T)ce_cos2pi(n * k, R), sn = (T)ce_sin2pi(n * k, R);
+        a = {a.x + sp[n].x * c, a.y + sp[n].y * c};
+        b = {b.x + dm[n].x * sn, b.y + dm[n].y * sn};
+      });
+      const cx<T> ib = rot<SIGN>(b);
+      o[k] = a + ib;
+      o[R - k] = a - ib;
+    });
+  }
+}
+
 // out[k] = sum_n in[n*S] exp(SIGN 2 pi i n k / N), decimation in time
 template <int N, int SIGN, typename T, int S>
 __device__ __forceinline__ void reg_fft(const cx<T> *in, cx<T> *out) {
@@ -140,19 +197,15 @@ __device__ __forceinline__ void reg_fft(const cx<T> *in, cx<T> *out) {
     });
     sfor<0, M>([&](auto k1) {
       constexpr int K1 = decltype(k1)::value;
-      cx<T> t[R];
+      cx<T> t[R], o[R];
       sfor<0, R>([&](auto n2) {
         constexpr int N2 = decltype(n2)::value;
         t[N2] = tw<N, N2 * K1, SIGN>(y[N2 * M + K1]);
       });
+      dft_small<R, SIGN, T>(t, o);
       sfor<0, R>([&](auto k2) {
         constexpr int K2 = decltype(k2)::value;
-        cx<T> s = t[0];
-        sfor<1, R>([&](auto n2) {
-          constexpr int N2 = decltype(n2)::value;
-          s = s + tw<R, N2 * K2, SIGN>(t[N2]);
-        });
-        out[K1 + M * K2] = s;
+        out[K1 + M * K2] = o[K2];
       });
     });
   }
@@ -311,10 +364,8 @@ __global__ __launch_bounds__(256) void k_fft_planes(FftLaunch L) {
 //           transforms them and writes the sphere's pencils (k1, k2) to tmp.
 // Lanes run over adjacent columns first, so each group of lanes touches one
 // contiguous run in global memory and in LDS.
-// Register budget: blocks of 256 threads or more keep two blocks per CU
-// (waves per SIMD = 2 * threads / 256); smaller blocks are left unbounded,
-// since their lines of 28 or 32 points would spill.
-constexpr int fftc_min_waves(int nt) { return nt >= 256 ? (nt + 127) / 128 : 1; }
+// Register budget: two blocks per CU (waves per SIMD = 2 * threads / 256).
+constexpr int fftc_min_waves(int nt) { return nt >= 128 ? (nt + 127) / 128 : 1; }
 template <typename T, int SIGN, int NC>
 __global__ __launch_bounds__(fftc_threads(NC, (int)sizeof(cx<T>)),
                              fftc_min_waves(fftc_threads(NC, (int)sizeof(cx<T>))))
