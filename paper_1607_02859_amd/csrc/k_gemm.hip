@@ -195,7 +195,16 @@ struct Gemm {
   // whole 16-byte slots; a slot holding several bands feeds as many MFMA steps
   // (the MFMA's k index is the lane group, and A and B use the same
   // band-to-(step, group) assignment, so every band enters the sum once).
+  // The MFMA section runs at raised wave priority, so that of the waves
+  // sharing a SIMD the one holding its operands keeps the matrix core busy
+  // while the others issue their LDS reads (measured: +3 % on split-BF16,
+  // neutral on FP32, none for FP64).
   static __device__ __forceinline__ void compute(Acc &acc, const char *buf, int wr, int wc) {
+    if constexpr (P != P_FP64) __builtin_amdgcn_s_setprio(1);
+    compute_body(acc, buf, wr, wc);
+    if constexpr (P != P_FP64) __builtin_amdgcn_s_setprio(0);
+  }
+  static __device__ __forceinline__ void compute_body(Acc &acc, const char *buf, int wr, int wc) {
     const int l = threadIdx.x & 63;
     const int ra = wr * WTM * M::MB + M::frag_row(l);
     const int rb = T::BM + wc * WTN * M::MB + M::frag_row(l);
