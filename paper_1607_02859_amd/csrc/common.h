@@ -118,6 +118,7 @@ struct FftLaunch {
   int32_t n_units_pencils;
   int32_t in_real;          // input is real
   int32_t lower_only;       // column c holds only rows r >= col0 + c; others read as zero
+  int32_t grouped;          // every job's input is column-grouped (s_col == 0)
 };
 
 // ---------------------------------------------------------------------------

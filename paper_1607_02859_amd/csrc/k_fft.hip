@@ -357,16 +357,20 @@ __global__ __launch_bounds__(256) void k_fft_planes(FftLaunch L) {
 
 // Specialised cubic grid NC^3.  A block of fftc_threads(NC) threads owns C
 // adjacent columns x P planes:
-//   step 1: one thread per line (p, i1, column) loads the NC values along i2
-//           straight from global memory, transforms them in registers and
-//           stores the result to LDS, [p][i1][k2][column];
+//   step 1: one thread per line (p, i1, column) gets the NC values along i2
+//           (column-grouped input: straight from global memory; input
+//           contiguous along r: through a coalesced copy into LDS),
+//           transforms them in registers and stores the result to LDS,
+//           [p][i1][k2][column];
 //   step 2: one thread per line (p, k2, column) reads the NC values along i1,
 //           transforms them and writes the sphere's pencils (k1, k2) to tmp.
 // Lanes run over adjacent columns first, so each group of lanes touches one
 // contiguous run in global memory and in LDS.
 // Register budget: two blocks per CU (waves per SIMD = 2 * threads / 256).
 constexpr int fftc_min_waves(int nt) { return nt >= 128 ? (nt + 127) / 128 : 1; }
-template <typename T, int SIGN, int NC>
+// GROUPED: every job's input is column-grouped (else contiguous along r with
+// unit stride, s_r == 1).
+template <typename T, int SIGN, int NC, bool GROUPED>
 __global__ __launch_bounds__(fftc_threads(NC, (int)sizeof(cx<T>)),
                              fftc_min_waves(fftc_threads(NC, (int)sizeof(cx<T>))))
 void k_fft_planes_c(FftLaunch L) {
@@ -393,42 +397,54 @@ void k_fft_planes_c(FftLaunch L) {
     if (L.lower_only && (int64_t)(p0 + P) * plane <= (int64_t)J.col0 + c0) continue;
     const int c = c0 + cc;
     const bool col_ok = c < J.n_cols;
-    // step 1: line (p, i1 = a, c) along i2
-    {
-      const int64_t r0 = (int64_t)(p0 + p) * plane + (int64_t)a * NC;
-      int64_t e0, es;
-      if (J.s_col == 0) {        // column-grouped input, groups of C columns
-        e0 = ((int64_t)cg * G.n_r + r0) * C + cc;
-        es = C;
-      } else {
-        e0 = r0 * J.s_r + (int64_t)c * J.s_col;
-        es = J.s_r;
+    const int64_t zlim = L.lower_only ? (int64_t)J.col0 + c : -1;
+    // LDS element (grid point rl of the block, column k)
+    auto li = [&](int rl, int k) { return rl * C + k; };
+    // A thread's loads go out unconditionally at constant offsets from one
+    // base (element 0 when its column is past the end), all NC in flight
+    // together; masked values are replaced by zero afterwards.  Every row a
+    // block touches lies inside the input buffer.
+    auto load = [&](int64_t e) -> cx<T> {
+      if (L.in_real) return cx<T>{ld_g(reinterpret_cast<const T *>(J.in), e), (T)0};
+      return ld_g(reinterpret_cast<const cx<T> *>(J.in), e);
+    };
+    cx<T> v[NC], o[NC];
+    const int rl0 = (p * NC + a) * NC;   // first point of this thread's i2 line
+    if constexpr (GROUPED) {
+      // column-grouped input (groups of C columns): a thread's line along i2
+      // is a run of NC rows of one group, read straight into registers;
+      // rows above the diagonal of lower-triangle storage read as zero
+      const int64_t r0 = (int64_t)p0 * plane + rl0;
+      const int64_t e0 = col_ok ? ((int64_t)cg * G.n_r + r0) * C + cc : 0;
+#pragma unroll
+      for (int i = 0; i < NC; ++i) {
+        const cx<T> x = load(e0 + i * C);
+        v[i] = (col_ok && r0 + i >= zlim) ? x : cx<T>{(T)0, (T)0};
       }
-      const int64_t zlim = L.lower_only ? (int64_t)J.col0 + c : -1;
-      // every load is issued unconditionally (element 0 stands in for the
-      // masked ones), so that all NC loads are in flight together
-      cx<T> v[NC], o[NC];
-      if (L.in_real) {
-        const T *in = reinterpret_cast<const T *>(J.in);
+    } else {
+      // each column contiguous in r with unit stride (element (r, c) at
+      // r + c * s_col; never lower-triangle storage): the block's region is
+      // copied to LDS, lanes over the C columns first and then over
+      // consecutive points, so that a wave reads C runs of 64 / C points and
+      // writes one LDS run; then each thread reads its line from LDS
+      const int k = tid % C, rl1 = tid / C;
+      const bool ok_k = c0 + k < J.n_cols;
+      const int64_t e1 = ok_k ? (int64_t)p0 * plane + rl1 + (int64_t)(c0 + k) * J.s_col : 0;
 #pragma unroll
-        for (int i = 0; i < NC; ++i) {
-          const bool ok = col_ok && r0 + i >= zlim;
-          const T x = ld_g(in, ok ? e0 + i * es : 0);
-          v[i] = cx<T>{ok ? x : (T)0, (T)0};
-        }
-      } else {
-        const cx<T> *in = reinterpret_cast<const cx<T> *>(J.in);
-#pragma unroll
-        for (int i = 0; i < NC; ++i) {
-          const bool ok = col_ok && r0 + i >= zlim;
-          const cx<T> x = ld_g(in, ok ? e0 + i * es : 0);
-          v[i] = ok ? x : cx<T>{(T)0, (T)0};
-        }
+      for (int i = 0; i < NC; ++i) {
+        const cx<T> x = load(e1 + i * (P * NC));
+        v[i] = ok_k ? x : cx<T>{(T)0, (T)0};
       }
-      reg_fft<NC, SIGN, T, 1>(v, o);
 #pragma unroll
-      for (int k = 0; k < NC; ++k) buf[((p * NC + a) * NC + k) * C + cc] = o[k];
+      for (int i = 0; i < NC; ++i) buf[li(rl1 + i * (P * NC), k)] = v[i];
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < NC; ++i) v[i] = buf[li(rl0 + i, cc)];
     }
+    // step 1: line (p, i1 = a, column) along i2, kept in LDS as [p][i1][k2]
+    reg_fft<NC, SIGN, T, 1>(v, o);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) buf[li(rl0 + k, cc)] = o[k];
     __syncthreads();
     // step 2: line (p, k2 = a, c) along i1, then the sphere's pencils; the
     // pencil indices are loaded first, so that none waits behind a store
@@ -436,9 +452,8 @@ void k_fft_planes_c(FftLaunch L) {
       int dk[NC];
 #pragma unroll
       for (int k = 0; k < NC; ++k) dk[k] = ld_g(G.disk_of, k * NC + a);
-      cx<T> v[NC], o[NC];
 #pragma unroll
-      for (int i = 0; i < NC; ++i) v[i] = buf[((p * NC + i) * NC + a) * C + cc];
+      for (int i = 0; i < NC; ++i) v[i] = buf[li((p * NC + i) * NC + a, cc)];
       reg_fft<NC, SIGN, T, 1>(v, o);
       if (col_ok) {
         cx<T> *tmp = reinterpret_cast<cx<T> *>(J.tmp) + (int64_t)(p0 + p) * D * J.n_cols + c;
@@ -514,11 +529,10 @@ hipError_t launch_fft_t(const FftLaunch &L, int lds_bytes, hipStream_t s) {
     constexpr int EC = (int)sizeof(cx<T>);
     constexpr int lds = fftc_lds_bytes(NC, fftc_cols(NC, EC), fftc_planes(NC, EC), EC);
     (void)lds_bytes;
-    e = hipFuncSetAttribute((const void *)k_fft_planes_c<T, S, NC>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    auto kern = L.grouped ? k_fft_planes_c<T, S, NC, true> : k_fft_planes_c<T, S, NC, false>;
+    e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
-    if (g1 > 0)
-      hipLaunchKernelGGL((k_fft_planes_c<T, S, NC>), dim3(g1), dim3(fftc_threads(NC, EC)), lds, s, L);
+    if (g1 > 0) hipLaunchKernelGGL(kern, dim3(g1), dim3(fftc_threads(NC, EC)), lds, s, L);
   } else {
     e = hipFuncSetAttribute((const void *)k_fft_planes<T, S>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
@@ -560,6 +574,7 @@ int fft_supported(int n) {
 
 hipError_t launch_fft(const FftLaunch &L, int dbl, int sign, int lds_bytes, int cubic_n,
                       hipStream_t s) {
+  if (cubic_n < 0) return hipErrorInvalidValue;   // layouts the planner never mixes
   const int n = fft_specialised(cubic_n) ? cubic_n : 0;
   if (dbl) return sign < 0 ? launch_fft_n<double, -1>(L, lds_bytes, n, s)
                            : launch_fft_n<double, 1>(L, lds_bytes, n, s);
