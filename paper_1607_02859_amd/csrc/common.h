@@ -8,7 +8,18 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace gw {
+
+// compile-time loop: f(integral_constant<int, i>) for i in [B, E)
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor(F &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    sfor<B + 1, E>(f);
+  }
+}
 
 enum Prec : int { P_FP64 = 0, P_FP32 = 1, P_BF16X3 = 2 };
 

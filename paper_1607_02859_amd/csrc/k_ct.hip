@@ -120,10 +120,11 @@ __global__ __launch_bounds__(256) void k_ct(CtLaunch L, int k0) {
 // holds exactly (the same sums with conjugated terms), so one block computes a
 // 32x32 tile on or below the block diagonal and writes it and its mirror.
 // 512 threads: thread (tx, ty) owns (a0 + ty + 16 i, b0 + tx), i = 0, 1, for
-// CH frequencies.  The next tau's two input tiles are fetched into registers
-// while the current ones are used from LDS.
+// CH frequencies.  The input tiles of the next PD taus are in flight in
+// registers while the current ones are used from LDS.
 template <typename T, int CH>
 __global__ __launch_bounds__(512) void k_ct_herm(CtLaunch L, int k0) {
+  constexpr int PD = 2;
   __shared__ double2 t1[32][33];     // t1[gp][g] = x_j[b0 + gp][a0 + g] = X[g][g']
   __shared__ double2 t2[32][33];     // t2[g][gp] = x_j[a0 + g][b0 + gp] = X[g'][g]
   const int tid = threadIdx.x;
@@ -154,44 +155,56 @@ __global__ __launch_bounds__(512) void k_ct_herm(CtLaunch L, int k0) {
                                                                     (int64_t)g * ng + gp]
                         : make_double2(0.0, 0.0);
     }
-    // element q of a 32x32 tile: row q >> 5, column q & 31
-    V r1[2], r2[2];
-    auto fetch = [&](int j) {
+    // element q of a 32x32 tile: row q >> 5, column q & 31.  The two input
+    // tiles of tau j + PD are fetched into register slot j % PD while tau j
+    // is used from LDS, so that PD taus of loads are in flight.
+    V r1[PD][2], r2[PD][2];
+    auto fetch = [&](int j, V (&q1)[2], V (&q2)[2]) {
       const int64_t base = (int64_t)j * mat;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int e = tid + 512 * q, row = e >> 5, col = e & 31;
         const int g1 = a0 + col, gp1 = b0 + row;     // t1: x_j[gp][g]
-        r1[q] = (g1 < ng && gp1 < ng) ? x[base + (int64_t)gp1 * ng + g1] : V{0, 0};
+        q1[q] = (g1 < ng && gp1 < ng) ? x[base + (int64_t)gp1 * ng + g1] : V{0, 0};
         const int g2 = a0 + row, gp2 = b0 + col;     // t2: x_j[g][gp]
-        r2[q] = (g2 < ng && gp2 < ng) ? x[base + (int64_t)g2 * ng + gp2] : V{0, 0};
+        q2[q] = (g2 < ng && gp2 < ng) ? x[base + (int64_t)g2 * ng + gp2] : V{0, 0};
       }
     };
-    if (it.n_tau_x > 0) fetch(0);
-    for (int j = 0; j < it.n_tau_x; ++j) {
+    const int nt = it.n_tau_x;
+    sfor<0, PD>([&](auto ss) {
+      constexpr int sl = decltype(ss)::value;
+      if (sl < nt) fetch(sl, r1[sl], r2[sl]);
+    });
+    for (int jb = 0; jb < nt; jb += PD) {
+      sfor<0, PD>([&](auto ss) {
+        constexpr int sl = decltype(ss)::value;
+        const int j = jb + sl;
+        if (j < nt) {
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int e = tid + 512 * q, row = e >> 5, col = e & 31;
-        t1[row][col] = make_double2((double)r1[q].x, (double)r1[q].y);
-        t2[row][col] = make_double2((double)r2[q].x, (double)r2[q].y);
-      }
-      __syncthreads();
-      if (j + 1 < it.n_tau_x) fetch(j + 1);
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int gl = ty + 16 * i;
-        const double2 u = t1[tx][gl], w = t2[gl][tx];
-        const double xr = u.x + w.x, xi = u.y - w.y;
-#pragma unroll
-        for (int k = 0; k < CH; ++k) {
-          if (k0 + k < it.n_omega) {
-            const double c = it.coef[(int64_t)(k0 + k) * it.n_tau + it.j0 + j];
-            acc[i][k].x += c * xr;
-            acc[i][k].y += c * xi;
+          for (int q = 0; q < 2; ++q) {
+            const int e = tid + 512 * q, row = e >> 5, col = e & 31;
+            t1[row][col] = make_double2((double)r1[sl][q].x, (double)r1[sl][q].y);
+            t2[row][col] = make_double2((double)r2[sl][q].x, (double)r2[sl][q].y);
           }
+          __syncthreads();
+          if (j + PD < nt) fetch(j + PD, r1[sl], r2[sl]);
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const int gl = ty + 16 * i;
+            const double2 u = t1[tx][gl], w = t2[gl][tx];
+            const double xr = u.x + w.x, xi = u.y - w.y;
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+              if (k0 + k < it.n_omega) {
+                const double c = it.coef[(int64_t)(k0 + k) * it.n_tau + it.j0 + j];
+                acc[i][k].x += c * xr;
+                acc[i][k].y += c * xi;
+              }
+            }
+          }
+          __syncthreads();
         }
-      }
-      __syncthreads();
+      });
     }
     double2 *out = reinterpret_cast<double2 *>(it.out);
 #pragma unroll

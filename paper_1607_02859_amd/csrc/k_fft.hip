@@ -93,13 +93,6 @@ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) {
   return {a.x + b.x, a.y + b.y};
 }
 
-template <int B, int E, typename F>
-__device__ __forceinline__ void sfor(F &&f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    sfor<B + 1, E>(f);
-  }
-}
 
 // a * exp(SIGN * 2 pi i E / N)
 template <int N, int E, int SIGN, typename T>

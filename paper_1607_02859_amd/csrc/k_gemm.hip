@@ -85,14 +85,6 @@ struct MM<P_BF16X3, C> {
   static __device__ __forceinline__ int frag_row(int l) { return l & 31; }
 };
 
-// compile-time loop: f(integral_constant<int, i>) for i in [B, E)
-template <int B, int E, typename F>
-__device__ __forceinline__ void sfor(F &&f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    sfor<B + 1, E>(f);
-  }
-}
 
 __device__ __forceinline__ bf8v as_bf8(uint4 q) { return __builtin_bit_cast(bf8v, q); }
 __device__ __forceinline__ uint4 neg_bf8(uint4 q) {
