@@ -156,24 +156,26 @@ struct Gemm {
 
   // Direct global -> LDS loads: wave w issues the 1 KB blocks w, w + NW, ...
   // of a stage; lane l of block b fills bytes 16 l .. 16 l + 15 of it, which
-  // hold logical slot ((16 l) % ROWB / 16) ^ swz(row) of that row.
-  // Per-lane byte offset of load t within an operand of row pitch pitchB:
-  static __device__ __forceinline__ uint32_t dma_off(int t, int r0, int c0, uint32_t pitchB) {
+  // hold logical slot ((16 l) % ROWB / 16) ^ swz(row) of that row.  Per lane
+  // and load t: the operand row and the byte offset of the slot.
+  static __device__ __forceinline__ void dma_lane(int t, int r0, int c0, uint32_t &grow,
+                                                  uint32_t &sb) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int byte = (w + t * T::NW) * 1024 + l * 16;
     const int row = byte / T::ROWB, p = (byte % T::ROWB) >> 4;
-    const int s = p ^ T::swz(row);
-    const int grow = row < T::BM ? r0 + row : c0 + (row - T::BM);
-    return (uint32_t)grow * pitchB + (uint32_t)(s << 4);
+    grow = (uint32_t)(row < T::BM ? r0 + row : c0 + (row - T::BM));
+    sb = (uint32_t)((p ^ T::swz(row)) << 4);
   }
-  // the loads of one chunk: base points at the chunk's first band of row 0
-  static __device__ __forceinline__ void issue(const char *base, const uint32_t (&off)[T::LPW],
-                                               char *buf) {
+  // the loads of one chunk: base points at the chunk's first band of row 0,
+  // pitchB is the operand's row pitch in bytes
+  static __device__ __forceinline__ void issue(const char *base, uint32_t pitchB,
+                                               const uint32_t (&grow)[T::LPW],
+                                               const uint32_t (&sb)[T::LPW], char *buf) {
     const int w = threadIdx.x >> 6;
     sfor<0, T::LPW>([&](auto tt) {
       constexpr int t = decltype(tt)::value;
       __builtin_amdgcn_global_load_lds(
-          (const __attribute__((address_space(1))) void *)(base + off[t]),
+          (const __attribute__((address_space(1))) void *)(base + (grow[t] * pitchB + sb[t])),
           (__attribute__((address_space(3))) void *)(buf + (w + t * T::NW) * 1024), 16, 0, 0);
     });
   }
@@ -411,19 +413,19 @@ struct Gemm {
       const int4 unit = L.units[u];
       const GemmJob job = L.jobs[unit.x];
       const int r0 = unit.y, c0 = unit.z;
-      const char *base_o = reinterpret_cast<const char *>(job.psi_o);
-      const char *base_u = reinterpret_cast<const char *>(job.psi_u);
-      uint32_t off_o[T::LPW], off_u[T::LPW];
+      uint32_t grow[T::LPW], sb[T::LPW];
       sfor<0, T::LPW>([&](auto tt) {
         constexpr int t = decltype(tt)::value;
-        off_o[t] = dma_off(t, r0, c0, (uint32_t)job.ld_o * M::BPB);
-        off_u[t] = dma_off(t, r0, c0, (uint32_t)job.ld_u * M::BPB);
+        dma_lane(t, r0, c0, grow[t], sb[t]);
       });
       // one pipelined pass over the n chunks of an operand into acc
-      auto pipe = [&](Acc &acc, const char *base, const uint32_t (&off)[T::LPW], int n) {
+      auto pipe = [&](Acc &acc, const void *psi, int ld, int n) {
         constexpr int CB = KC * M::BPB;      // bytes per chunk in a row
+        const char *base = reinterpret_cast<const char *>(psi);
+        const uint32_t pitch = (uint32_t)ld * M::BPB;
         sfor<0, ST - 1>([&](auto ss) {
-          if (decltype(ss)::value < n) issue(base + (size_t)decltype(ss)::value * CB, off, stage(ss));
+          if (decltype(ss)::value < n)
+            issue(base + (size_t)decltype(ss)::value * CB, pitch, grow, sb, stage(ss));
         });
         for (int cb = 0; cb < n; cb += ST) {
           sfor<0, ST>([&](auto ss) {
@@ -435,7 +437,7 @@ struct Gemm {
               else wait_then_barrier<0>();
               // refill the stage of chunk c - 1, which every wave has finished
               if (c + ST - 1 < n)
-                issue(base + (size_t)(c + ST - 1) * CB, off,
+                issue(base + (size_t)(c + ST - 1) * CB, pitch, grow, sb,
                       stage(std::integral_constant<int, (s + ST - 1) % ST>{}));
               compute(acc, stage(ss), wr, wc);
             }
@@ -447,8 +449,8 @@ struct Gemm {
       Acc ao, au;
       zero(ao);
       zero(au);
-      pipe(ao, base_o, off_o, job.k_o / KC);
-      pipe(au, base_u, off_u, job.k_u / KC);
+      pipe(ao, job.psi_o, job.ld_o, job.k_o / KC);
+      pipe(au, job.psi_u, job.ld_u, job.k_u / KC);
       // epilogue: chi = -acc_o * conj(acc_u), column-major slab
       const int n_r = job.n_r;
       const int cend = job.s0 + job.w;
