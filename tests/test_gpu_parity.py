@@ -36,6 +36,11 @@ CASES = {
     "cplx8": lambda: synth.make_item(103, (8, 8, 8), 8, 40, True, 6, x_min=1.0),
     "ragged": lambda: synth.make_item(104, (10, 12, 9), 20, 100, True, 4, x_min=1.0),
     "ragged_real": lambda: synth.make_item(105, (9, 10, 14), 13, 77, False, 3, x_min=1.0),
+    # cubic grids with specialised FFT kernels (column-grouped and contiguous
+    # plane kernels, radices 4, 2, 3, 5)
+    "cplx16": lambda: synth.make_item(107, (16, 16, 16), 8, 40, True, 4, x_min=1.0),
+    "real18": lambda: synth.make_item(108, (18, 18, 18), 6, 30, False, 3, x_min=1.0),
+    "cplx20": lambda: synth.make_item(109, (20, 20, 20), 6, 30, True, 3, x_min=1.0),
     "cfg1": lambda: synth.make_config(1)[0],
 }
 
@@ -65,7 +70,6 @@ def test_parity(ctx, name, prec):
 @pytest.mark.parametrize("prec", PRECS)
 def test_every_tile_config(ctx, prec):
     it, ref = case("ragged")
-    n = len([0 for _ in range(8)])
     for t in range(1, 7):
         ctx.set_options(tile_id=t, use_graph=0)
         out = ctx.build([it], prec)
@@ -79,7 +83,6 @@ def test_every_tile_config(ctx, prec):
         out = ctx.build([it2], prec)
         assert oc.rel_frobenius(out[0], ref2) <= TOL[prec]
     ctx.set_options(tile_id=0, use_graph=1)
-    del n
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -176,6 +179,36 @@ def test_config2_full_size_sampled_rows(ctx):
     assert err <= TOL["fp32"]
     herm = np.abs(out - np.conj(np.transpose(out, (0, 2, 1)))).max() / np.abs(out).max()
     assert herm < 1e-5
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", ["cplx16", "real18", "cplx20"])
+def test_cubic_hermitian_default(ctx, name, prec):
+    """The default options (Hermitian completion, persistent launch, graph) on
+    the cubic grids with specialised FFT kernels."""
+    it, ref = case(name)
+    ctx.set_options(use_graph=1, hermitian=1, skip_zero_bands=0, slab_width=0, tile_id=0)
+    out = ctx.build([it], prec)[0]
+    err = oc.rel_frobenius(out, ref)
+    say(f"[cubic-herm] case={name} prec={prec} err={err:.3e}")
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_cplx28_sampled_rows(ctx, prec):
+    """28^3 complex (radix-7 line transforms, the largest-register plane
+    kernels), default options, checked on sampled rows from the pair-sum
+    oracle and by Hermiticity."""
+    it = synth.make_item(110, (28, 28, 28), 4, 20, True, 2, x_min=1.0)
+    say(f"[cplx28] prec={prec} n_g={it.n_g}")
+    ctx.set_options(use_graph=1, hermitian=1, skip_zero_bands=0, slab_width=0, tile_id=0)
+    out = ctx.build([it], prec)[0]
+    rows = [0, 1, 333, it.n_g - 1]
+    err = oc.rel_frobenius(out[:, rows, :], oc.chi_rows(it, rows))
+    say(f"   sampled-row err={err:.3e}")
+    assert err <= TOL[prec]
+    herm = np.abs(out - np.conj(np.transpose(out, (0, 2, 1)))).max() / np.abs(out).max()
+    assert herm < (1e-12 if prec == "fp64" else 1e-5)
 
 
 @pytest.mark.parametrize("prec", PRECS)
