@@ -515,7 +515,9 @@ __global__ __launch_bounds__(256) void k_fft_pencils(FftLaunch L) {
 
 template <typename T, int S, int NC>
 hipError_t launch_fft_t(const FftLaunch &L, int lds_bytes, hipStream_t s) {
-  const int g1 = L.n_units_planes < 65536 ? L.n_units_planes : 65536;
+  // plane blocks: a grid of a few resident rounds that strides over the units
+  // (a unit above the diagonal of lower-triangle storage exits at once)
+  const int g1 = L.n_units_planes < 2048 ? L.n_units_planes : 2048;
   const int g2 = L.n_units_pencils < 65536 ? L.n_units_pencils : 65536;
   hipError_t e;
   if constexpr (NC > 0) {
