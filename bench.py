@@ -110,7 +110,12 @@ def main():
                          "of known size against which HBM byte counters are scaled)")
     ap.add_argument("--config", type=int, default=2,
                     help="workload configuration (2 is the headline; 1, 3, 4, 5 for the record)")
+    ap.add_argument("--autotune", type=int, default=None,
+                    help="time every GEMM tile on the workload before the warm-up and use the "
+                         "fastest (default: on for the k-point batch, configuration 3)")
     args = ap.parse_args()
+    if args.autotune is None:
+        args.autotune = 1 if args.config == 3 else 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is a design note only)", file=sys.stderr)
@@ -152,6 +157,10 @@ def main():
 
     paths = {}
     for prec in args.precisions.split(","):
+        if args.autotune:
+            t0 = time.perf_counter()
+            ctx.autotune(items, prec)
+            log(f"[bench] {prec}: autotuned GEMM tiles in {time.perf_counter() - t0:.1f} s")
         for _ in range(args.warmup):
             ctx.build_device(items, phis, outs, prec, stream=stream, report=True)
         torch.cuda.synchronize()
@@ -226,7 +235,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.config],
                    "precision": head, "hermitian": args.hermitian,
-                   "skip_zero_bands": args.skip_zero_bands},
+                   "skip_zero_bands": args.skip_zero_bands,
+                   "autotune": args.autotune},
         "ms_per_tau": H["ms_per_tau"],
         "speedup_vs_fp64": (paths["fp64"]["ms_per_step"] / H["ms_per_step"]) if "fp64" in paths else None,
         "err_vs_oracle": H.get("err_vs_oracle_sampled_rows"),
