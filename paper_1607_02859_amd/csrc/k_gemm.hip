@@ -539,7 +539,7 @@ hipError_t launch_one(const GemmLaunch &L, int grid, int num_cu, hipStream_t s) 
   return hipGetLastError();
 }
 
-// (precision, complex, wave tile M, wave tile N, K chunk, workgroups per CU,
+// (precision, complex, wave tile M, wave tile N, K chunk, minimum waves per SIMD,
 // rows of waves); entry 0 is the default.  Defaults come from timing every
 // entry on the 24^3 complex and the 24^3 real workloads.
 #define GW_TILES_FP64_C(X)                                                                     \
