@@ -127,8 +127,9 @@ typedef struct {
   int32_t hermitian;         /* 1 = compute only the lower block triangle of chi(r,r')
                                 and complete by Hermiticity (default 1)                 */
   int32_t persistent;        /* 1 = band-GEMM launches are persistent (resident
-                                workgroups take tiles by atomic ticket, most bands
-                                first); 0 = one workgroup per tile (default 1)          */
+                                workgroups take tiles by atomic ticket from per-XCD
+                                queues of tile groups, most bands first); 0 = one
+                                workgroup per tile (default 1)                          */
   int32_t kappa;             /* 1 = when a report is requested, also compute the
                                 norms behind kappa_F_max (default 1); 0 = report
                                 kappa_F_max = -1 and skip that pass                     */

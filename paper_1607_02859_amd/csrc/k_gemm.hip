@@ -99,7 +99,7 @@ __device__ __forceinline__ uint4 neg_bf8(uint4 q) {
 // consumed in chunks of KC bands.  The operand rows of one chunk (BM rows of
 // the tile, then BN rows of its columns) sit in LDS as rows of ROWB bytes made
 // of 16-byte slots; slot s of row r is stored at slot s ^ swz(r), so that the
-// lanes reading one slot of consecutive rows fall on distinct banks.  The LDS
+// lanes reading one slot of 16 consecutive rows fall on distinct banks.  The LDS
 // holds a ring of ST chunks, filled by direct global-to-LDS loads (1 KB per
 // wave instruction) ST - 1 chunks ahead of the MFMAs.
 template <int P, bool C, int WTM, int WTN, int KC, int WM, int OCC>
@@ -122,11 +122,16 @@ struct Tile {
                 "a stage must split into whole 1 KB loads per wave");
   static_assert(ST >= 2, "two stages must fit");
   static_assert(KC % M::KR == 0, "chunk must hold whole read rounds");
-  static_assert(SPR == 1 || SPR == 2 || SPR == 4 || SPR % 8 == 0, "row of 1, 2, 4 or 8k slots");
+  static_assert(SPR == 1 || SPR == 2 || SPR == 4 || SPR == 8 || SPR % 16 == 0,
+                "row of 1, 2, 4, 8 or 16k slots");
+  // A 16-byte LDS read serves 16 lanes per cycle from a 256-byte bank window;
+  // the 16 lanes read one logical slot of 16 consecutive rows, so the swizzle
+  // gives those rows 16 distinct slot positions within the window.
   static __device__ __forceinline__ int swz(int r) {
-    if constexpr (SPR >= 8) return r & 7;
-    else if constexpr (SPR == 4) return (r >> 1) & 3;
-    else if constexpr (SPR == 2) return (r >> 2) & 1;
+    if constexpr (SPR >= 16) return r & 15;
+    else if constexpr (SPR == 8) return (r >> 1) & 7;
+    else if constexpr (SPR == 4) return (r >> 2) & 3;
+    else if constexpr (SPR == 2) return (r >> 3) & 1;
     else return 0;
   }
   // byte offset of (row, logical slot) in a stage
