@@ -172,7 +172,8 @@ struct Gemm {
     sb = (uint32_t)((p ^ T::swz(row)) << 4);
   }
   // the loads of one chunk: base points at the chunk's first band of row 0,
-  // pitchB is the operand's row pitch in bytes
+  // pitchB is the operand's row pitch in bytes (row offsets in 64 bits: an
+  // operand can exceed 4 GB)
   static __device__ __forceinline__ void issue(const char *base, uint32_t pitchB,
                                                const uint32_t (&grow)[T::LPW],
                                                const uint32_t (&sb)[T::LPW], char *buf) {
@@ -180,7 +181,7 @@ struct Gemm {
     sfor<0, T::LPW>([&](auto tt) {
       constexpr int t = decltype(tt)::value;
       __builtin_amdgcn_global_load_lds(
-          (const __attribute__((address_space(1))) void *)(base + (grow[t] * pitchB + sb[t])),
+          (const __attribute__((address_space(1))) void *)(base + ((uint64_t)grow[t] * pitchB + sb[t])),
           (__attribute__((address_space(3))) void *)(buf + (w + t * T::NW) * 1024), 16, 0, 0);
     });
   }
