@@ -211,6 +211,36 @@ def test_cplx28_sampled_rows(ctx, prec):
     assert herm < (1e-12 if prec == "fp64" else 1e-5)
 
 
+# Degenerate shapes: one occupied and one unoccupied band, one tau point, two
+# plane waves, and grids far smaller than one GEMM tile.
+DEGENERATE = {
+    "one_pair_two_pw": lambda: synth.make_item(111, (3, 4, 5), 1, 1, True, 1, x_min=1.0, n_g=2),
+    "real_tiny": lambda: synth.make_item(112, (3, 3, 3), 1, 2, False, 2, x_min=1.0, n_g=5),
+    "one_occ": lambda: synth.make_item(113, (6, 6, 6), 1, 3, True, 2, x_min=1.0),
+}
+_DEG = {}
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("herm", [0, 1])
+@pytest.mark.parametrize("name", list(DEGENERATE))
+def test_degenerate_shapes(ctx, name, herm, prec):
+    if name not in _DEG:
+        it = DEGENERATE[name]()
+        _DEG[name] = (it, oc.chi_omega(it))
+    it, ref = _DEG[name]
+    ctx.set_options(use_graph=1, hermitian=herm, skip_zero_bands=0, slab_width=0, tile_id=0)
+    out = ctx.build([it], prec)[0]
+    err = oc.rel_frobenius(out, ref)
+    say(f"[degenerate] case={name} herm={herm} prec={prec} err={err:.3e}")
+    assert err <= TOL[prec]
+    # the G = 0 row and column vanish (orthonormal orbitals), up to the
+    # rounding level of the path
+    scale = np.abs(ref).max()
+    assert np.abs(out[:, 0, :]).max() <= 10 * TOL[prec] * scale
+    assert np.abs(out[:, :, 0]).max() <= 10 * TOL[prec] * scale
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_multi_pass_bitwise(ctx, prec):
     """Jobs split over several passes (an item's taus straddling passes, the
