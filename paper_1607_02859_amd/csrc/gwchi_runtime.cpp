@@ -1315,7 +1315,7 @@ gwchi_status gwchi_create(gwchi_ctx **out, int32_t device_id, const char *tune_c
       return GWCHI_EDEVICE;
     }
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
-      g_tls_error = std::string("device is ") + prop.gcnArchName + ", this build targets gfx950";
+      g_tls_error = std::string("device is ") + prop.gcnArchName + ", libgwchi is compiled for gfx950 only";
       return GWCHI_EDEVICE;
     }
     std::unique_ptr<gwchi_ctx> ctx(new gwchi_ctx());
