@@ -551,13 +551,17 @@ void emit_fft(Built &B, const Plan &P, std::vector<FftJob> &jobs, int phase, int
     F.fft.in_real = in_real;
     F.fft.lower_only = lower_only;
     // the jobs of a launch are all column-grouped or all contiguous along r
-    // with unit stride (the two layouts the cubic kernels read); anything
-    // else is refused at launch (fft_cubic = -1)
+    // with unit stride (the two layouts the cubic kernels read; contiguous
+    // input is complex, its columns start 16-byte aligned, so FP32 reads two
+    // points at a time); anything else is refused at launch (fft_cubic = -1)
     F.fft.grouped = 1;
     for (auto &f : fj) F.fft.grouped &= f.s_col == 0 ? 1 : 0;
     bool layout_ok = true;
     for (auto &f : fj)
-      if (!F.fft.grouped && (f.s_col == 0 || f.s_r != 1 || lower_only)) layout_ok = false;
+      if (!F.fft.grouped &&
+          (f.s_col == 0 || f.s_r != 1 || lower_only || in_real || (f.s_col & 1) ||
+           (reinterpret_cast<uintptr_t>(f.in) & 15)))
+        layout_ok = false;
     F.fft_sign = sign;
     F.fft_lds = lds;
     F.fft_cubic = (n0 == n1 && n1 == n2) ? n0 : 0;

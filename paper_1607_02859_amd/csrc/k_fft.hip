@@ -422,14 +422,34 @@ void k_fft_planes_c(FftLaunch L) {
       // writes one LDS run; then each thread reads its line from LDS
       const int k = tid % C, rl1 = tid / C;
       const bool ok_k = c0 + k < J.n_cols;
-      const int64_t e1 = ok_k ? (int64_t)p0 * plane + rl1 + (int64_t)(c0 + k) * J.s_col : 0;
+      if constexpr (sizeof(T) == 4) {
+        // complex FP32: two adjacent points per 16-byte load (n even, so the
+        // column starts and the point pairs are 16-byte aligned)
+        const int64_t e1 = ok_k ? (int64_t)p0 * plane + 2 * rl1 + (int64_t)(c0 + k) * J.s_col : 0;
+        const float4 *in4 = reinterpret_cast<const float4 *>(reinterpret_cast<const cx<T> *>(J.in) + e1);
 #pragma unroll
-      for (int i = 0; i < NC; ++i) {
-        const cx<T> x = load(e1 + i * (P * NC));
-        v[i] = ok_k ? x : cx<T>{(T)0, (T)0};
+        for (int i = 0; i < NC / 2; ++i) {
+          typedef float f4 __attribute__((ext_vector_type(4)));
+          const f4 q = ((const __attribute__((address_space(1))) f4 *)in4)[i * (P * NC)];
+          v[2 * i] = ok_k ? cx<T>{q.x, q.y} : cx<T>{(T)0, (T)0};
+          v[2 * i + 1] = ok_k ? cx<T>{q.z, q.w} : cx<T>{(T)0, (T)0};
+        }
+#pragma unroll
+        for (int i = 0; i < NC / 2; ++i) {
+          const int rl = 2 * (rl1 + i * (P * NC));
+          buf[li(rl, k)] = v[2 * i];
+          buf[li(rl + 1, k)] = v[2 * i + 1];
+        }
+      } else {
+        const int64_t e1 = ok_k ? (int64_t)p0 * plane + rl1 + (int64_t)(c0 + k) * J.s_col : 0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+          const cx<T> x = load(e1 + i * (P * NC));
+          v[i] = ok_k ? x : cx<T>{(T)0, (T)0};
+        }
+#pragma unroll
+        for (int i = 0; i < NC; ++i) buf[li(rl1 + i * (P * NC), k)] = v[i];
       }
-#pragma unroll
-      for (int i = 0; i < NC; ++i) buf[li(rl1 + i * (P * NC), k)] = v[i];
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < NC; ++i) v[i] = buf[li(rl0 + i, cc)];
