@@ -38,6 +38,9 @@ __all__ = [
     "make_config",
     "CONFIGS",
     "algorithmic_flops",
+    "WItem",
+    "coulomb_sqrt",
+    "make_w_item",
 ]
 
 
@@ -304,3 +307,76 @@ def algorithmic_flops(item: Item) -> float:
     2 N_r^2 K (real), K = n_occ + n_unocc."""
     per = 8.0 if item.is_complex else 2.0
     return per * item.n_r ** 2 * (item.n_occ + item.n_unocc) * item.n_tau
+
+
+# ----------------------------------------------------------------------------
+# Inputs of the screened-interaction step (W~ from chi)
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class WItem:
+    """One screened-interaction problem: chi(G, G', i omega_k) of one k-point,
+    the square root of the Coulomb kernel per plane wave and the forward
+    cosine matrix of the same grid (``ct[k][j]``, square)."""
+
+    chi: np.ndarray          # (n_omega, n_g, n_g) complex128, Hermitian negative semidefinite
+    sqrt_v: np.ndarray       # (n_g,) float64, >= 0
+    ct: np.ndarray           # (n_omega, n_tau) float64, n_tau == n_omega
+    omega: np.ndarray        # (n_omega,)
+
+    @property
+    def n_g(self) -> int:
+        return self.chi.shape[1]
+
+    @property
+    def n_omega(self) -> int:
+        return self.chi.shape[0]
+
+    @property
+    def n_tau(self) -> int:
+        return self.ct.shape[1]
+
+
+def coulomb_sqrt(n: Sequence[int], g_index: np.ndarray, alpha: float = 1.0,
+                 k: Sequence[float] = (0.0, 0.0, 0.0)) -> np.ndarray:
+    """alpha / |k + m| per plane wave, m the integer vector of the flat FFT index
+    (cubic cell in units where the reciprocal lattice vectors are unit
+    vectors), and 0 where k + m = 0 (the G = 0 term at k = 0 is dropped)."""
+    n0, n1, n2 = (int(v) for v in n)
+    g = np.asarray(g_index, dtype=np.int64)
+    k0, rem = np.divmod(g, n1 * n2)
+    k1, k2 = np.divmod(rem, n2)
+
+    def signed(kd, nd):
+        return np.where(kd > nd // 2, kd - nd, kd).astype(np.float64)
+
+    q = np.stack([signed(k0, n0) + k[0], signed(k1, n1) + k[1], signed(k2, n2) + k[2]], axis=1)
+    norm = np.sqrt((q * q).sum(axis=1))
+    out = np.zeros(g.shape[0])
+    nz = norm > 0
+    out[nz] = alpha / norm[nz]
+    return out
+
+
+def make_w_item(seed, n, n_tau, *, rank=None, strength=1.0, alpha=1.0,
+                x_min=0.5, x_max=50.0) -> WItem:
+    """Seeded chi(i omega_k) of the shape the polarizability build returns:
+    Hermitian, negative semidefinite, decaying with omega.  It is a sum of
+    ``rank`` (default n_g / 4) rank-one terms -b_m b_m^H with Lorentzian weights
+    x_m^2 / (x_m^2 + omega_k^2), x_m log-spaced in [x_min, x_max]; the plane
+    waves are the sphere of grid ``n`` and ``sqrt_v`` is ``coulomb_sqrt`` at
+    k = 0.  ``strength`` scales chi; the dielectric matrix stays positive
+    definite for any strength >= 0."""
+    g_index = g_sphere(n)
+    n_g = g_index.shape[0]
+    rank = n_g // 4 if rank is None else int(rank)
+    rng = np.random.default_rng(seed)
+    tau, omega, ct, _ = ct_grid(n_tau, x_min, x_max)
+    b = (rng.standard_normal((n_g, rank)) + 1j * rng.standard_normal((n_g, rank))) / math.sqrt(2.0 * n_g)
+    x = np.exp(np.linspace(math.log(x_min), math.log(x_max), rank))
+    chi = np.empty((omega.shape[0], n_g, n_g), dtype=np.complex128)
+    for kk, w in enumerate(omega):
+        lw = strength * x * x / (x * x + w * w)
+        chi[kk] = -(b * lw[None, :]) @ b.conj().T
+        chi[kk] = 0.5 * (chi[kk] + chi[kk].conj().T)
+    return WItem(chi=chi, sqrt_v=coulomb_sqrt(n, g_index, alpha), ct=ct, omega=omega)
