@@ -174,6 +174,69 @@ gwchi_status gwchi_chi_build_device(gwchi_ctx *ctx, const gwchi_item *items, int
 gwchi_status gwchi_autotune(gwchi_ctx *ctx, const gwchi_item *items, int32_t n_items,
                             gwchi_precision prec);
 
+/* ------------------------------------------------------------------------
+ * Screened interaction W~ from chi (Sec. II.C steps (iii)-(iv)), FP64.
+ *
+ * For one k-point, every imaginary frequency omega_k and the symmetric
+ * Coulomb kernel v(G, G') = s(G) s(G') of Eq. (47):
+ *
+ *   eps(G,G')        = delta_GG' - v(G,G') chi(G,G',i omega_k)        (Eq. (48))
+ *   W~(G,G',i w_k)   = v(G,G') (eps^-1(G,G') - delta_GG')   (Eqs. (46), (49):
+ *                      W minus its bare Coulomb part v(G) delta_GG')
+ *   W~(G,G',i tau_j) = sum_k xi_jk cos(tau_j omega_k) W~(G,G',i omega_k)  (Eq. (50))
+ *
+ * where the matrix xi cos(tau omega) is the inverse of the forward cosine
+ * matrix ct[k][j] = gamma_kj cos(omega_k tau_j) (Eq. (6)); the library
+ * inverts ct on the host in FP64.  eps must be Hermitian positive definite,
+ * which holds when chi(i omega) is Hermitian negative semidefinite (as the
+ * build above returns it); it is inverted without pivoting.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t n_g;              /* >= 1, at most 65535                                       */
+  int32_t n_omega;          /* >= 1                                                      */
+  int32_t n_tau;            /* == n_omega (square grid), at most 32                      */
+  /* chi[k][g][g'] complex interleaved FP64, [n_omega][n_g][n_g] (the chi_out
+   * layout of the polarizability build).  gwchi_w_build: host memory;
+   * gwchi_w_build_device: device memory.  Read only. */
+  const double *chi;
+  const double *sqrt_v;     /* [n_g] s(G) = sqrt(4 pi e^2) / |k + G| >= 0, finite; 0 drops the
+                               plane wave (e.g. G = 0 at k = 0); host memory               */
+  const double *ct;         /* [n_omega][n_tau] row-major, as gwchi_item.ct; host memory   */
+  /* Outputs, complex interleaved FP64, same memory kind as chi:
+   * w_tau_out [n_tau][n_g][n_g] (required), w_omega_out [n_omega][n_g][n_g]
+   * (W~(i omega_k); may be NULL). */
+  double *w_tau_out;
+  double *w_omega_out;
+} gwchi_w_item;
+
+typedef struct {
+  double ms_total;          /* stream time of the whole call                            */
+  double ms_eps;            /* dielectric matrices                                      */
+  double ms_invert;         /* blocked Gauss-Jordan inversion                           */
+  double ms_final;          /* W~(i omega) and the inverse cosine transform             */
+  double alg_flops;         /* 8 n_g^3 per matrix (complex inversion), summed           */
+  int32_t n_launches;       /* kernel launches of the call                              */
+} gwchi_w_report;
+
+/* Host-only check of W items (no device is touched): the EINVAL cases of
+ * gwchi_w_build below. */
+gwchi_status gwchi_w_validate(const gwchi_w_item *items, int32_t n_items);
+
+/* W~(i tau) (and optionally W~(i omega)) for every item; host buffers in and
+ * out.  Blocking.  EINVAL on null pointers, n_g < 1 or > 65535, n_tau !=
+ * n_omega, n_tau > 32, negative or non-finite sqrt_v, non-finite or singular
+ * ct; ENUMERIC when a pivot of eps is not positive (eps not positive
+ * definite; outputs unspecified).  report may be NULL. */
+gwchi_status gwchi_w_build(gwchi_ctx *ctx, const gwchi_w_item *items, int32_t n_items,
+                           gwchi_w_report *report);
+
+/* Same with chi, w_tau_out and w_omega_out in device memory of the context's
+ * device; sqrt_v and ct in host memory.  Enqueued on hip_stream (NULL = the
+ * context's stream); returns once enqueued unless report is non-NULL, in
+ * which case it waits, fills the report and checks the pivots (ENUMERIC). */
+gwchi_status gwchi_w_build_device(gwchi_ctx *ctx, const gwchi_w_item *items, int32_t n_items,
+                                  void *hip_stream, gwchi_w_report *report);
+
 /* Message of the last failure on this context (never NULL). */
 const char *gwchi_last_error(const gwchi_ctx *ctx);
 

@@ -27,8 +27,10 @@ imaginary frequency omega_k, from chi(G, G', i omega_k):
    gamma cos(omega tau) of Eq. (4) (stated with Eq. (6)); the grids are
    square (N tau points, N frequencies).
 
-The inverse is a library routine (numpy.linalg.inv) used as one step.
-Pins (tests/test_oracle_pins.py): the Dyson equation by matrix products
+The inverse is a library routine (numpy.linalg.inv) used as one step;
+``w_tilde_rows`` gives selected rows of the same result through linear solves
+(numpy.linalg.solve) for sizes where full inverses on the CPU are slow.
+Pins (tests/test_oracle_w_pins.py): the Dyson equation by matrix products
 only, the closed form for a diagonal chi, Hermiticity and negative
 semidefiniteness of W~(i omega) for a Hermitian negative semidefinite chi,
 and the inverse transform against the exact Laplace pair exp(-x tau) <->
@@ -38,7 +40,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["inverse_ct", "coulomb_kernel", "w_tilde_omega", "w_tilde_tau"]
+__all__ = ["inverse_ct", "coulomb_kernel", "w_tilde_omega", "w_tilde_tau", "w_tilde_rows"]
 
 
 def inverse_ct(ct: np.ndarray) -> np.ndarray:
@@ -82,3 +84,28 @@ def w_tilde_tau(chi_w: np.ndarray, s: np.ndarray, ct: np.ndarray, return_omega=F
         for k in range(n_omega):                     # summed in increasing k
             out[j] += ict[j, k] * w_w[k]
     return (out, w_w) if return_omega else out
+
+
+def w_tilde_rows(chi_w: np.ndarray, s: np.ndarray, ct: np.ndarray, rows) -> np.ndarray:
+    """Rows ``rows`` of W~(G, G', i tau_j) for every j, shape [n_tau][len(rows)][n_g].
+
+    Row g of eps^-1 is e_g^T eps^-1 = (eps^-T e_g)^T, one linear solve per
+    frequency for all selected rows; then Eqs. (46), (49) and (50) as above."""
+    chi_w = np.asarray(chi_w, dtype=np.complex128)
+    s = np.asarray(s, dtype=np.float64)
+    rows = np.asarray(rows, dtype=np.int64)
+    n_g = s.shape[0]
+    v = coulomb_kernel(s)
+    e = np.zeros((n_g, rows.shape[0]))
+    e[rows, np.arange(rows.shape[0])] = 1.0
+    w_w = np.empty((chi_w.shape[0], rows.shape[0], n_g), dtype=np.complex128)
+    for k in range(chi_w.shape[0]):
+        eps = np.eye(n_g) - v * chi_w[k]                            # Eq. (48)
+        inv_rows = np.linalg.solve(eps.T, e).T                      # rows of eps^-1
+        w_w[k] = v[rows] * inv_rows - v[rows] * e.T                 # Eqs. (46), (49)
+    ict = inverse_ct(ct)
+    out = np.zeros((ict.shape[0],) + w_w.shape[1:], dtype=np.complex128)
+    for j in range(ict.shape[0]):
+        for k in range(ict.shape[1]):                               # Eq. (50)
+            out[j] += ict[j, k] * w_w[k]
+    return out

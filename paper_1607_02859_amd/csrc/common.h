@@ -226,4 +226,21 @@ hipError_t launch_norms_impl(const CtLaunch &L, int dbl, int mode, double *norm_
                              const int32_t *omega_off, int max_mats, hipStream_t s);
 hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Screened interaction from chi (FP64): eps = I - s chi s, its inverse by a
+// blocked Gauss-Jordan exchange of kWBlock pivots per step, then W~(i omega)
+// and the inverse cosine transform.  Matrices [n_mat][n][n] complex.
+// ---------------------------------------------------------------------------
+constexpr int kWBlock = 32;
+constexpr int kWMaxTau = 32;
+hipError_t launch_w_eps(const void *chi, const double *s, void *a, int n, int n_mat,
+                        hipStream_t st);
+// one pivot block at P0: dinv [n_mat][kWBlock][kWBlock], rp [n_mat][kWBlock][n],
+// cp [n_mat][n][kWBlock]; *flag is set when a pivot is not positive
+hipError_t launch_w_block(void *a, void *dinv, void *rp, void *cp, int n, int n_mat, int P0,
+                          int *flag, hipStream_t st);
+// ict [n_tau][n_omega]; w_omega may be null; n_tau <= kWMaxTau
+hipError_t launch_w_final(const void *a, const double *s, const double *ict, void *w_tau,
+                          void *w_omega, int n, int n_omega, int n_tau, hipStream_t st);
+
 }  // namespace gw

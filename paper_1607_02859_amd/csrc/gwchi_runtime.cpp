@@ -118,6 +118,10 @@ struct gwchi_ctx {
   std::string tune_path;
   std::map<std::string, int> tune;   // key -> tile index
   DevBuf b_phi, b_out, b_psi, b_slab, b_xr, b_x, b_tmp, b_tables, b_norm, b_ctr;
+  // screened-interaction step: chi / outputs of the host entry, the matrices
+  // being inverted, the pivot-block panels, the per-item tables, the pivot flag
+  DevBuf b_wchi, b_wtau, b_womega, b_wa, b_wdinv, b_wrp, b_wcp, b_wtab, b_wflag;
+  HostPinned h_wtab;
   HostPinned h_tables, h_norm;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::vector<hipEvent_t> ev_pool;
@@ -1275,6 +1279,200 @@ gwchi_status upload_items(gwchi_ctx *ctx, const gwchi_item *items, int n_items,
   return GWCHI_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Screened interaction W~ from chi (Sec. II.C steps (iii)-(iv)).
+// ---------------------------------------------------------------------------
+
+// Inverse of the n x n row-major matrix a by Gauss-Jordan elimination with
+// partial pivoting, in FP64 (the inverse cosine matrix of Eq. (6)); false
+// when a pivot falls below 1e-13 n max|a| (numerically singular) or the
+// result is not finite.
+bool invert_small(const double *a, int n, std::vector<double> &inv) {
+  std::vector<double> m(a, a + (size_t)n * n);
+  double scale = 0.0;
+  for (double x : m) scale = std::max(scale, std::fabs(x));
+  const double tiny = 1e-13 * n * scale;
+  inv.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    double best = std::fabs(m[(size_t)c * n + c]);
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(m[(size_t)r * n + c]) > best) {
+        best = std::fabs(m[(size_t)r * n + c]);
+        piv = r;
+      }
+    if (!(best > tiny) || !std::isfinite(best)) return false;
+    if (piv != c)
+      for (int k = 0; k < n; ++k) {
+        std::swap(m[(size_t)c * n + k], m[(size_t)piv * n + k]);
+        std::swap(inv[(size_t)c * n + k], inv[(size_t)piv * n + k]);
+      }
+    const double d = 1.0 / m[(size_t)c * n + c];
+    for (int k = 0; k < n; ++k) {
+      m[(size_t)c * n + k] *= d;
+      inv[(size_t)c * n + k] *= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = m[(size_t)r * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) {
+        m[(size_t)r * n + k] -= f * m[(size_t)c * n + k];
+        inv[(size_t)r * n + k] -= f * inv[(size_t)c * n + k];
+      }
+    }
+  }
+  return finite_all(inv.data(), (int64_t)n * n);
+}
+
+// Host checks of the items; fills the inverse cosine matrix of each item.
+gwchi_status validate_w_items(gwchi_ctx *ctx, const gwchi_w_item *items, int32_t n_items,
+                              std::vector<std::vector<double>> &ict) {
+  if (!items || n_items < 1) {
+    set_err(ctx, "items is NULL or n_items < 1");
+    return GWCHI_EINVAL;
+  }
+  ict.assign(n_items, {});
+  for (int t = 0; t < n_items; ++t) {
+    const gwchi_w_item &it = items[t];
+    const std::string at = "w item " + std::to_string(t) + ": ";
+    if (!it.chi || !it.sqrt_v || !it.ct || !it.w_tau_out) {
+      set_err(ctx, at + "chi, sqrt_v, ct and w_tau_out must not be NULL");
+      return GWCHI_EINVAL;
+    }
+    if (it.n_g < 1 || it.n_g > 65535) {
+      set_err(ctx, at + "n_g must be in [1, 65535]");
+      return GWCHI_EINVAL;
+    }
+    if (it.n_omega < 1 || it.n_tau != it.n_omega || it.n_tau > kWMaxTau) {
+      set_err(ctx, at + "n_tau must equal n_omega, in [1, " + std::to_string(kWMaxTau) + "]");
+      return GWCHI_EINVAL;
+    }
+    for (int g = 0; g < it.n_g; ++g)
+      if (!(it.sqrt_v[g] >= 0.0) || !std::isfinite(it.sqrt_v[g])) {
+        set_err(ctx, at + "sqrt_v must be finite and >= 0");
+        return GWCHI_EINVAL;
+      }
+    if (!finite_all(it.ct, (int64_t)it.n_omega * it.n_tau)) {
+      set_err(ctx, at + "ct is not finite");
+      return GWCHI_EINVAL;
+    }
+    if (!invert_small(it.ct, it.n_tau, ict[t])) {
+      set_err(ctx, at + "ct is singular");
+      return GWCHI_EINVAL;
+    }
+  }
+  return GWCHI_OK;
+}
+
+// Enqueue W~ for items whose chi and outputs are device pointers, on the
+// context's stream.  With a report: wait, fill it and check the pivot flag.
+gwchi_status run_w(gwchi_ctx *ctx, const gwchi_w_item *items, int n_items,
+                   const std::vector<std::vector<double>> &ict, gwchi_w_report *rep) {
+  hipStream_t st = ctx->stream;
+  int64_t a_b = 0, p_b = 0, d_b = 0, tab = 0;
+  std::vector<int64_t> toff(n_items);
+  for (int t = 0; t < n_items; ++t) {
+    const gwchi_w_item &it = items[t];
+    const int64_t n = it.n_g, K = it.n_omega;
+    a_b = std::max(a_b, K * n * n * 16);
+    p_b = std::max(p_b, K * kWBlock * n * 16);
+    d_b = std::max(d_b, K * kWBlock * kWBlock * 16);
+    toff[t] = tab;
+    tab += round_up(n + (int64_t)it.n_tau * it.n_omega, 32);
+  }
+  HIPCHK(ctx->b_wa.ensure(a_b, nullptr));
+  HIPCHK(ctx->b_wrp.ensure(p_b, nullptr));
+  HIPCHK(ctx->b_wcp.ensure(p_b, nullptr));
+  HIPCHK(ctx->b_wdinv.ensure(d_b, nullptr));
+  HIPCHK(ctx->b_wtab.ensure(tab * 8, nullptr));
+  HIPCHK(ctx->b_wflag.ensure(256, nullptr));
+  // the pinned staging buffer may still feed an earlier call's copy
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(ctx->h_wtab.ensure(tab * 8));
+  double *h = reinterpret_cast<double *>(ctx->h_wtab.p);
+  for (int t = 0; t < n_items; ++t) {
+    const gwchi_w_item &it = items[t];
+    std::memcpy(h + toff[t], it.sqrt_v, (size_t)it.n_g * 8);
+    std::memcpy(h + toff[t] + it.n_g, ict[t].data(), ict[t].size() * 8);
+  }
+  HIPCHK(hipMemcpyAsync(ctx->b_wtab.p, h, tab * 8, hipMemcpyHostToDevice, st));
+  int *flag = reinterpret_cast<int *>(ctx->b_wflag.p);
+  HIPCHK(launch_fill_zero(flag, 256, st));
+  int launches = 1;
+  std::vector<hipEvent_t> ev;
+  auto mark = [&]() -> gwchi_status {
+    if (!rep) return GWCHI_OK;
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    ev.push_back(e);
+    HIPCHK(hipEventRecord(e, st));
+    return GWCHI_OK;
+  };
+  auto cleanup = [&]() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  };
+  gwchi_status s0 = mark();
+  if (s0 != GWCHI_OK) return cleanup(), s0;
+  double flops = 0.0;
+  for (int t = 0; t < n_items; ++t) {
+    const gwchi_w_item &it = items[t];
+    const int n = it.n_g, K = it.n_omega;
+    const double *s_dev = reinterpret_cast<const double *>(ctx->b_wtab.p) + toff[t];
+    const double *ict_dev = s_dev + n;
+    hipError_t e = launch_w_eps(it.chi, s_dev, ctx->b_wa.p, n, K, st);
+    ++launches;
+    if (e == hipSuccess && (s0 = mark()) != GWCHI_OK) return cleanup(), s0;
+    for (int p0 = 0; e == hipSuccess && p0 < n; p0 += kWBlock) {
+      e = launch_w_block(ctx->b_wa.p, ctx->b_wdinv.p, ctx->b_wrp.p, ctx->b_wcp.p, n, K, p0, flag, st);
+      launches += 3;
+    }
+    if (e == hipSuccess && (s0 = mark()) != GWCHI_OK) return cleanup(), s0;
+    if (e == hipSuccess)
+      e = launch_w_final(ctx->b_wa.p, s_dev, ict_dev, it.w_tau_out, it.w_omega_out, n, K,
+                         it.n_tau, st);
+    ++launches;
+    if (e != hipSuccess) {
+      cleanup();
+      set_err(ctx, std::string("W~ launch: ") + hipGetErrorString(e));
+      return GWCHI_EDEVICE;
+    }
+    if ((s0 = mark()) != GWCHI_OK) return cleanup(), s0;
+    flops += 8.0 * (double)n * n * n * K;
+  }
+  if (!rep) return GWCHI_OK;
+  hipError_t e = hipStreamSynchronize(st);
+  gwchi_w_report r{};
+  r.alg_flops = flops;
+  r.n_launches = launches;
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev.front(), ev.back());
+  r.ms_total = ms;
+  for (int t = 0; t < n_items && e == hipSuccess; ++t) {
+    float a = 0.f, b = 0.f, c = 0.f;
+    e = hipEventElapsedTime(&a, ev[3 * t], ev[3 * t + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[3 * t + 1], ev[3 * t + 2]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&c, ev[3 * t + 2], ev[3 * t + 3]);
+    r.ms_eps += a;
+    r.ms_invert += b;
+    r.ms_final += c;
+  }
+  int hflag = 0;
+  if (e == hipSuccess) e = hipMemcpy(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost);
+  cleanup();
+  if (e != hipSuccess) {
+    set_err(ctx, std::string("W~: ") + hipGetErrorString(e));
+    return GWCHI_EDEVICE;
+  }
+  *rep = r;
+  if (hflag) {
+    set_err(ctx, "W~: a pivot of the dielectric matrix is not positive (eps is not positive definite)");
+    return GWCHI_ENUMERIC;
+  }
+  return GWCHI_OK;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -1357,9 +1555,12 @@ gwchi_status gwchi_destroy(gwchi_ctx *ctx) {
   if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
   if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
   for (DevBuf *b : {&ctx->b_phi, &ctx->b_out, &ctx->b_psi, &ctx->b_slab, &ctx->b_xr, &ctx->b_x,
-                    &ctx->b_tmp, &ctx->b_tables, &ctx->b_norm, &ctx->b_ctr})
+                    &ctx->b_tmp, &ctx->b_tables, &ctx->b_norm, &ctx->b_ctr, &ctx->b_wchi,
+                    &ctx->b_wtau, &ctx->b_womega, &ctx->b_wa, &ctx->b_wdinv, &ctx->b_wrp,
+                    &ctx->b_wcp, &ctx->b_wtab, &ctx->b_wflag})
     b->release();
   ctx->h_tables.release();
+  ctx->h_wtab.release();
   ctx->h_norm.release();
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -1491,6 +1692,93 @@ gwchi_status gwchi_autotune(gwchi_ctx *ctx, const gwchi_item *items, int32_t n_i
     ctx->tune[tune_key((int)prec, cplx)] = best_t;
     save_tune(ctx);
     return GWCHI_OK;
+  } catch (...) {
+    set_err(ctx, "internal error");
+    return GWCHI_EDEVICE;
+  }
+}
+
+gwchi_status gwchi_w_validate(const gwchi_w_item *items, int32_t n_items) {
+  try {
+    std::vector<std::vector<double>> ict;
+    return validate_w_items(nullptr, items, n_items, ict);
+  } catch (...) {
+    g_tls_error = "internal error";
+    return GWCHI_EDEVICE;
+  }
+}
+
+gwchi_status gwchi_w_build_device(gwchi_ctx *ctx, const gwchi_w_item *items, int32_t n_items,
+                                  void *hip_stream, gwchi_w_report *report) {
+  if (!ctx) {
+    g_tls_error = "ctx is NULL";
+    return GWCHI_EINVAL;
+  }
+  try {
+    std::vector<std::vector<double>> ict;
+    gwchi_status st = validate_w_items(ctx, items, n_items, ict);
+    if (st != GWCHI_OK) return st;
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t us = reinterpret_cast<hipStream_t>(hip_stream);
+    HIPCHK(hipEventRecord(ctx->ev_in, us));
+    HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->ev_in, 0));
+    st = run_w(ctx, items, n_items, ict, report);
+    if (st != GWCHI_OK) return st;
+    HIPCHK(hipEventRecord(ctx->ev_out, ctx->stream));
+    HIPCHK(hipStreamWaitEvent(us, ctx->ev_out, 0));
+    return GWCHI_OK;
+  } catch (const std::bad_alloc &) {
+    set_err(ctx, "host allocation failed");
+    return GWCHI_ENOMEM;
+  } catch (...) {
+    set_err(ctx, "internal error");
+    return GWCHI_EDEVICE;
+  }
+}
+
+gwchi_status gwchi_w_build(gwchi_ctx *ctx, const gwchi_w_item *items, int32_t n_items,
+                           gwchi_w_report *report) {
+  if (!ctx) {
+    g_tls_error = "ctx is NULL";
+    return GWCHI_EINVAL;
+  }
+  try {
+    std::vector<std::vector<double>> ict;
+    gwchi_status st = validate_w_items(ctx, items, n_items, ict);
+    if (st != GWCHI_OK) return st;
+    HIPCHK(hipSetDevice(ctx->device));
+    gwchi_w_report total{};
+    // one item at a time through the context's device buffers
+    for (int t = 0; t < n_items; ++t) {
+      const gwchi_w_item &it = items[t];
+      const size_t in_b = (size_t)it.n_omega * it.n_g * it.n_g * 16;
+      const size_t tau_b = (size_t)it.n_tau * it.n_g * it.n_g * 16;
+      HIPCHK(ctx->b_wchi.ensure(in_b, nullptr));
+      HIPCHK(ctx->b_wtau.ensure(tau_b, nullptr));
+      if (it.w_omega_out) HIPCHK(ctx->b_womega.ensure(in_b, nullptr));
+      HIPCHK(hipMemcpy(ctx->b_wchi.p, it.chi, in_b, hipMemcpyHostToDevice));
+      gwchi_w_item d = it;
+      d.chi = reinterpret_cast<const double *>(ctx->b_wchi.p);
+      d.w_tau_out = reinterpret_cast<double *>(ctx->b_wtau.p);
+      d.w_omega_out = it.w_omega_out ? reinterpret_cast<double *>(ctx->b_womega.p) : nullptr;
+      std::vector<std::vector<double>> one(1, ict[t]);
+      gwchi_w_report r{};
+      st = run_w(ctx, &d, 1, one, &r);
+      if (st != GWCHI_OK) return st;
+      HIPCHK(hipMemcpy(it.w_tau_out, d.w_tau_out, tau_b, hipMemcpyDeviceToHost));
+      if (it.w_omega_out) HIPCHK(hipMemcpy(it.w_omega_out, d.w_omega_out, in_b, hipMemcpyDeviceToHost));
+      total.ms_total += r.ms_total;
+      total.ms_eps += r.ms_eps;
+      total.ms_invert += r.ms_invert;
+      total.ms_final += r.ms_final;
+      total.alg_flops += r.alg_flops;
+      total.n_launches += r.n_launches;
+    }
+    if (report) *report = total;
+    return GWCHI_OK;
+  } catch (const std::bad_alloc &) {
+    set_err(ctx, "host allocation failed");
+    return GWCHI_ENOMEM;
   } catch (...) {
     set_err(ctx, "internal error");
     return GWCHI_EDEVICE;

@@ -1,0 +1,307 @@
+// Screened interaction from the polarizability (gfx950), FP64 throughout.
+//
+// For one k-point and every imaginary frequency omega_k (Sec. II.C steps
+// (iii)-(iv)), with v(G, G') = s(G) s(G') the symmetric Coulomb kernel of
+// Eq. (47):
+//   eps(G, G')   = delta_GG' - s(G) chi(G, G') s(G')             Eq. (48)
+//   W~(G, G')    = s(G) (eps^-1(G, G') - delta_GG') s(G')       Eqs. (46), (49)
+//   W~(i tau_j)  = sum_k ict[j][k] W~(i omega_k)                Eq. (50)
+// ict being the inverse of the forward cosine matrix (Eq. (6)).
+//
+// eps is Hermitian positive definite for a Hermitian negative semidefinite
+// chi (its eigenvalues are >= 1), so it is inverted in place by the
+// Gauss-Jordan exchange (sweep) without pivoting, in blocks of kWBlock
+// pivots.  Per block P = [P0, P0 + nb) of every matrix of the batch:
+//   k_w_diag   D^-1 of the diagonal block (one workgroup per matrix, LDS);
+//   k_w_panel  row panel R[p][j] = (D^-1 A[P, :])[p][j] for j outside P and
+//              D^-1 on P; column panel C[i][p] = A[i][P0 + p] for i outside P;
+//   k_w_update A[i][j] <- R[i - P0][j] for i in P, else
+//              A[i][j] * [j outside P] - sum_p C[i][p] R[p][j]
+//              (rank-nb update on FP64 MFMA, panels staged in LDS).
+// After the last block A holds eps^-1.  k_w_final then forms W~(i omega_k)
+// and the inverse cosine transform in one pass over the matrices.
+#include "common.h"
+
+namespace gw {
+namespace {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 csub(double2 a, double2 b) {
+  return make_double2(a.x - b.x, a.y - b.y);
+}
+__device__ __forceinline__ double2 cinv(double2 a) {
+  const double d = a.x * a.x + a.y * a.y;
+  return make_double2(a.x / d, -a.y / d);
+}
+
+constexpr int NB = kWBlock;
+
+// grid (ceil(n / 256), n, n_mat): a[m][g][h] = delta - s_g chi[m][g][h] s_h
+__global__ __launch_bounds__(256) void k_w_eps(const double2 *__restrict__ chi,
+                                               const double *__restrict__ s, double2 *__restrict__ a,
+                                               int n) {
+  const int h = blockIdx.x * 256 + threadIdx.x;
+  const int g = blockIdx.y;
+  if (h >= n) return;
+  const int64_t e = ((int64_t)blockIdx.z * n + g) * n + h;
+  const double sg = s[g] * s[h];
+  const double2 x = chi[e];
+  double2 y = make_double2(-sg * x.x, -sg * x.y);
+  if (g == h) y.x += 1.0;
+  a[e] = y;
+}
+
+// one workgroup per matrix: the exchange of the nb pivots of the diagonal
+// block at P0, in LDS; rows and columns past nb are the identity.  A pivot
+// whose real part is not positive and finite (eps not positive definite)
+// sets *flag.
+__global__ __launch_bounds__(256) void k_w_diag(const double2 *__restrict__ a,
+                                                double2 *__restrict__ dinv, int n, int P0,
+                                                int *flag) {
+  __shared__ double2 d[NB][NB + 1];
+  const int m = blockIdx.x;
+  const double2 *A = a + (int64_t)m * n * n;
+  const int nb = min(NB, n - P0);
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int i = e / NB, j = e % NB;
+    d[i][j] = (i < nb && j < nb) ? A[(int64_t)(P0 + i) * n + P0 + j]
+                                 : make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  constexpr int PER = NB * NB / 256;
+  for (int p = 0; p < nb; ++p) {
+    const double2 dpp = d[p][p];
+    if (threadIdx.x == 0 && !(dpp.x > 0.0 && dpp.x < 1.0e300)) atomicOr(flag, 1);
+    const double2 piv = cinv(dpp);
+    double2 nv[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int e = threadIdx.x + 256 * t;
+      const int i = e / NB, j = e % NB;
+      const double2 dip = d[i][p], dpj = d[p][j];
+      if (i != p && j != p) nv[t] = csub(d[i][j], cmul(cmul(dip, piv), dpj));
+      else if (i != p) {
+        const double2 x = cmul(dip, piv);
+        nv[t] = make_double2(-x.x, -x.y);
+      }
+      else if (j != p) nv[t] = cmul(piv, dpj);
+      else nv[t] = piv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int e = threadIdx.x + 256 * t;
+      d[e / NB][e % NB] = nv[t];
+    }
+    __syncthreads();
+  }
+  double2 *D = dinv + (int64_t)m * NB * NB;
+  for (int e = threadIdx.x; e < NB * NB; e += 256) D[e] = d[e / NB][e % NB];
+}
+
+// grid (ceil(n / 64), n_mat): for the 64 columns j0 .. j0 + 63 the row panel
+// rp[m][p][j] (layout [n_mat][NB][n]) and, for the rows i of the same range,
+// the column panel cp[m][i][p] (layout [n_mat][n][NB]); entries with p >= nb
+// are zero.
+__global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
+                                                 const double2 *__restrict__ dinv,
+                                                 double2 *__restrict__ rp, double2 *__restrict__ cp,
+                                                 int n, int P0) {
+  __shared__ double2 sd[NB][NB + 1];
+  __shared__ double2 sa[NB][64 + 1];
+  const int m = blockIdx.y;
+  const int j0 = blockIdx.x * 64;
+  const int nb = min(NB, n - P0);
+  const double2 *A = a + (int64_t)m * n * n;
+  const double2 *D = dinv + (int64_t)m * NB * NB;
+  for (int e = threadIdx.x; e < NB * NB; e += 256) sd[e / NB][e % NB] = D[e];
+  for (int e = threadIdx.x; e < NB * 64; e += 256) {
+    const int q = e / 64, c = e % 64, j = j0 + c;
+    sa[q][c] = (q < nb && j < n) ? A[(int64_t)(P0 + q) * n + j] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const int c = threadIdx.x % 64, p0 = threadIdx.x / 64;
+  const int j = j0 + c;
+  if (j < n) {
+    const bool in_p = j >= P0 && j < P0 + nb;
+    for (int p = p0; p < NB; p += 4) {
+      double2 val = make_double2(0.0, 0.0);
+      if (p < nb) {
+        if (in_p) {
+          val = sd[p][j - P0];
+        } else {
+          for (int q = 0; q < nb; ++q) {
+            const double2 x = cmul(sd[p][q], sa[q][c]);
+            val.x += x.x;
+            val.y += x.y;
+          }
+        }
+      }
+      rp[((int64_t)m * NB + p) * n + j] = val;
+    }
+  }
+  for (int e = threadIdx.x; e < 64 * NB; e += 256) {
+    const int r = e / NB, p = e % NB, i = j0 + r;
+    if (i >= n) continue;
+    const bool in_p = i >= P0 && i < P0 + nb;
+    cp[((int64_t)m * n + i) * NB + p] =
+        (p < nb && !in_p) ? A[(int64_t)i * n + P0 + p] : make_double2(0.0, 0.0);
+  }
+}
+
+// grid (ceil(n / 64), ceil(n / 64), n_mat): 64 x 64 tile (rows i0.., columns
+// j0..) of the rank-nb update.  Four waves, each a 32 x 32 quarter as 2 x 2
+// blocks of v_mfma_f64_16x16x4 (lane l holds A-operand row l % 16, B-operand
+// column l % 16, band l / 16 of the step; result value v of lane l is row
+// l / 16 + 4 v, column l % 16).  The C rows are padded to NB + 1 entries so
+// that the 16 lanes reading one band of 16 rows hit distinct LDS banks.
+__global__ __launch_bounds__(256) void k_w_update(double2 *__restrict__ a,
+                                                  const double2 *__restrict__ rp,
+                                                  const double2 *__restrict__ cp, int n, int P0) {
+  __shared__ double2 sc[64][NB + 1];
+  __shared__ double2 sr[NB][64];
+  const int m = blockIdx.z;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int nb = min(NB, n - P0);
+  double2 *A = a + (int64_t)m * n * n;
+  for (int e = threadIdx.x; e < 64 * NB; e += 256) {
+    const int r = e / NB, p = e % NB, i = i0 + r;
+    sc[r][p] = i < n ? cp[((int64_t)m * n + i) * NB + p] : make_double2(0.0, 0.0);
+  }
+  for (int e = threadIdx.x; e < NB * 64; e += 256) {
+    const int p = e / 64, c = e % 64, j = j0 + c;
+    sr[p][c] = j < n ? rp[((int64_t)m * NB + p) * n + j] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int wr = w >> 1, wc = w & 1;
+  d4v re[2][2], im[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) re[bi][bj] = im[bi][bj] = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < NB; k += 4) {
+    double2 x[2], y[2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) x[bi] = sc[wr * 32 + bi * 16 + (l & 15)][k + (l >> 4)];
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) y[bj] = sr[k + (l >> 4)][wc * 32 + bj * 16 + (l & 15)];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].x, y[bj].x, re[bi][bj], 0, 0, 0);
+        re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x[bi].y, y[bj].y, re[bi][bj], 0, 0, 0);
+        im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].x, y[bj].y, im[bi][bj], 0, 0, 0);
+        im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].y, y[bj].x, im[bi][bj], 0, 0, 0);
+      }
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const int cl = wc * 32 + bj * 16 + (l & 15);
+      const int j = j0 + cl;
+      const bool j_in_p = j >= P0 && j < P0 + nb;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wr * 32 + bi * 16 + (l >> 4) + 4 * v;
+        if (i >= n || j >= n) continue;
+        const int64_t e = (int64_t)i * n + j;
+        if (i >= P0 && i < P0 + nb) {
+          A[e] = sr[i - P0][cl];
+        } else {
+          const double2 old = j_in_p ? make_double2(0.0, 0.0) : A[e];
+          A[e] = make_double2(old.x - re[bi][bj][v], old.y - im[bi][bj][v]);
+        }
+      }
+    }
+}
+
+// grid (ceil(n / 256), n): per element (g, h), W~(i omega_k) = s_g s_h
+// (A_k(g, h) - delta) for every k (written when w_omega is not null) and
+// W~(i tau_j) = sum_k ict[j][k] W~(i omega_k), summed in increasing k, all
+// taus in registers (n_tau <= MT).
+template <int MT>
+__global__ __launch_bounds__(256) void k_w_final(const double2 *__restrict__ a,
+                                                 const double *__restrict__ s,
+                                                 const double *__restrict__ ict,
+                                                 double2 *__restrict__ w_tau,
+                                                 double2 *__restrict__ w_omega, int n,
+                                                 int n_omega, int n_tau) {
+  const int h = blockIdx.x * 256 + threadIdx.x;
+  const int g = blockIdx.y;
+  if (h >= n) return;
+  const int64_t nn = (int64_t)n * n;
+  const int64_t e = (int64_t)g * n + h;
+  const double ss = s[g] * s[h];
+  double2 acc[MT];
+#pragma unroll
+  for (int j = 0; j < MT; ++j) acc[j] = make_double2(0.0, 0.0);
+  for (int k = 0; k < n_omega; ++k) {
+    double2 x = a[k * nn + e];
+    if (g == h) x.x -= 1.0;
+    const double2 wv = make_double2(ss * x.x, ss * x.y);
+    if (w_omega) w_omega[k * nn + e] = wv;
+#pragma unroll
+    for (int j = 0; j < MT; ++j) {
+      if (j < n_tau) {
+        const double c = ict[j * n_omega + k];
+        acc[j].x += c * wv.x;
+        acc[j].y += c * wv.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < MT; ++j)
+    if (j < n_tau) w_tau[j * nn + e] = acc[j];
+}
+
+}  // namespace
+
+hipError_t launch_w_eps(const void *chi, const double *s, void *a, int n, int n_mat,
+                        hipStream_t st) {
+  if (n < 1 || n_mat < 1) return hipSuccess;
+  if (n > 65535 || n_mat > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_w_eps, dim3((n + 255) / 256, n, n_mat), dim3(256), 0, st,
+                     (const double2 *)chi, s, (double2 *)a, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_w_block(void *a, void *dinv, void *rp, void *cp, int n, int n_mat, int P0,
+                          int *flag, hipStream_t st) {
+  if (P0 < 0 || P0 >= n) return hipErrorInvalidValue;
+  if (n_mat > 65535) return hipErrorInvalidValue;
+  const int tiles = (n + 63) / 64;
+  hipLaunchKernelGGL(k_w_diag, dim3(n_mat), dim3(256), 0, st, (const double2 *)a,
+                     (double2 *)dinv, n, P0, flag);
+  hipLaunchKernelGGL(k_w_panel, dim3(tiles, n_mat), dim3(256), 0, st, (const double2 *)a,
+                     (const double2 *)dinv, (double2 *)rp, (double2 *)cp, n, P0);
+  hipLaunchKernelGGL(k_w_update, dim3(tiles, tiles, n_mat), dim3(256), 0, st, (double2 *)a,
+                     (const double2 *)rp, (const double2 *)cp, n, P0);
+  return hipGetLastError();
+}
+
+hipError_t launch_w_final(const void *a, const double *s, const double *ict, void *w_tau,
+                          void *w_omega, int n, int n_omega, int n_tau, hipStream_t st) {
+  if (n > 65535) return hipErrorInvalidValue;
+  const dim3 grid((n + 255) / 256, n), block(256);
+  const double2 *A = (const double2 *)a;
+  double2 *T = (double2 *)w_tau, *O = (double2 *)w_omega;
+  if (n_tau <= 8)
+    hipLaunchKernelGGL(k_w_final<8>, grid, block, 0, st, A, s, ict, T, O, n, n_omega, n_tau);
+  else if (n_tau <= 16)
+    hipLaunchKernelGGL(k_w_final<16>, grid, block, 0, st, A, s, ict, T, O, n, n_omega, n_tau);
+  else if (n_tau <= 32)
+    hipLaunchKernelGGL(k_w_final<32>, grid, block, 0, st, A, s, ict, T, O, n, n_omega, n_tau);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace gw

@@ -21,7 +21,7 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTSUP", 5: "ENU
 
 EXPORTS = ["gwchi_create", "gwchi_destroy", "gwchi_set_options", "gwchi_get_options",
            "gwchi_validate", "gwchi_chi_build", "gwchi_chi_build_device", "gwchi_autotune",
-           "gwchi_last_error", "gwchi_version"]
+           "gwchi_last_error", "gwchi_version", "gwchi_w_build", "gwchi_w_build_device", "gwchi_w_validate"]
 
 
 class GwchiItem(C.Structure):
@@ -84,6 +84,33 @@ class GwchiOptions(C.Structure):
     ]
 
 
+class GwchiWItem(C.Structure):
+    _fields_ = [
+        ("n_g", C.c_int32),
+        ("n_omega", C.c_int32),
+        ("n_tau", C.c_int32),
+        ("chi", C.c_void_p),
+        ("sqrt_v", C.c_void_p),
+        ("ct", C.c_void_p),
+        ("w_tau_out", C.c_void_p),
+        ("w_omega_out", C.c_void_p),
+    ]
+
+
+class GwchiWReport(C.Structure):
+    _fields_ = [
+        ("ms_total", C.c_double),
+        ("ms_eps", C.c_double),
+        ("ms_invert", C.c_double),
+        ("ms_final", C.c_double),
+        ("alg_flops", C.c_double),
+        ("n_launches", C.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -112,11 +139,16 @@ def load(path: str = LIB_PATH):
     lib.gwchi_chi_build_device.argtypes = [C.c_void_p, P(GwchiItem), C.c_int32, C.c_int,
                                            C.c_void_p, P(GwchiReport)]
     lib.gwchi_autotune.argtypes = [C.c_void_p, P(GwchiItem), C.c_int32, C.c_int]
+    lib.gwchi_w_build.argtypes = [C.c_void_p, P(GwchiWItem), C.c_int32, P(GwchiWReport)]
+    lib.gwchi_w_validate.argtypes = [P(GwchiWItem), C.c_int32]
+    lib.gwchi_w_build_device.argtypes = [C.c_void_p, P(GwchiWItem), C.c_int32, C.c_void_p,
+                                         P(GwchiWReport)]
     lib.gwchi_last_error.argtypes = [C.c_void_p]
     lib.gwchi_last_error.restype = C.c_char_p
     lib.gwchi_version.restype = C.c_char_p
     for f in ("gwchi_create", "gwchi_destroy", "gwchi_set_options", "gwchi_get_options",
-              "gwchi_validate", "gwchi_chi_build", "gwchi_chi_build_device", "gwchi_autotune"):
+              "gwchi_validate", "gwchi_chi_build", "gwchi_chi_build_device", "gwchi_autotune",
+              "gwchi_w_build", "gwchi_w_build_device", "gwchi_w_validate"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -183,6 +215,25 @@ def make_item(keep: _Keep, item, phi_occ=None, phi_unocc=None, chi_out=None) -> 
     return it
 
 
+def make_w_item(keep: _Keep, witem, chi=None, w_tau=None, w_omega=None) -> GwchiWItem:
+    """Fill a GwchiWItem from a synth.WItem (or any object with ``chi``,
+    ``sqrt_v`` and ``ct``).  ``chi`` defaults to the host array of the item;
+    pass device tensors (and device outputs) for the device entry."""
+    it = GwchiWItem()
+    ct = keep.f64(witem.ct)
+    it.n_omega, it.n_tau = int(ct.shape[0]), int(ct.shape[1])
+    if chi is None:
+        chi = np.ascontiguousarray(witem.chi, dtype=np.complex128)
+        keep.refs.append(chi)
+    it.n_g = int(chi.shape[1])
+    it.chi = _ptr(chi)
+    it.sqrt_v = _ptr(keep.f64(witem.sqrt_v))
+    it.ct = _ptr(ct)
+    it.w_tau_out = _ptr(w_tau)
+    it.w_omega_out = _ptr(w_omega)
+    return it
+
+
 def validate(items, check_orbitals=True) -> int:
     """gwchi_validate on host arrays; returns the status code."""
     lib = load()
@@ -190,6 +241,19 @@ def validate(items, check_orbitals=True) -> int:
     outs = [np.zeros(1, np.complex128) for _ in items]
     arr = (GwchiItem * len(items))(*[make_item(keep, it, chi_out=o) for it, o in zip(items, outs)])
     return int(lib.gwchi_validate(arr, len(items), 1 if check_orbitals else 0))
+
+
+def w_validate(witems) -> int:
+    """gwchi_w_validate on host arrays; returns the status code."""
+    lib = load()
+    keep = _Keep()
+    its = []
+    for w in witems:
+        t = np.zeros(1, np.complex128)
+        keep.refs.append(t)
+        its.append(make_w_item(keep, w, w_tau=t))
+    arr = (GwchiWItem * len(its))(*its)
+    return int(lib.gwchi_w_validate(arr, len(its)))
 
 
 class Context:
@@ -276,3 +340,46 @@ class Context:
         st = self.lib.gwchi_autotune(self.h, arr, len(items), PRECISIONS[prec])
         if st != 0:
             raise self._err(st)
+
+    def w_build(self, witems: Sequence, omega=False, report=False):
+        """Host-memory W~ (gwchi_w_build): returns a list of complex128 arrays
+        W~(i tau) (n_tau, n_g, n_g), with W~(i omega) when ``omega``, and the
+        report dict when ``report``."""
+        keep = _Keep()
+        taus, oms, its = [], [], []
+        for w in witems:
+            n_g, K = w.chi.shape[1], w.chi.shape[0]
+            t = np.empty((np.asarray(w.ct).shape[1], n_g, n_g), np.complex128)
+            o = np.empty((K, n_g, n_g), np.complex128) if omega else None
+            taus.append(t)
+            oms.append(o)
+            its.append(make_w_item(keep, w, w_tau=t, w_omega=o))
+        arr = (GwchiWItem * len(its))(*its)
+        rep = GwchiWReport()
+        st = self.lib.gwchi_w_build(self.h, arr, len(its), C.byref(rep) if report else None)
+        if st != 0:
+            raise self._err(st)
+        out = (taus, oms) if omega else taus
+        return (out, rep.as_dict()) if report else out
+
+    def w_build_device(self, witems: Sequence, chis, w_taus, w_omegas=None, stream=None,
+                       report=False):
+        """Device-memory W~ (gwchi_w_build_device).  ``chis``: complex128 device
+        tensors (n_omega, n_g, n_g); ``w_taus`` (and optionally ``w_omegas``):
+        complex128 device outputs."""
+        keep = _Keep()
+        if w_omegas is None:
+            w_omegas = [None] * len(witems)
+        arr = (GwchiWItem * len(witems))(*[
+            make_w_item(keep, w, chi=c, w_tau=t, w_omega=o)
+            for w, c, t, o in zip(witems, chis, w_taus, w_omegas)])
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream()
+        sh = int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream or 0)
+        rep = GwchiWReport()
+        st = self.lib.gwchi_w_build_device(self.h, arr, len(witems), C.c_void_p(sh),
+                                           C.byref(rep) if report else None)
+        if st != 0:
+            raise self._err(st)
+        return rep.as_dict() if report else None

@@ -359,17 +359,19 @@ def coulomb_sqrt(n: Sequence[int], g_index: np.ndarray, alpha: float = 1.0,
 
 
 def make_w_item(seed, n, n_tau, *, rank=None, strength=1.0, alpha=1.0,
-                x_min=0.5, x_max=50.0) -> WItem:
+                x_min=0.5, x_max=50.0, n_g=None, k=(0.0, 0.0, 0.0)) -> WItem:
     """Seeded chi(i omega_k) of the shape the polarizability build returns:
     Hermitian, negative semidefinite, decaying with omega.  It is a sum of
     ``rank`` (default n_g / 4) rank-one terms -b_m b_m^H with Lorentzian weights
     x_m^2 / (x_m^2 + omega_k^2), x_m log-spaced in [x_min, x_max]; the plane
-    waves are the sphere of grid ``n`` and ``sqrt_v`` is ``coulomb_sqrt`` at
-    k = 0.  ``strength`` scales chi; the dielectric matrix stays positive
-    definite for any strength >= 0."""
+    waves are the sphere of grid ``n`` (its first ``n_g`` when given) and
+    ``sqrt_v`` is ``coulomb_sqrt`` at ``k``.  ``strength`` scales chi; the
+    dielectric matrix stays positive definite for any strength >= 0."""
     g_index = g_sphere(n)
+    if n_g is not None:
+        g_index = g_index[:int(n_g)]
     n_g = g_index.shape[0]
-    rank = n_g // 4 if rank is None else int(rank)
+    rank = max(1, n_g // 4) if rank is None else int(rank)
     rng = np.random.default_rng(seed)
     tau, omega, ct, _ = ct_grid(n_tau, x_min, x_max)
     b = (rng.standard_normal((n_g, rank)) + 1j * rng.standard_normal((n_g, rank))) / math.sqrt(2.0 * n_g)
@@ -379,4 +381,4 @@ def make_w_item(seed, n, n_tau, *, rank=None, strength=1.0, alpha=1.0,
         lw = strength * x * x / (x * x + w * w)
         chi[kk] = -(b * lw[None, :]) @ b.conj().T
         chi[kk] = 0.5 * (chi[kk] + chi[kk].conj().T)
-    return WItem(chi=chi, sqrt_v=coulomb_sqrt(n, g_index, alpha), ct=ct, omega=omega)
+    return WItem(chi=chi, sqrt_v=coulomb_sqrt(n, g_index, alpha, k), ct=ct, omega=omega)

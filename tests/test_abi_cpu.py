@@ -106,7 +106,8 @@ def test_struct_layout_matches_header(lib, tmp_path):
         pytest.skip("no C compiler")
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gwchi.h"', 'int main(void){']
     mirrors = [("gwchi_item", gwchi.GwchiItem), ("gwchi_report", gwchi.GwchiReport),
-               ("gwchi_options", gwchi.GwchiOptions)]
+               ("gwchi_options", gwchi.GwchiOptions), ("gwchi_w_item", gwchi.GwchiWItem),
+               ("gwchi_w_report", gwchi.GwchiWReport)]
     for cname, py in mirrors:
         lines.append(f'printf("%zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:
@@ -123,3 +124,60 @@ def test_struct_layout_matches_header(lib, tmp_path):
         want.append(C.sizeof(py))
         want += [getattr(py, f).offset for f, _ in py._fields_]
     assert got == want
+
+
+# ---- screened-interaction entry: host-only validation ----------------------
+
+@pytest.fixture(scope="module")
+def witem():
+    return synth.make_w_item(5, (12, 12, 12), 6)
+
+
+def test_w_valid_item_passes(lib, witem):
+    assert gwchi.w_validate([witem]) == 0
+
+
+def _w_mut(witem, **kw):
+    import copy
+    w = copy.copy(witem)
+    for k, v in kw.items():
+        setattr(w, k, v)
+    return w
+
+
+@pytest.mark.parametrize("mut", [
+    "neg_s", "nan_s", "nan_ct", "singular_ct", "non_square", "too_many_tau"])
+def test_w_validate_rejects(lib, witem, mut):
+    if mut == "neg_s":
+        s = witem.sqrt_v.copy()
+        s[3] = -1.0
+        w = _w_mut(witem, sqrt_v=s)
+    elif mut == "nan_s":
+        s = witem.sqrt_v.copy()
+        s[0] = np.nan
+        w = _w_mut(witem, sqrt_v=s)
+    elif mut == "nan_ct":
+        c = witem.ct.copy()
+        c[1, 2] = np.inf
+        w = _w_mut(witem, ct=c)
+    elif mut == "singular_ct":
+        c = witem.ct.copy()
+        c[1] = c[0]
+        w = _w_mut(witem, ct=c)
+    elif mut == "non_square":
+        w = _w_mut(witem, ct=witem.ct[:, :-1].copy())
+    else:
+        n = 33
+        w = _w_mut(witem, ct=np.eye(n), chi=np.zeros((n, 4, 4), np.complex128),
+                   sqrt_v=np.ones(4))
+    assert gwchi.w_validate([w]) == 1
+
+
+def test_w_validate_empty_and_null(lib, witem):
+    import ctypes as C
+    assert lib.gwchi_w_validate(None, 0) == 1
+    keep = gwchi._Keep()
+    it = gwchi.make_w_item(keep, witem, w_tau=None)
+    arr = (gwchi.GwchiWItem * 1)(it)
+    assert lib.gwchi_w_validate(arr, 1) == 1
+    assert b"NULL" in lib.gwchi_last_error(None)

@@ -112,3 +112,11 @@ def test_tau_transform_is_linear_in_frequencies(witem):
 def test_inverse_ct_rejects_non_square():
     with pytest.raises(ValueError):
         ow.inverse_ct(np.ones((3, 4)))
+
+
+def test_rows_by_solves_match_full_inverse(witem):
+    """The sampled-row form (linear solves) agrees with the full inverse."""
+    full = ow.w_tilde_tau(witem.chi, witem.sqrt_v, witem.ct)
+    rows = [0, 1, 57, witem.n_g - 1]
+    part = ow.w_tilde_rows(witem.chi, witem.sqrt_v, witem.ct, rows)
+    assert _rel(part, full[:, rows, :]) < 1e-12
