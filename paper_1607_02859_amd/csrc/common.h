@@ -231,7 +231,7 @@ hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t s);
 // blocked Gauss-Jordan exchange of kWBlock pivots per step, then W~(i omega)
 // and the inverse cosine transform.  Matrices [n_mat][n][n] complex.
 // ---------------------------------------------------------------------------
-constexpr int kWBlock = 32;
+constexpr int kWBlock = 64;
 constexpr int kWMaxTau = 32;
 hipError_t launch_w_eps(const void *chi, const double *s, void *a, int n, int n_mat,
                         hipStream_t st);

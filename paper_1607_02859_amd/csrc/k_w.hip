@@ -157,67 +157,88 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
 // j0..) of the rank-nb update.  Four waves, each a 32 x 32 quarter as 2 x 2
 // blocks of v_mfma_f64_16x16x4 (lane l holds A-operand row l % 16, B-operand
 // column l % 16, band l / 16 of the step; result value v of lane l is row
-// l / 16 + 4 v, column l % 16).  The C rows are padded to NB + 1 entries so
-// that the 16 lanes reading one band of 16 rows hit distinct LDS banks.
+// l / 16 + 4 v, column l % 16).  The tile's current values are read into
+// registers first, so that their latency overlaps the panel loads and the
+// MFMAs; the panels pass through LDS in chunks of KC bands, the C rows padded
+// to KC + 1 entries so that the 16 lanes reading one band of 16 rows hit
+// distinct LDS banks.
+constexpr int KC = 32;
 __global__ __launch_bounds__(256) void k_w_update(double2 *__restrict__ a,
                                                   const double2 *__restrict__ rp,
                                                   const double2 *__restrict__ cp, int n, int P0) {
-  __shared__ double2 sc[64][NB + 1];
-  __shared__ double2 sr[NB][64];
+  __shared__ double2 sc[64][KC + 1];
+  __shared__ double2 sr[KC][64];
   const int m = blockIdx.z;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
   const int nb = min(NB, n - P0);
   double2 *A = a + (int64_t)m * n * n;
-  for (int e = threadIdx.x; e < 64 * NB; e += 256) {
-    const int r = e / NB, p = e % NB, i = i0 + r;
-    sc[r][p] = i < n ? cp[((int64_t)m * n + i) * NB + p] : make_double2(0.0, 0.0);
-  }
-  for (int e = threadIdx.x; e < NB * 64; e += 256) {
-    const int p = e / 64, c = e % 64, j = j0 + c;
-    sr[p][c] = j < n ? rp[((int64_t)m * NB + p) * n + j] : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int wr = w >> 1, wc = w & 1;
+  // current values of the lane's 16 outputs (0 where they are replaced)
+  double2 old[2][2][4];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const int j = j0 + wc * 32 + bj * 16 + (l & 15);
+      const bool keep_j = j < n && !(j >= P0 && j < P0 + nb);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wr * 32 + bi * 16 + (l >> 4) + 4 * v;
+        const bool keep = keep_j && i < n && !(i >= P0 && i < P0 + nb);
+        old[bi][bj][v] = keep ? A[(int64_t)i * n + j] : make_double2(0.0, 0.0);
+      }
+    }
   d4v re[2][2], im[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) re[bi][bj] = im[bi][bj] = d4v{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < nb; k0 += KC) {
+    for (int e = threadIdx.x; e < 64 * KC; e += 256) {
+      const int r = e / KC, p = e % KC, i = i0 + r;
+      sc[r][p] = i < n ? cp[((int64_t)m * n + i) * NB + k0 + p] : make_double2(0.0, 0.0);
+    }
+    for (int e = threadIdx.x; e < KC * 64; e += 256) {
+      const int p = e / 64, c = e % 64, j = j0 + c;
+      sr[p][c] = j < n ? rp[((int64_t)m * NB + k0 + p) * n + j] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
 #pragma unroll
-  for (int k = 0; k < NB; k += 4) {
-    double2 x[2], y[2];
+    for (int k = 0; k < KC; k += 4) {
+      double2 x[2], y[2];
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi) x[bi] = sc[wr * 32 + bi * 16 + (l & 15)][k + (l >> 4)];
+      for (int bi = 0; bi < 2; ++bi) x[bi] = sc[wr * 32 + bi * 16 + (l & 15)][k + (l >> 4)];
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) y[bj] = sr[k + (l >> 4)][wc * 32 + bj * 16 + (l & 15)];
+      for (int bj = 0; bj < 2; ++bj) y[bj] = sr[k + (l >> 4)][wc * 32 + bj * 16 + (l & 15)];
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+      for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj) {
-        re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].x, y[bj].x, re[bi][bj], 0, 0, 0);
-        re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x[bi].y, y[bj].y, re[bi][bj], 0, 0, 0);
-        im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].x, y[bj].y, im[bi][bj], 0, 0, 0);
-        im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].y, y[bj].x, im[bi][bj], 0, 0, 0);
-      }
+        for (int bj = 0; bj < 2; ++bj) {
+          re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].x, y[bj].x, re[bi][bj], 0, 0, 0);
+          re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x[bi].y, y[bj].y, re[bi][bj], 0, 0, 0);
+          im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].x, y[bj].y, im[bi][bj], 0, 0, 0);
+          im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].y, y[bj].x, im[bi][bj], 0, 0, 0);
+        }
+    }
+    __syncthreads();
   }
+  // rows of the pivot block take the row panel (D^-1 on the block's columns)
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
-      const int cl = wc * 32 + bj * 16 + (l & 15);
-      const int j = j0 + cl;
-      const bool j_in_p = j >= P0 && j < P0 + nb;
+      const int j = j0 + wc * 32 + bj * 16 + (l & 15);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = i0 + wr * 32 + bi * 16 + (l >> 4) + 4 * v;
         if (i >= n || j >= n) continue;
         const int64_t e = (int64_t)i * n + j;
         if (i >= P0 && i < P0 + nb) {
-          A[e] = sr[i - P0][cl];
+          A[e] = rp[((int64_t)m * NB + (i - P0)) * n + j];
         } else {
-          const double2 old = j_in_p ? make_double2(0.0, 0.0) : A[e];
-          A[e] = make_double2(old.x - re[bi][bj][v], old.y - im[bi][bj][v]);
+          const double2 o = old[bi][bj][v];
+          A[e] = make_double2(o.x - re[bi][bj][v], o.y - im[bi][bj][v]);
         }
       }
     }
