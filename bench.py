@@ -94,6 +94,65 @@ def cpu_baseline(item, n_tau_sample: int = 1):
                       f"(space-time steps 1-4, FP64 NumPy/SciPy), {dt:.1f} s"}
 
 
+def bench_w(ctx, item, args):
+    """The screened-interaction step after the build (Sec. II.C steps (iii)-(iv)):
+    W~(G, G', i tau) from chi(G, G', i omega) on the workload's plane-wave
+    sphere and frequency grid, FP64.  chi is a seeded Hermitian negative
+    semidefinite stand-in of the same shape, resident in HBM; one step is one
+    call (dielectric matrices, their inversion, W~ and the inverse cosine
+    transform).  Algorithmic flops: 8 n_g^3 per frequency (complex inversion)."""
+    import torch
+    from paper_1607_02859_amd import synth
+    dev = torch.device("cuda:0")
+    w = synth.make_w_item(61, item.n, item.n_tau, strength=4.0)
+    chi = torch.from_numpy(w.chi).to(dev)
+    w_tau = torch.empty((w.n_tau, w.n_g, w.n_g), dtype=torch.complex128, device=dev)
+    w_om = torch.empty((w.n_omega, w.n_g, w.n_g), dtype=torch.complex128, device=dev)
+    for _ in range(max(1, args.warmup)):
+        ctx.w_build_device([w], [chi], [w_tau], [w_om], report=True)
+    reps = [ctx.w_build_device([w], [chi], [w_tau], [w_om], report=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    ms = sum(r["ms_total"] for r in reps) / len(reps)
+    ms_inv = sum(r["ms_invert"] for r in reps) / len(reps)
+    flops = reps[0]["alg_flops"]
+    out = {
+        "metric": "W~(G,G',i tau) from chi(G,G',i omega): TFLOP/s (8 n_g^3 per frequency)",
+        "value": flops / ms * 1e-9, "unit": "TFLOP/s", "ms_per_step": ms, "dtype": "f64",
+        "config": {"n_g": w.n_g, "n_omega": w.n_omega, "n_tau": w.n_tau,
+                   "data": "seeded Hermitian negative semidefinite chi(i omega) of the "
+                           "workload's sphere and frequency grid"},
+        "ms_phases": {"eps": sum(r["ms_eps"] for r in reps) / len(reps), "invert": ms_inv,
+                      "final": sum(r["ms_final"] for r in reps) / len(reps)},
+        "roofline": {"bound": "mfma", "kernel": "inversion (k_w_diag + k_w_panel + k_w_update)",
+                     "achieved": flops / ms_inv * 1e-9, "peak": PEAK_TFLOPS["fp64"],
+                     "unit": "TFLOP/s", "frac": flops / ms_inv * 1e-9 / PEAK_TFLOPS["fp64"],
+                     "traffic": None},
+    }
+    if not args.no_check:
+        rows = [0, w.n_g // 2, w.n_g - 1]
+        got = w_om.cpu().numpy()
+        from oracle import w as ow
+        errs = [float(np.linalg.norm(got[k][rows] - ow.w_tilde_omega_rows(w.chi[k], w.sqrt_v, rows))
+                      / np.linalg.norm(ow.w_tilde_omega_rows(w.chi[k], w.sqrt_v, rows)))
+                for k in (0, w.n_omega - 1)]
+        out["err_vs_oracle_sampled"] = max(errs)
+    if not args.no_cpu:
+        from oracle import w as ow
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        cores = max([i.get("num_threads", 1) for i in info] or [1])
+        t0 = time.perf_counter()
+        ow.w_tilde_omega(w.chi[:1], w.sqrt_v)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 8.0 * w.n_g ** 3 / dt * 1e-12, "unit": "TFLOP/s",
+                               "cores": int(cores), "kind": "oracle",
+                               "sample": f"1 of {w.n_omega} frequencies (dense inverse, FP64 "
+                                         f"NumPy), {dt:.1f} s"}
+    log(f"[bench] w_tilde: {ms:.2f} ms/step (invert {ms_inv:.2f}), "
+        f"{out['value']:.1f} TFLOP/s, err {out.get('err_vs_oracle_sampled', float('nan')):.2e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +169,11 @@ def main():
                          "of known size against which HBM byte counters are scaled)")
     ap.add_argument("--config", type=int, default=2,
                     help="workload configuration (2 is the headline; 1, 3, 4, 5 for the record)")
+    ap.add_argument("--w", type=int, default=None,
+                    help="also time the screened-interaction step W~ from chi(i omega) on the "
+                         "plane-wave sphere of the workload (default: on for configuration 2)")
+    ap.add_argument("--w-only", action="store_true",
+                    help="time only the W~ step (prints one JSON line with the w_tilde object)")
     ap.add_argument("--autotune", type=int, default=None,
                     help="time every GEMM tile on the workload before the warm-up and use the "
                          "fastest (default: on for the k-point batch, configuration 3)")
@@ -129,6 +193,12 @@ def main():
     item = items[0]
     log(f"[bench] config {args.config}: {len(items)} item(s), first n={item.n} "
         f"K={item.n_occ}+{item.n_unocc} n_tau={item.n_tau} n_g={item.n_g}")
+    if args.w_only:
+        ctx = gwchi.Context(0)
+        out = {"w_tilde": bench_w(ctx, item, args)}
+        ctx.close()
+        print(json.dumps(out), flush=True)
+        return
     phis = [(torch.from_numpy(it.phi_occ).to(dev), torch.from_numpy(it.phi_unocc).to(dev))
             for it in items]
     outs = [torch.empty((it.n_omega, it.n_g, it.n_g), dtype=torch.complex128, device=dev)
@@ -263,6 +333,10 @@ def main():
     }
     if not args.no_cpu and args.config == 2:
         res["cpu_baseline"] = cpu_baseline(item, 6)
+    if args.w is None:
+        args.w = 1 if args.config == 2 else 0
+    if args.w:
+        res["w_tilde"] = bench_w(ctx, item, args)
     ctx.close()
     print(json.dumps(res), flush=True)
 

@@ -40,7 +40,8 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["inverse_ct", "coulomb_kernel", "w_tilde_omega", "w_tilde_tau", "w_tilde_rows"]
+__all__ = ["inverse_ct", "coulomb_kernel", "w_tilde_omega", "w_tilde_tau", "w_tilde_rows",
+           "w_tilde_omega_rows"]
 
 
 def inverse_ct(ct: np.ndarray) -> np.ndarray:
@@ -92,20 +93,25 @@ def w_tilde_rows(chi_w: np.ndarray, s: np.ndarray, ct: np.ndarray, rows) -> np.n
     Row g of eps^-1 is e_g^T eps^-1 = (eps^-T e_g)^T, one linear solve per
     frequency for all selected rows; then Eqs. (46), (49) and (50) as above."""
     chi_w = np.asarray(chi_w, dtype=np.complex128)
-    s = np.asarray(s, dtype=np.float64)
-    rows = np.asarray(rows, dtype=np.int64)
-    n_g = s.shape[0]
-    v = coulomb_kernel(s)
-    e = np.zeros((n_g, rows.shape[0]))
-    e[rows, np.arange(rows.shape[0])] = 1.0
-    w_w = np.empty((chi_w.shape[0], rows.shape[0], n_g), dtype=np.complex128)
-    for k in range(chi_w.shape[0]):
-        eps = np.eye(n_g) - v * chi_w[k]                            # Eq. (48)
-        inv_rows = np.linalg.solve(eps.T, e).T                      # rows of eps^-1
-        w_w[k] = v[rows] * inv_rows - v[rows] * e.T                 # Eqs. (46), (49)
+    w_w = np.stack([w_tilde_omega_rows(chi_w[k], s, rows) for k in range(chi_w.shape[0])])
     ict = inverse_ct(ct)
     out = np.zeros((ict.shape[0],) + w_w.shape[1:], dtype=np.complex128)
     for j in range(ict.shape[0]):
         for k in range(ict.shape[1]):                               # Eq. (50)
             out[j] += ict[j, k] * w_w[k]
     return out
+
+
+def w_tilde_omega_rows(chi: np.ndarray, s: np.ndarray, rows) -> np.ndarray:
+    """Rows ``rows`` of W~(G, G', i omega) for one frequency (Eqs. (46)-(49));
+    row g of eps^-1 is e_g^T eps^-1 = (eps^-T e_g)^T, one linear solve."""
+    chi = np.asarray(chi, dtype=np.complex128)
+    s = np.asarray(s, dtype=np.float64)
+    rows = np.asarray(rows, dtype=np.int64)
+    n_g = s.shape[0]
+    v = coulomb_kernel(s)
+    e = np.zeros((n_g, rows.shape[0]))
+    e[rows, np.arange(rows.shape[0])] = 1.0
+    eps = np.eye(n_g) - v * chi                                     # Eq. (48)
+    inv_rows = np.linalg.solve(eps.T, e).T                          # rows of eps^-1
+    return v[rows] * inv_rows - v[rows] * e.T                       # Eqs. (46), (49)

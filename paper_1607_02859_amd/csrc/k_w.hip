@@ -55,64 +55,67 @@ __global__ __launch_bounds__(256) void k_w_eps(const double2 *__restrict__ chi,
   a[e] = y;
 }
 
-// one workgroup per matrix: the exchange of the nb pivots of the diagonal
-// block at P0, in LDS; rows and columns past nb are the identity.  A pivot
-// whose real part is not positive and finite (eps not positive definite)
-// sets *flag.
-__global__ __launch_bounds__(256) void k_w_diag(const double2 *__restrict__ a,
-                                                double2 *__restrict__ dinv, int n, int P0,
-                                                int *flag) {
-  __shared__ double2 d[NB][NB + 1];
+// one workgroup of 1024 threads per matrix: the exchange of the nb pivots of
+// the diagonal block at P0, in LDS; rows and columns past nb are the
+// identity.  Each pivot reads one LDS copy of the block and writes the other
+// (one barrier per pivot).  A pivot whose real part is not positive and
+// finite (eps not positive definite) sets *flag.
+constexpr int DT = 1024;
+__global__ __launch_bounds__(DT) void k_w_diag(const double2 *__restrict__ a,
+                                               double2 *__restrict__ dinv, int n, int P0,
+                                               int *flag) {
+  __shared__ double2 d[2][NB][NB + 1];
   const int m = blockIdx.x;
   const double2 *A = a + (int64_t)m * n * n;
   const int nb = min(NB, n - P0);
-  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+  for (int e = threadIdx.x; e < NB * NB; e += DT) {
     const int i = e / NB, j = e % NB;
-    d[i][j] = (i < nb && j < nb) ? A[(int64_t)(P0 + i) * n + P0 + j]
-                                 : make_double2(i == j ? 1.0 : 0.0, 0.0);
+    d[0][i][j] = (i < nb && j < nb) ? A[(int64_t)(P0 + i) * n + P0 + j]
+                                    : make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
-  constexpr int PER = NB * NB / 256;
+  constexpr int PER = NB * NB / DT;
+  int cur = 0;
   for (int p = 0; p < nb; ++p) {
-    const double2 dpp = d[p][p];
+    const double2 dpp = d[cur][p][p];
     if (threadIdx.x == 0 && !(dpp.x > 0.0 && dpp.x < 1.0e300)) atomicOr(flag, 1);
     const double2 piv = cinv(dpp);
-    double2 nv[PER];
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
-      const int e = threadIdx.x + 256 * t;
+      const int e = threadIdx.x + DT * t;
       const int i = e / NB, j = e % NB;
-      const double2 dip = d[i][p], dpj = d[p][j];
-      if (i != p && j != p) nv[t] = csub(d[i][j], cmul(cmul(dip, piv), dpj));
-      else if (i != p) {
+      const double2 dip = d[cur][i][p], dpj = d[cur][p][j];
+      double2 nv;
+      if (i != p && j != p) {
+        nv = csub(d[cur][i][j], cmul(cmul(dip, piv), dpj));
+      } else if (i != p) {
         const double2 x = cmul(dip, piv);
-        nv[t] = make_double2(-x.x, -x.y);
+        nv = make_double2(-x.x, -x.y);
+      } else if (j != p) {
+        nv = cmul(piv, dpj);
+      } else {
+        nv = piv;
       }
-      else if (j != p) nv[t] = cmul(piv, dpj);
-      else nv[t] = piv;
+      d[cur ^ 1][i][j] = nv;
     }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < PER; ++t) {
-      const int e = threadIdx.x + 256 * t;
-      d[e / NB][e % NB] = nv[t];
-    }
+    cur ^= 1;
     __syncthreads();
   }
   double2 *D = dinv + (int64_t)m * NB * NB;
-  for (int e = threadIdx.x; e < NB * NB; e += 256) D[e] = d[e / NB][e % NB];
+  for (int e = threadIdx.x; e < NB * NB; e += DT) D[e] = d[cur][e / NB][e % NB];
 }
 
 // grid (ceil(n / 64), n_mat): for the 64 columns j0 .. j0 + 63 the row panel
-// rp[m][p][j] (layout [n_mat][NB][n]) and, for the rows i of the same range,
-// the column panel cp[m][i][p] (layout [n_mat][n][NB]); entries with p >= nb
-// are zero.
+// rp[m][p][j] = (D^-1 A[P, :])[p][j] (D^-1 itself on the block's columns;
+// layout [n_mat][NB][n]) on FP64 MFMA, and for the rows i of the same range
+// the column panel cp[m][i][p] = A[i][P0 + p] (layout [n_mat][n][NB]); entries
+// with p >= nb are zero.  Waves and lanes as in k_w_update below.
 __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
                                                  const double2 *__restrict__ dinv,
                                                  double2 *__restrict__ rp, double2 *__restrict__ cp,
                                                  int n, int P0) {
   __shared__ double2 sd[NB][NB + 1];
-  __shared__ double2 sa[NB][64 + 1];
+  __shared__ double2 sa[NB][64];
   const int m = blockIdx.y;
   const int j0 = blockIdx.x * 64;
   const int nb = min(NB, n - P0);
@@ -123,27 +126,7 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
     const int q = e / 64, c = e % 64, j = j0 + c;
     sa[q][c] = (q < nb && j < n) ? A[(int64_t)(P0 + q) * n + j] : make_double2(0.0, 0.0);
   }
-  __syncthreads();
-  const int c = threadIdx.x % 64, p0 = threadIdx.x / 64;
-  const int j = j0 + c;
-  if (j < n) {
-    const bool in_p = j >= P0 && j < P0 + nb;
-    for (int p = p0; p < NB; p += 4) {
-      double2 val = make_double2(0.0, 0.0);
-      if (p < nb) {
-        if (in_p) {
-          val = sd[p][j - P0];
-        } else {
-          for (int q = 0; q < nb; ++q) {
-            const double2 x = cmul(sd[p][q], sa[q][c]);
-            val.x += x.x;
-            val.y += x.y;
-          }
-        }
-      }
-      rp[((int64_t)m * NB + p) * n + j] = val;
-    }
-  }
+  // column panel (independent of the LDS contents)
   for (int e = threadIdx.x; e < 64 * NB; e += 256) {
     const int r = e / NB, p = e % NB, i = j0 + r;
     if (i >= n) continue;
@@ -151,6 +134,46 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
     cp[((int64_t)m * n + i) * NB + p] =
         (p < nb && !in_p) ? A[(int64_t)i * n + P0 + p] : make_double2(0.0, 0.0);
   }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int wr = w >> 1, wc = w & 1;
+  d4v re[2][2], im[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) re[bi][bj] = im[bi][bj] = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k = 0; k < NB; k += 4) {
+    double2 x[2], y[2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) x[bi] = sd[wr * 32 + bi * 16 + (l & 15)][k + (l >> 4)];
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) y[bj] = sa[k + (l >> 4)][wc * 32 + bj * 16 + (l & 15)];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].x, y[bj].x, re[bi][bj], 0, 0, 0);
+        re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x[bi].y, y[bj].y, re[bi][bj], 0, 0, 0);
+        im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].x, y[bj].y, im[bi][bj], 0, 0, 0);
+        im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].y, y[bj].x, im[bi][bj], 0, 0, 0);
+      }
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const int j = j0 + wc * 32 + bj * 16 + (l & 15);
+      if (j >= n) continue;
+      const bool in_p = j >= P0 && j < P0 + nb;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int p = wr * 32 + bi * 16 + (l >> 4) + 4 * v;
+        double2 val = make_double2(0.0, 0.0);
+        if (p < nb) val = in_p ? sd[p][j - P0] : make_double2(re[bi][bj][v], im[bi][bj][v]);
+        rp[((int64_t)m * NB + p) * n + j] = val;
+      }
+    }
 }
 
 // grid (ceil(n / 64), ceil(n / 64), n_mat): 64 x 64 tile (rows i0.., columns
@@ -299,7 +322,7 @@ hipError_t launch_w_block(void *a, void *dinv, void *rp, void *cp, int n, int n_
   if (P0 < 0 || P0 >= n) return hipErrorInvalidValue;
   if (n_mat > 65535) return hipErrorInvalidValue;
   const int tiles = (n + 63) / 64;
-  hipLaunchKernelGGL(k_w_diag, dim3(n_mat), dim3(256), 0, st, (const double2 *)a,
+  hipLaunchKernelGGL(k_w_diag, dim3(n_mat), dim3(DT), 0, st, (const double2 *)a,
                      (double2 *)dinv, n, P0, flag);
   hipLaunchKernelGGL(k_w_panel, dim3(tiles, n_mat), dim3(256), 0, st, (const double2 *)a,
                      (const double2 *)dinv, (double2 *)rp, (double2 *)cp, n, P0);
