@@ -180,12 +180,12 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
 // j0..) of the rank-nb update.  Four waves, each a 32 x 32 quarter as 2 x 2
 // blocks of v_mfma_f64_16x16x4 (lane l holds A-operand row l % 16, B-operand
 // column l % 16, band l / 16 of the step; result value v of lane l is row
-// l / 16 + 4 v, column l % 16).  The tile's current values are read into
-// registers first, so that their latency overlaps the panel loads and the
-// MFMAs; the panels pass through LDS in chunks of KC bands, the C rows padded
-// to KC + 1 entries so that the 16 lanes reading one band of 16 rows hit
-// distinct LDS banks.
-constexpr int KC = 32;
+// l / 16 + 4 v, column l % 16).  The panels pass through LDS in chunks of KC
+// bands (33 KB, so that three workgroups share a CU), the C rows padded to
+// KC + 1 entries so that the 16 lanes reading one band of 16 rows hit
+// distinct LDS banks; the tile's current values are read at the end.  (Reading
+// them first, into 64 more registers, or chunks of 32 bands, measured slower.)
+constexpr int KC = 16;
 __global__ __launch_bounds__(256) void k_w_update(double2 *__restrict__ a,
                                                   const double2 *__restrict__ rp,
                                                   const double2 *__restrict__ cp, int n, int P0) {
@@ -197,21 +197,6 @@ __global__ __launch_bounds__(256) void k_w_update(double2 *__restrict__ a,
   double2 *A = a + (int64_t)m * n * n;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int wr = w >> 1, wc = w & 1;
-  // current values of the lane's 16 outputs (0 where they are replaced)
-  double2 old[2][2][4];
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      const int j = j0 + wc * 32 + bj * 16 + (l & 15);
-      const bool keep_j = j < n && !(j >= P0 && j < P0 + nb);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = i0 + wr * 32 + bi * 16 + (l >> 4) + 4 * v;
-        const bool keep = keep_j && i < n && !(i >= P0 && i < P0 + nb);
-        old[bi][bj][v] = keep ? A[(int64_t)i * n + j] : make_double2(0.0, 0.0);
-      }
-    }
   d4v re[2][2], im[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -260,7 +245,8 @@ __global__ __launch_bounds__(256) void k_w_update(double2 *__restrict__ a,
         if (i >= P0 && i < P0 + nb) {
           A[e] = rp[((int64_t)m * NB + (i - P0)) * n + j];
         } else {
-          const double2 o = old[bi][bj][v];
+          const bool j_in_p = j >= P0 && j < P0 + nb;
+          const double2 o = j_in_p ? make_double2(0.0, 0.0) : A[e];
           A[e] = make_double2(o.x - re[bi][bj][v], o.y - im[bi][bj][v]);
         }
       }
