@@ -17,15 +17,20 @@
 //              D^-1 on P; column panel C[i][p] = A[i][P0 + p] for i outside P;
 //   k_w_update A[i][j] <- R[i - P0][j] for i in P, else
 //              A[i][j] * [j outside P] - sum_p C[i][p] R[p][j]
-//              (rank-nb update on FP64 MFMA, panels staged in LDS).
+//              (rank-nb update on FP64 MFMA; persistent, the next panel
+//              chunks loaded while the MFMAs run).
 // After the last block A holds eps^-1.  k_w_final then forms W~(i omega_k)
 // and the inverse cosine transform in one pass over the matrices.
+#include <algorithm>
+#include <type_traits>
+
 #include "common.h"
 
 namespace gw {
 namespace {
 
 typedef double d4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -176,81 +181,161 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
     }
 }
 
-// grid (ceil(n / 64), ceil(n / 64), n_mat): 64 x 64 tile (rows i0.., columns
-// j0..) of the rank-nb update.  Four waves, each a 32 x 32 quarter as 2 x 2
-// blocks of v_mfma_f64_16x16x4 (lane l holds A-operand row l % 16, B-operand
-// column l % 16, band l / 16 of the step; result value v of lane l is row
-// l / 16 + 4 v, column l % 16).  The panels pass through LDS in chunks of KC
-// bands (33 KB, so that three workgroups share a CU), the C rows padded to
-// KC + 1 entries so that the 16 lanes reading one band of 16 rows hit
-// distinct LDS banks; the tile's current values are read at the end.  (Reading
-// them first, into 64 more registers, or chunks of 32 bands, measured slower.)
-constexpr int KC = 16;
-__global__ __launch_bounds__(256) void k_w_update(double2 *__restrict__ a,
-                                                  const double2 *__restrict__ rp,
-                                                  const double2 *__restrict__ cp, int n, int P0) {
-  __shared__ double2 sc[64][KC + 1];
-  __shared__ double2 sr[KC][64];
-  const int m = blockIdx.z;
-  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+// Rank-nb update, persistent: each workgroup of four waves walks the 64 x 64
+// tiles t = blockIdx.x, blockIdx.x + gridDim.x, ... of all matrices (tile t:
+// matrix t / T^2, row tile (t / T) % T, column tile t % T, T tiles per side).
+// Per tile: A[i][j] <- R[i - P0][j] for i in the pivot block P, else
+// A[i][j] [j outside P] - sum_p C[i][p] R[p][j].
+//
+// The panels stream in chunks of UKC = 16 bands (NB / UKC per tile) through a
+// two-stage LDS ring; each thread holds the next two chunks in registers,
+// loaded while the MFMAs of the current chunk run, across tile boundaries,
+// and the tile's current A values are loaded at its start, so that HBM and
+// L2 traffic overlap the MFMAs.  Every load is issued from a clamped, valid
+// address; out-of-range rows and columns only feed outputs never stored.
+//   stage layout: C rows 64 x (UKC + 1) entries (padded: the 16 lanes reading
+//   one band of 16 rows hit distinct banks), then R: UKC band rows x 64.
+// Waves and lanes as in k_w_panel.
+constexpr int UKC = 16;
+constexpr int UCH = NB / UKC;                 // chunks per tile
+
+struct UTile {
+  int m, i0, j0;
+};
+__device__ __forceinline__ UTile utile(int t, int T) {
+  UTile u;
+  u.m = t / (T * T);
+  const int r = t - u.m * T * T;
+  u.i0 = (r / T) * 64;
+  u.j0 = (r % T) * 64;
+  return u;
+}
+
+// one chunk of panel values per thread: 4 C entries and 4 R entries
+// (native vectors: arrays of them stay in registers across the tile loop)
+__device__ __forceinline__ void uload(d2v (&hc)[4], d2v (&hr)[4], const double2 *__restrict__ rp,
+                                      const double2 *__restrict__ cp, int n, const UTile &u,
+                                      int kc) {
+  const int k0 = kc * UKC;
+  sfor<0, 4>([&](auto qq) {
+    constexpr int q = decltype(qq)::value;
+    const int e = threadIdx.x + 256 * q;       // C: row e / UKC, band e % UKC
+    const int gi = min(u.i0 + e / UKC, n - 1);
+    hc[q] = *reinterpret_cast<const d2v *>(cp + ((int64_t)u.m * n + gi) * NB + k0 + e % UKC);
+    const int gj = min(u.j0 + e % 64, n - 1);  // R: band e / 64, column e % 64
+    hr[q] = *reinterpret_cast<const d2v *>(rp + ((int64_t)u.m * NB + k0 + e / 64) * n + gj);
+  });
+}
+__device__ __forceinline__ void ustore(const d2v (&hc)[4], const d2v (&hr)[4],
+                                       double2 (*sc)[UKC + 1], double2 (*sr)[64]) {
+  sfor<0, 4>([&](auto qq) {
+    constexpr int q = decltype(qq)::value;
+    const int e = threadIdx.x + 256 * q;
+    *reinterpret_cast<d2v *>(&sc[e / UKC][e % UKC]) = hc[q];
+    *reinterpret_cast<d2v *>(&sr[e / 64][e % 64]) = hr[q];
+  });
+}
+
+__global__ __launch_bounds__(256, 2) void k_w_update(double2 *__restrict__ a,
+                                                     const double2 *__restrict__ rp,
+                                                     const double2 *__restrict__ cp, int n,
+                                                     int P0, int T, int n_tiles) {
+  __shared__ double2 sc0[64][UKC + 1], sc1[64][UKC + 1];
+  __shared__ double2 sr0[UKC][64], sr1[UKC][64];
   const int nb = min(NB, n - P0);
-  double2 *A = a + (int64_t)m * n * n;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int wr = w >> 1, wc = w & 1;
-  d4v re[2][2], im[2][2];
+  const int G = gridDim.x;
+  const int my_tiles = (n_tiles - (int)blockIdx.x + G - 1) / G;
+  const int n_chunks = my_tiles * UCH;
+  // chunk c: tile blockIdx.x + (c / UCH) G, band chunk c % UCH; chunks past the
+  // end load the last tile again (never used)
+  auto chunk_tile = [&](int c) {
+    return utile((int)blockIdx.x + min(c / UCH, my_tiles - 1) * G, T);
+  };
+  // register sets X and Y: before chunk c, X holds chunk c + 1 and Y chunk
+  // c + 2 for even c, the other way round for odd c
+  d2v xc[4], xr[4], yc[4], yr[4];
+  uload(xc, xr, rp, cp, n, chunk_tile(0), 0);
+  ustore(xc, xr, sc0, sr0);
+  uload(xc, xr, rp, cp, n, chunk_tile(1), 1 % UCH);
+  uload(yc, yr, rp, cp, n, chunk_tile(2), 2 % UCH);
+  __syncthreads();
+  for (int it = 0; it < my_tiles; ++it) {
+    const UTile u = chunk_tile(it * UCH);
+    double2 *A = a + (int64_t)u.m * n * n;
+    double2 old[2][2][4];
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) re[bi][bj] = im[bi][bj] = d4v{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < nb; k0 += KC) {
-    for (int e = threadIdx.x; e < 64 * KC; e += 256) {
-      const int r = e / KC, p = e % KC, i = i0 + r;
-      sc[r][p] = i < n ? cp[((int64_t)m * n + i) * NB + k0 + p] : make_double2(0.0, 0.0);
-    }
-    for (int e = threadIdx.x; e < KC * 64; e += 256) {
-      const int p = e / 64, c = e % 64, j = j0 + c;
-      sr[p][c] = j < n ? rp[((int64_t)m * NB + k0 + p) * n + j] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
+      for (int bj = 0; bj < 2; ++bj) {
+        const int j = min(u.j0 + wc * 32 + bj * 16 + (l & 15), n - 1);
 #pragma unroll
-    for (int k = 0; k < KC; k += 4) {
-      double2 x[2], y[2];
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi) x[bi] = sc[wr * 32 + bi * 16 + (l & 15)][k + (l >> 4)];
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj) y[bj] = sr[k + (l >> 4)][wc * 32 + bj * 16 + (l & 15)];
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-          re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].x, y[bj].x, re[bi][bj], 0, 0, 0);
-          re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x[bi].y, y[bj].y, re[bi][bj], 0, 0, 0);
-          im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].x, y[bj].y, im[bi][bj], 0, 0, 0);
-          im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].y, y[bj].x, im[bi][bj], 0, 0, 0);
-        }
-    }
-    __syncthreads();
-  }
-  // rows of the pivot block take the row panel (D^-1 on the block's columns)
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      const int j = j0 + wc * 32 + bj * 16 + (l & 15);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = i0 + wr * 32 + bi * 16 + (l >> 4) + 4 * v;
-        if (i >= n || j >= n) continue;
-        const int64_t e = (int64_t)i * n + j;
-        if (i >= P0 && i < P0 + nb) {
-          A[e] = rp[((int64_t)m * NB + (i - P0)) * n + j];
-        } else {
-          const bool j_in_p = j >= P0 && j < P0 + nb;
-          const double2 o = j_in_p ? make_double2(0.0, 0.0) : A[e];
-          A[e] = make_double2(o.x - re[bi][bj][v], o.y - im[bi][bj][v]);
+        for (int v = 0; v < 4; ++v) {
+          const int i = min(u.i0 + wr * 32 + bi * 16 + (l >> 4) + 4 * v, n - 1);
+          old[bi][bj][v] = A[(int64_t)i * n + j];
         }
       }
-    }
+    d4v re[2][2], im[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) re[bi][bj] = im[bi][bj] = d4v{0.0, 0.0, 0.0, 0.0};
+    sfor<0, UCH>([&](auto kk) {
+      constexpr int kc = decltype(kk)::value;
+      const int c = it * UCH + kc;
+      // chunk c is in stage c % 2 (UCH is even, so stage kc % 2)
+      double2(*sc)[UKC + 1] = (kc & 1) ? sc1 : sc0;
+      double2(*sr)[64] = (kc & 1) ? sr1 : sr0;
+#pragma unroll
+      for (int k = 0; k < UKC; k += 4) {
+        double2 x[2], y[2];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) x[bi] = sc[wr * 32 + bi * 16 + (l & 15)][k + (l >> 4)];
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) y[bj] = sr[k + (l >> 4)][wc * 32 + bj * 16 + (l & 15)];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) {
+            re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].x, y[bj].x, re[bi][bj], 0, 0, 0);
+            re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x[bi].y, y[bj].y, re[bi][bj], 0, 0, 0);
+            im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].x, y[bj].y, im[bi][bj], 0, 0, 0);
+            im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].y, y[bj].x, im[bi][bj], 0, 0, 0);
+          }
+      }
+      // chunk c + 1 into the other stage (last read by chunk c - 1, which
+      // every wave finished before the previous barrier), then load c + 3
+      if constexpr ((kc & 1) == 0) {
+        if (c + 1 < n_chunks) ustore(xc, xr, sc1, sr1);
+        uload(xc, xr, rp, cp, n, chunk_tile(c + 3), (kc + 3) % UCH);
+      } else {
+        if (c + 1 < n_chunks) ustore(yc, yr, sc0, sr0);
+        uload(yc, yr, rp, cp, n, chunk_tile(c + 3), (kc + 3) % UCH);
+      }
+      __syncthreads();
+    });
+    // rows of the pivot block take the row panel (D^-1 on the block's columns)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        const int j = u.j0 + wc * 32 + bj * 16 + (l & 15);
+        const bool j_in_p = j >= P0 && j < P0 + nb;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = u.i0 + wr * 32 + bi * 16 + (l >> 4) + 4 * v;
+          if (i >= n || j >= n) continue;
+          const int64_t e = (int64_t)i * n + j;
+          if (i >= P0 && i < P0 + nb) {
+            A[e] = rp[((int64_t)u.m * NB + (i - P0)) * n + j];
+          } else {
+            const double2 o = j_in_p ? make_double2(0.0, 0.0) : old[bi][bj][v];
+            A[e] = make_double2(o.x - re[bi][bj][v], o.y - im[bi][bj][v]);
+          }
+        }
+      }
+  }
 }
 
 // grid (ceil(n / 256), n): per element (g, h), W~(i omega_k) = s_g s_h
@@ -312,8 +397,19 @@ hipError_t launch_w_block(void *a, void *dinv, void *rp, void *cp, int n, int n_
                      (double2 *)dinv, n, P0, flag);
   hipLaunchKernelGGL(k_w_panel, dim3(tiles, n_mat), dim3(256), 0, st, (const double2 *)a,
                      (const double2 *)dinv, (double2 *)rp, (double2 *)cp, n, P0);
-  hipLaunchKernelGGL(k_w_update, dim3(tiles, tiles, n_mat), dim3(256), 0, st, (double2 *)a,
-                     (const double2 *)rp, (const double2 *)cp, n, P0);
+  static int num_cu = 0;
+  if (num_cu <= 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        num_cu <= 0)
+      num_cu = 256;
+  }
+  const int64_t n_tiles = (int64_t)tiles * tiles * n_mat;
+  if (n_tiles > 0x7fffffff) return hipErrorInvalidValue;
+  const int grid = (int)std::min<int64_t>(n_tiles, 2 * num_cu);
+  hipLaunchKernelGGL(k_w_update, dim3(grid), dim3(256), 0, st, (double2 *)a, (const double2 *)rp,
+                     (const double2 *)cp, n, P0, tiles, (int)n_tiles);
   return hipGetLastError();
 }
 
