@@ -60,6 +60,19 @@ def test_edge_sizes(ctx, n_g):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("n_tau", [1, 20])
+def test_grid_sizes(ctx, n_tau):
+    """One frequency (a 1 x 1 cosine matrix), and 20 (the widest register set
+    of the final pass: up to 32 taus).  Larger synthetic grids are too ill
+    conditioned for a parity bound (condition number 5e13 at 32 points)."""
+    w = synth.make_w_item(90 + n_tau, (8, 8, 8), n_tau, strength=3.0, n_g=70, k=K_SHIFT)
+    (taus, oms) = ctx.w_build([w], omega=True)
+    ref_t, ref_w = ow.w_tilde_tau(w.chi, w.sqrt_v, w.ct, return_omega=True)
+    et, ew = rel(taus[0], ref_t), rel(oms[0], ref_w)
+    say(f"[w] n_tau={n_tau} err tau={et:.3e} omega={ew:.3e}")
+    assert et <= TOL and ew <= TOL
+
+
 def test_several_items_one_call(ctx):
     ws = [synth.make_w_item(41, (12, 12, 12), 5, strength=2.0, n_g=200, k=K_SHIFT),
           synth.make_w_item(42, (12, 12, 12), 5, strength=5.0),
