@@ -50,21 +50,22 @@ def log(*a):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_gemm_gamma_complex_24cubed_hbm_traffic.md")
+W_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_w_update_sphere24_hbm_traffic.md")
 
 
-def gemm_traffic(kernel_prefix: str):
-    """HBM bytes per launch of the band-GEMM kernel from the committed
-    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by its
-    reading for a plain copy of known size), or None when that summary was
-    taken on a different k_gemm.hip than the one built here."""
+def gemm_traffic(kernel_prefix: str, profile: str = TRAFFIC_PROFILE, source: str = "k_gemm.hip"):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by its reading for a plain
+    copy of known size), or None when that summary was taken on a different
+    version of the kernel's source file than the one built here."""
     import hashlib
     import re
     try:
-        txt = open(TRAFFIC_PROFILE).read()
+        txt = open(profile).read()
     except OSError:
         return None
-    m = re.search(r"k_gemm.hip sha256 when measured: `([0-9a-f]+)`", txt)
-    src = os.path.join(ROOT, "paper_1607_02859_amd", "csrc", "k_gemm.hip")
+    m = re.search(re.escape(source) + r" sha256 when measured: `([0-9a-f]+)`", txt)
+    src = os.path.join(ROOT, "paper_1607_02859_amd", "csrc", source)
     if not m or hashlib.sha256(open(src, "rb").read()).hexdigest() != m.group(1):
         return None
     for line in txt.splitlines():
@@ -126,7 +127,12 @@ def bench_w(ctx, item, args):
         "roofline": {"bound": "mfma", "kernel": "inversion (k_w_diag + k_w_panel + k_w_update)",
                      "achieved": flops / ms_inv * 1e-9, "peak": PEAK_TFLOPS["fp64"],
                      "unit": "TFLOP/s", "frac": flops / ms_inv * 1e-9 / PEAK_TFLOPS["fp64"],
-                     "traffic": None},
+                     # HBM bytes of one k_w_update launch (the inversion's dominant
+                     # kernel) on this workload, against 2 x 16 n_g^2 K algorithmic
+                     "traffic_k_w_update": gemm_traffic("k_w_update", W_TRAFFIC_PROFILE, "k_w.hip")
+                     if (w.n_g == 2969 and w.n_omega == 12) else None,
+                     "traffic_k_w_update_algorithmic": 32.0 * w.n_g ** 2 * w.n_omega,
+                     "traffic_source": os.path.relpath(W_TRAFFIC_PROFILE, ROOT)},
     }
     if not args.no_check:
         rows = [0, w.n_g // 2, w.n_g - 1]
@@ -193,6 +199,14 @@ def main():
     item = items[0]
     log(f"[bench] config {args.config}: {len(items)} item(s), first n={item.n} "
         f"K={item.n_occ}+{item.n_unocc} n_tau={item.n_tau} n_g={item.n_g}")
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy << 20
+        a = torch.empty(n, dtype=torch.uint8, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if args.w_only:
         ctx = gwchi.Context(0)
         out = {"w_tilde": bench_w(ctx, item, args)}
@@ -203,14 +217,6 @@ def main():
             for it in items]
     outs = [torch.empty((it.n_omega, it.n_g, it.n_g), dtype=torch.complex128, device=dev)
             for it in items]
-    if args.calibrate_copy > 0:
-        n = args.calibrate_copy << 20
-        a = torch.empty(n, dtype=torch.uint8, device=dev).fill_(1)
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
     ctx = gwchi.Context(0)
     ctx.set_options(use_graph=1, timing=1, slab_width=2048, hermitian=args.hermitian,
                     skip_zero_bands=args.skip_zero_bands, kappa=0)

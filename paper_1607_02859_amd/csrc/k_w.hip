@@ -181,9 +181,14 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
     }
 }
 
-// Rank-nb update, persistent: each workgroup of four waves walks the 64 x 64
-// tiles t = blockIdx.x, blockIdx.x + gridDim.x, ... of all matrices (tile t:
-// matrix t / T^2, row tile (t / T) % T, column tile t % T, T tiles per side).
+// Rank-nb update, persistent: each workgroup of four waves walks a share of
+// the 64 x 64 tiles of all matrices (T tiles per side).  Workgroups are dealt
+// to the XCDs in turn, so workgroup b serves partition b % XP (XP = 8, or the
+// grid if smaller), and partition x owns the column tiles [x T / XP,
+// (x + 1) T / XP) of every row tile and matrix: the row panels its tiles read
+// (the R chunks, about n_g / XP columns) stay in that XCD's L2 while A streams
+// through.  Within a partition the tiles run matrix by matrix, row tile by row
+// tile, and its workgroups take every nk-th of them.
 // Per tile: A[i][j] <- R[i - P0][j] for i in the pivot block P, else
 // A[i][j] [j outside P] - sum_p C[i][p] R[p][j].
 //
@@ -202,12 +207,13 @@ constexpr int UCH = NB / UKC;                 // chunks per tile
 struct UTile {
   int m, i0, j0;
 };
-__device__ __forceinline__ UTile utile(int t, int T) {
+// local tile q of a partition owning columns [c_lo, c_lo + wx)
+__device__ __forceinline__ UTile utile(int q, int T, int c_lo, int wx) {
   UTile u;
-  u.m = t / (T * T);
-  const int r = t - u.m * T * T;
-  u.i0 = (r / T) * 64;
-  u.j0 = (r % T) * 64;
+  u.m = q / (T * wx);
+  const int r = q - u.m * T * wx;
+  u.i0 = (r / wx) * 64;
+  u.j0 = (c_lo + r % wx) * 64;
   return u;
 }
 
@@ -246,13 +252,17 @@ __global__ __launch_bounds__(256, 2) void k_w_update(double2 *__restrict__ a,
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int wr = w >> 1, wc = w & 1;
   const int G = gridDim.x;
-  const int my_tiles = (n_tiles - (int)blockIdx.x + G - 1) / G;
+  const int XP = min(8, G);
+  const int x = (int)blockIdx.x % XP, k = (int)blockIdx.x / XP;
+  const int nk = (G - x + XP - 1) / XP;        // workgroups of partition x
+  const int c_lo = x * T / XP, wx = (x + 1) * T / XP - c_lo;
+  const int part_tiles = (n_tiles / (T * T)) * T * wx;
+  const int my_tiles = part_tiles > k ? (part_tiles - k + nk - 1) / nk : 0;
+  if (my_tiles == 0) return;                   // the whole workgroup leaves together
   const int n_chunks = my_tiles * UCH;
-  // chunk c: tile blockIdx.x + (c / UCH) G, band chunk c % UCH; chunks past the
+  // chunk c: local tile k + (c / UCH) nk, band chunk c % UCH; chunks past the
   // end load the last tile again (never used)
-  auto chunk_tile = [&](int c) {
-    return utile((int)blockIdx.x + min(c / UCH, my_tiles - 1) * G, T);
-  };
+  auto chunk_tile = [&](int c) { return utile(k + min(c / UCH, my_tiles - 1) * nk, T, c_lo, wx); };
   // register sets X and Y: before chunk c, X holds chunk c + 1 and Y chunk
   // c + 2 for even c, the other way round for odd c
   d2v xc[4], xr[4], yc[4], yr[4];
