@@ -239,8 +239,9 @@ hipError_t launch_w_eps(const void *chi, const double *s, void *a, int n, int n_
 // cp [n_mat][n][kWBlock]; *flag is set when a pivot is not positive
 hipError_t launch_w_block(void *a, void *dinv, void *rp, void *cp, int n, int n_mat, int P0,
                           int *flag, hipStream_t st);
-// ict [n_tau][n_omega]; w_omega may be null; n_tau <= kWMaxTau
-hipError_t launch_w_final(const void *a, const double *s, const double *ict, void *w_tau,
+// fills the tiles above the block diagonal of a from those below (Hermitian),
+// then ict [n_tau][n_omega]; w_omega may be null; n_tau <= kWMaxTau
+hipError_t launch_w_final(void *a, const double *s, const double *ict, void *w_tau,
                           void *w_omega, int n, int n_omega, int n_tau, hipStream_t st);
 
 }  // namespace gw

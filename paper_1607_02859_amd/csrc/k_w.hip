@@ -120,24 +120,42 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
                                                  double2 *__restrict__ rp, double2 *__restrict__ cp,
                                                  int n, int P0) {
   __shared__ double2 sd[NB][NB + 1];
-  __shared__ double2 sa[NB][64];
+  __shared__ double2 sa[NB][64 + 1];
   const int m = blockIdx.y;
   const int j0 = blockIdx.x * 64;
+  const int tile = (int)blockIdx.x, bp = P0 / 64;   // tile index, pivot block index
   const int nb = min(NB, n - P0);
   const double2 *A = a + (int64_t)m * n * n;
   const double2 *D = dinv + (int64_t)m * NB * NB;
   for (int e = threadIdx.x; e < NB * NB; e += 256) sd[e / NB][e % NB] = D[e];
-  for (int e = threadIdx.x; e < NB * 64; e += 256) {
-    const int q = e / 64, c = e % 64, j = j0 + c;
-    sa[q][c] = (q < nb && j < n) ? A[(int64_t)(P0 + q) * n + j] : make_double2(0.0, 0.0);
+  if (tile <= bp) {
+    // M[P, j] is stored (block-lower): lanes along j
+    for (int e = threadIdx.x; e < NB * 64; e += 256) {
+      const int q = e / 64, c = e % 64, j = j0 + c;
+      sa[q][c] = (q < nb && j < n) ? A[(int64_t)(P0 + q) * n + j] : make_double2(0.0, 0.0);
+    }
+  } else {
+    // M[P, j] = conj(M[j, P]) above the diagonal: lanes along the row j
+    for (int e = threadIdx.x; e < NB * 64; e += 256) {
+      const int c = e / NB, q = e % NB, j = j0 + c;
+      double2 x = make_double2(0.0, 0.0);
+      if (q < nb && j < n) {
+        x = A[(int64_t)j * n + P0 + q];
+        x.y = -x.y;
+      }
+      sa[q][c] = x;
+    }
   }
-  // column panel (independent of the LDS contents)
-  for (int e = threadIdx.x; e < 64 * NB; e += 256) {
-    const int r = e / NB, p = e % NB, i = j0 + r;
-    if (i >= n) continue;
-    const bool in_p = i >= P0 && i < P0 + nb;
-    cp[((int64_t)m * n + i) * NB + p] =
-        (p < nb && !in_p) ? A[(int64_t)i * n + P0 + p] : make_double2(0.0, 0.0);
+  // column panel for the rows of this tile below the pivot block (stored);
+  // rows above it are written after the MFMAs, through LDS
+  if (tile >= bp) {
+    for (int e = threadIdx.x; e < 64 * NB; e += 256) {
+      const int r = e / NB, p = e % NB, i = j0 + r;
+      if (i >= n) continue;
+      const bool in_p = i >= P0 && i < P0 + nb;
+      cp[((int64_t)m * n + i) * NB + p] =
+          (p < nb && !in_p) ? A[(int64_t)i * n + P0 + p] : make_double2(0.0, 0.0);
+    }
   }
   __syncthreads();
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -179,16 +197,36 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
         rp[((int64_t)m * NB + p) * n + j] = val;
       }
     }
+  if (tile < bp) {
+    // rows i of this tile lie above the pivot block: M[i, p] = -conj(M[p, i]),
+    // M[p, i] stored; staged through LDS so that reads and writes run along rows
+    __syncthreads();
+    for (int e = threadIdx.x; e < NB * 64; e += 256) {
+      const int q = e / 64, r = e % 64, i = j0 + r;
+      sa[q][r] = (q < nb && i < n) ? A[(int64_t)(P0 + q) * n + i] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * NB; e += 256) {
+      const int r = e / NB, q = e % NB, i = j0 + r;
+      if (i >= n) continue;
+      const double2 x = sa[q][r];
+      cp[((int64_t)m * n + i) * NB + q] = make_double2(-x.x, x.y);
+    }
+  }
 }
 
-// Rank-nb update, persistent: each workgroup of four waves walks a share of
-// the 64 x 64 tiles of all matrices (T tiles per side).  Workgroups are dealt
-// to the XCDs in turn, so workgroup b serves partition b % XP (XP = 8, or the
-// grid if smaller), and partition x owns the column tiles [x T / XP,
-// (x + 1) T / XP) of every row tile and matrix: the row panels its tiles read
-// (the R chunks, about n_g / XP columns) stay in that XCD's L2 while A streams
-// through.  Within a partition the tiles run matrix by matrix, row tile by row
-// tile, and its workgroups take every nk-th of them.
+// Rank-nb update, persistent, on the block-lower tiles only (row tile >=
+// column tile; T tiles per side): the sweep of a Hermitian matrix keeps the
+// swept and unswept diagonal blocks Hermitian and the blocks between them
+// anti-Hermitian, so the tiles above the diagonal follow from those below
+// (the panels read them so, and k_w_mirror fills them at the end).
+// Workgroups are dealt to the XCDs in turn: workgroup b serves partition
+// b % XP (XP = 8, or the grid if smaller), which owns the column tiles x,
+// 2 XP - 1 - x, 2 XP + x, ... (a snake, so that the partitions get about
+// equal numbers of lower tiles) of every matrix, so the row panels its tiles
+// read stay in that XCD's L2 while A streams through.  Within a partition the
+// tiles run matrix by matrix, column by column, and its workgroups take every
+// nk-th of them.
 // Per tile: A[i][j] <- R[i - P0][j] for i in the pivot block P, else
 // A[i][j] [j outside P] - sum_p C[i][p] R[p][j].
 //
@@ -207,14 +245,39 @@ constexpr int UCH = NB / UKC;                 // chunks per tile
 struct UTile {
   int m, i0, j0;
 };
-// local tile q of a partition owning columns [c_lo, c_lo + wx)
-__device__ __forceinline__ UTile utile(int q, int T, int c_lo, int wx) {
+// column tile number g of partition x (snake order), or T and above when past
+// the last
+__device__ __forceinline__ int ucol(int g, int x, int XP) {
+  return (g & 1) ? g * XP + XP - 1 - x : g * XP + x;
+}
+// lower tiles of one matrix in partition x
+__device__ __forceinline__ int ulower(int T, int x, int XP) {
+  int cnt = 0;
+  for (int g = 0;; ++g) {
+    const int tj = ucol(g, x, XP);
+    if (tj >= T) {
+      if (g * XP >= T) break;
+      continue;
+    }
+    cnt += T - tj;
+  }
+  return cnt;
+}
+// local tile q of partition x (L lower tiles per matrix)
+__device__ __forceinline__ UTile utile(int q, int T, int x, int XP, int L) {
   UTile u;
-  u.m = q / (T * wx);
-  const int r = q - u.m * T * wx;
-  u.i0 = (r / wx) * 64;
-  u.j0 = (c_lo + r % wx) * 64;
-  return u;
+  u.m = q / L;
+  int r = q - u.m * L;
+  for (int g = 0;; ++g) {
+    const int tj = ucol(g, x, XP);
+    if (tj >= T) continue;                     // the last group is partial; q < L ends the walk
+    if (r < T - tj) {
+      u.j0 = tj * 64;
+      u.i0 = (tj + r) * 64;
+      return u;
+    }
+    r -= T - tj;
+  }
 }
 
 // one chunk of panel values per thread: 4 C entries and 4 R entries
@@ -245,7 +308,7 @@ __device__ __forceinline__ void ustore(const d2v (&hc)[4], const d2v (&hr)[4],
 __global__ __launch_bounds__(256, 2) void k_w_update(double2 *__restrict__ a,
                                                      const double2 *__restrict__ rp,
                                                      const double2 *__restrict__ cp, int n,
-                                                     int P0, int T, int n_tiles) {
+                                                     int P0, int T, int n_mat) {
   __shared__ double2 sc0[64][UKC + 1], sc1[64][UKC + 1];
   __shared__ double2 sr0[UKC][64], sr1[UKC][64];
   const int nb = min(NB, n - P0);
@@ -255,14 +318,14 @@ __global__ __launch_bounds__(256, 2) void k_w_update(double2 *__restrict__ a,
   const int XP = min(8, G);
   const int x = (int)blockIdx.x % XP, k = (int)blockIdx.x / XP;
   const int nk = (G - x + XP - 1) / XP;        // workgroups of partition x
-  const int c_lo = x * T / XP, wx = (x + 1) * T / XP - c_lo;
-  const int part_tiles = (n_tiles / (T * T)) * T * wx;
+  const int L = ulower(T, x, XP);
+  const int part_tiles = n_mat * L;
   const int my_tiles = part_tiles > k ? (part_tiles - k + nk - 1) / nk : 0;
   if (my_tiles == 0) return;                   // the whole workgroup leaves together
   const int n_chunks = my_tiles * UCH;
   // chunk c: local tile k + (c / UCH) nk, band chunk c % UCH; chunks past the
   // end load the last tile again (never used)
-  auto chunk_tile = [&](int c) { return utile(k + min(c / UCH, my_tiles - 1) * nk, T, c_lo, wx); };
+  auto chunk_tile = [&](int c) { return utile(k + min(c / UCH, my_tiles - 1) * nk, T, x, XP, L); };
   // register sets X and Y: before chunk c, X holds chunk c + 1 and Y chunk
   // c + 2 for even c, the other way round for odd c
   d2v xc[4], xr[4], yc[4], yr[4];
@@ -348,6 +411,30 @@ __global__ __launch_bounds__(256, 2) void k_w_update(double2 *__restrict__ a,
   }
 }
 
+// grid (T, T, n_mat): after the last pivot block A holds eps^-1 in its
+// block-lower tiles; the tile (I, J) above the diagonal (I < J) becomes the
+// conjugate transpose of tile (J, I), through LDS so that reads and writes run
+// along rows.
+__global__ __launch_bounds__(256) void k_w_mirror(double2 *__restrict__ a, int n) {
+  const int I = blockIdx.y, J = blockIdx.x;
+  if (I >= J) return;
+  __shared__ double2 t[64][64 + 1];
+  double2 *A = a + (int64_t)blockIdx.z * n * n;
+  const int r0 = J * 64, c0 = I * 64;          // source tile (J, I)
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e / 64, c = e % 64;
+    if (r0 + r < n && c0 + c < n) t[r][c] = A[(int64_t)(r0 + r) * n + c0 + c];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e / 64, c = e % 64;          // target (c0 + r, r0 + c) = conj(source (r0 + c, c0 + r))
+    if (c0 + r < n && r0 + c < n) {
+      const double2 x = t[c][r];
+      A[(int64_t)(c0 + r) * n + r0 + c] = make_double2(x.x, -x.y);
+    }
+  }
+}
+
 // grid (ceil(n / 256), n): per element (g, h), W~(i omega_k) = s_g s_h
 // (A_k(g, h) - delta) for every k (written when w_omega is not null) and
 // W~(i tau_j) = sum_k ict[j][k] W~(i omega_k), summed in increasing k, all
@@ -415,17 +502,20 @@ hipError_t launch_w_block(void *a, void *dinv, void *rp, void *cp, int n, int n_
         num_cu <= 0)
       num_cu = 256;
   }
-  const int64_t n_tiles = (int64_t)tiles * tiles * n_mat;
+  const int64_t n_tiles = (int64_t)tiles * (tiles + 1) / 2 * n_mat;   // block-lower tiles
   if (n_tiles > 0x7fffffff) return hipErrorInvalidValue;
   const int grid = (int)std::min<int64_t>(n_tiles, 2 * num_cu);
   hipLaunchKernelGGL(k_w_update, dim3(grid), dim3(256), 0, st, (double2 *)a, (const double2 *)rp,
-                     (const double2 *)cp, n, P0, tiles, (int)n_tiles);
+                     (const double2 *)cp, n, P0, tiles, n_mat);
   return hipGetLastError();
 }
 
-hipError_t launch_w_final(const void *a, const double *s, const double *ict, void *w_tau,
+hipError_t launch_w_final(void *a, const double *s, const double *ict, void *w_tau,
                           void *w_omega, int n, int n_omega, int n_tau, hipStream_t st) {
   if (n > 65535) return hipErrorInvalidValue;
+  const int tiles = (n + 63) / 64;
+  if (tiles > 1)
+    hipLaunchKernelGGL(k_w_mirror, dim3(tiles, tiles, n_omega), dim3(256), 0, st, (double2 *)a, n);
   const dim3 grid((n + 255) / 256, n), block(256);
   const double2 *A = (const double2 *)a;
   double2 *T = (double2 *)w_tau, *O = (double2 *)w_omega;
