@@ -119,33 +119,17 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
                                                  const double2 *__restrict__ dinv,
                                                  double2 *__restrict__ rp, double2 *__restrict__ cp,
                                                  int n, int P0) {
-  __shared__ double2 sd[NB][NB + 1];
-  __shared__ double2 sa[NB][64 + 1];
+  // the contraction over the block's 64 bands runs in two halves of PH, so
+  // that two workgroups share a CU
+  constexpr int PH = NB / 2;
+  __shared__ double2 sd[NB][PH + 1];
+  __shared__ double2 sa[PH][64 + 1];
   const int m = blockIdx.y;
   const int j0 = blockIdx.x * 64;
   const int tile = (int)blockIdx.x, bp = P0 / 64;   // tile index, pivot block index
   const int nb = min(NB, n - P0);
   const double2 *A = a + (int64_t)m * n * n;
   const double2 *D = dinv + (int64_t)m * NB * NB;
-  for (int e = threadIdx.x; e < NB * NB; e += 256) sd[e / NB][e % NB] = D[e];
-  if (tile <= bp) {
-    // M[P, j] is stored (block-lower): lanes along j
-    for (int e = threadIdx.x; e < NB * 64; e += 256) {
-      const int q = e / 64, c = e % 64, j = j0 + c;
-      sa[q][c] = (q < nb && j < n) ? A[(int64_t)(P0 + q) * n + j] : make_double2(0.0, 0.0);
-    }
-  } else {
-    // M[P, j] = conj(M[j, P]) above the diagonal: lanes along the row j
-    for (int e = threadIdx.x; e < NB * 64; e += 256) {
-      const int c = e / NB, q = e % NB, j = j0 + c;
-      double2 x = make_double2(0.0, 0.0);
-      if (q < nb && j < n) {
-        x = A[(int64_t)j * n + P0 + q];
-        x.y = -x.y;
-      }
-      sa[q][c] = x;
-    }
-  }
   // column panel for the rows of this tile below the pivot block (stored);
   // rows above it are written after the MFMAs, through LDS
   if (tile >= bp) {
@@ -157,7 +141,6 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
           (p < nb && !in_p) ? A[(int64_t)i * n + P0 + p] : make_double2(0.0, 0.0);
     }
   }
-  __syncthreads();
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int wr = w >> 1, wc = w & 1;
   d4v re[2][2], im[2][2];
@@ -165,22 +148,46 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) re[bi][bj] = im[bi][bj] = d4v{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-  for (int k = 0; k < NB; k += 4) {
-    double2 x[2], y[2];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi) x[bi] = sd[wr * 32 + bi * 16 + (l & 15)][k + (l >> 4)];
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) y[bj] = sa[k + (l >> 4)][wc * 32 + bj * 16 + (l & 15)];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj) {
-        re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].x, y[bj].x, re[bi][bj], 0, 0, 0);
-        re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x[bi].y, y[bj].y, re[bi][bj], 0, 0, 0);
-        im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].x, y[bj].y, im[bi][bj], 0, 0, 0);
-        im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].y, y[bj].x, im[bi][bj], 0, 0, 0);
+  for (int h = 0; h < 2; ++h) {
+    const int q0 = h * PH;
+    for (int e = threadIdx.x; e < NB * PH; e += 256) sd[e / PH][e % PH] = D[(e / PH) * NB + q0 + e % PH];
+    if (tile <= bp) {
+      // M[P, j] is stored (block-lower): lanes along j
+      for (int e = threadIdx.x; e < PH * 64; e += 256) {
+        const int q = e / 64, c = e % 64, j = j0 + c;
+        sa[q][c] = (q0 + q < nb && j < n) ? A[(int64_t)(P0 + q0 + q) * n + j] : make_double2(0.0, 0.0);
       }
+    } else {
+      // M[P, j] = conj(M[j, P]) above the diagonal: lanes along the row j
+      for (int e = threadIdx.x; e < PH * 64; e += 256) {
+        const int c = e / PH, q = e % PH, j = j0 + c;
+        double2 x = make_double2(0.0, 0.0);
+        if (q0 + q < nb && j < n) {
+          x = A[(int64_t)j * n + P0 + q0 + q];
+          x.y = -x.y;
+        }
+        sa[q][c] = x;
+      }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < PH; k += 4) {
+      double2 x[2], y[2];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) x[bi] = sd[wr * 32 + bi * 16 + (l & 15)][k + (l >> 4)];
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) y[bj] = sa[k + (l >> 4)][wc * 32 + bj * 16 + (l & 15)];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].x, y[bj].x, re[bi][bj], 0, 0, 0);
+          re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x[bi].y, y[bj].y, re[bi][bj], 0, 0, 0);
+          im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].x, y[bj].y, im[bi][bj], 0, 0, 0);
+          im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi].y, y[bj].x, im[bi][bj], 0, 0, 0);
+        }
+    }
+    __syncthreads();
   }
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -193,24 +200,29 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
       for (int v = 0; v < 4; ++v) {
         const int p = wr * 32 + bi * 16 + (l >> 4) + 4 * v;
         double2 val = make_double2(0.0, 0.0);
-        if (p < nb) val = in_p ? sd[p][j - P0] : make_double2(re[bi][bj][v], im[bi][bj][v]);
+        if (p < nb) val = in_p ? D[p * NB + (j - P0)] : make_double2(re[bi][bj][v], im[bi][bj][v]);
         rp[((int64_t)m * NB + p) * n + j] = val;
       }
     }
   if (tile < bp) {
     // rows i of this tile lie above the pivot block: M[i, p] = -conj(M[p, i]),
-    // M[p, i] stored; staged through LDS so that reads and writes run along rows
-    __syncthreads();
-    for (int e = threadIdx.x; e < NB * 64; e += 256) {
-      const int q = e / 64, r = e % 64, i = j0 + r;
-      sa[q][r] = (q < nb && i < n) ? A[(int64_t)(P0 + q) * n + i] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * NB; e += 256) {
-      const int r = e / NB, q = e % NB, i = j0 + r;
-      if (i >= n) continue;
-      const double2 x = sa[q][r];
-      cp[((int64_t)m * n + i) * NB + q] = make_double2(-x.x, x.y);
+    // M[p, i] stored; staged through LDS in halves so that reads and writes
+    // run along rows
+    for (int h = 0; h < 2; ++h) {
+      const int q0 = h * PH;
+      for (int e = threadIdx.x; e < PH * 64; e += 256) {
+        const int q = e / 64, r = e % 64, i = j0 + r;
+        sa[q][r] = (q0 + q < nb && i < n) ? A[(int64_t)(P0 + q0 + q) * n + i] : make_double2(0.0, 0.0);
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < 64 * PH; e += 256) {
+        const int r = e / PH, q = e % PH, i = j0 + r;
+        if (i < n) {
+          const double2 x = sa[q][r];
+          cp[((int64_t)m * n + i) * NB + q0 + q] = make_double2(-x.x, x.y);
+        }
+      }
+      __syncthreads();
     }
   }
 }
