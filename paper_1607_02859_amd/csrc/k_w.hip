@@ -19,8 +19,13 @@
 //              A[i][j] * [j outside P] - sum_p C[i][p] R[p][j]
 //              (rank-nb update on FP64 MFMA; persistent, the next panel
 //              chunks loaded while the MFMAs run).
-// After the last block A holds eps^-1.  k_w_final then forms W~(i omega_k)
-// and the inverse cosine transform in one pass over the matrices.
+// Only the block-lower 64 x 64 tiles are stored and updated: the sweep keeps
+// the swept and unswept diagonal blocks Hermitian and the blocks between
+// them anti-Hermitian, so a tile above the diagonal is the conjugate
+// transpose of its mirror, negated when exactly one of its two blocks is
+// swept (the panels read it so).  After the last block the block-lower tiles
+// hold eps^-1; k_w_mirror fills the upper tiles (Hermitian), and k_w_final
+// forms W~(i omega_k) and the inverse cosine transform in one pass.
 #include <algorithm>
 #include <type_traits>
 
