@@ -6,3 +6,4 @@ import this package; the library never does.
 """
 from . import chi  # noqa: F401
 from . import w  # noqa: F401
+from . import pade  # noqa: F401
