@@ -237,6 +237,52 @@ gwchi_status gwchi_w_build(gwchi_ctx *ctx, const gwchi_w_item *items, int32_t n_
 gwchi_status gwchi_w_build_device(gwchi_ctx *ctx, const gwchi_w_item *items, int32_t n_items,
                                   void *hip_stream, gwchi_w_report *report);
 
+/* ------------------------------------------------------------------------
+ * Analytic continuation by Thiele's reciprocal differences (Sec. II.E.1,
+ * Eqs. (72)-(74)), FP64, for many functions known at the same N points:
+ *
+ *   g_1(z_j) = f_j,
+ *   g_n(z_j) = (g_{n-1}(z_{n-1}) - g_{n-1}(z_j)) / ((z_j - z_{n-1}) g_{n-1}(z_j)),
+ *   a_n      = g_n(z_n),
+ *   P_N(w)   = a_1 / (1 + a_2 (w - z_1) / (1 + ... a_N (w - z_{N-1}) / 1)),
+ *
+ * the tail (w - z_N) g_{N+1}(w) of the last denominator dropped.  A zero
+ * denominator in the recursion (a function already represented by fewer
+ * levels, e.g. a constant) ends the fraction: that difference and every
+ * deeper one are 0.  P_N(z_j) = f_j.  A denominator of zero in the
+ * evaluation gives a non-finite value at that point.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t n_points;         /* N, in [1, 32]                                             */
+  const double *z;          /* [N] complex interleaved, distinct and finite; host memory */
+  int32_t n_fun;            /* >= 1                                                       */
+  /* f[fun][j] = f_fun(z_j), complex interleaved, [n_fun][N].  gwchi_pade: host
+   * memory; gwchi_pade_device: device memory.  Read only. */
+  const double *f;
+  int32_t n_eval;           /* M >= 0                                                     */
+  const double *w;          /* [M] complex interleaved, finite; host memory (NULL if M = 0) */
+  /* Outputs, same memory kind as f: out[fun][p] = P_N(w_p), [n_fun][M] (NULL if
+   * M = 0); coef[fun][n] = a_{n+1}, [n_fun][N], or NULL. */
+  double *out;
+  double *coef;
+} gwchi_pade_item;
+
+/* Host-only check of a continuation item (no device is touched): EINVAL on
+ * NULL pointers, N outside [1, 32], n_fun < 1, n_eval < 0, non-finite or
+ * repeated z, non-finite w. */
+gwchi_status gwchi_pade_validate(const gwchi_pade_item *item);
+
+/* Continuation with host buffers; blocking.  ms, if not NULL, receives the
+ * kernel's stream time. */
+gwchi_status gwchi_pade(gwchi_ctx *ctx, const gwchi_pade_item *item, double *ms);
+
+/* Same with f, out and coef in device memory of the context's device (z and w
+ * in host memory).  Enqueued on hip_stream (NULL = the context's stream);
+ * returns once enqueued unless ms is not NULL, in which case it waits and
+ * reports the kernel's stream time. */
+gwchi_status gwchi_pade_device(gwchi_ctx *ctx, const gwchi_pade_item *item, void *hip_stream,
+                               double *ms);
+
 /* Message of the last failure on this context (never NULL). */
 const char *gwchi_last_error(const gwchi_ctx *ctx);
 

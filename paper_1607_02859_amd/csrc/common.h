@@ -244,4 +244,13 @@ hipError_t launch_w_block(void *a, void *dinv, void *rp, void *cp, int n, int n_
 hipError_t launch_w_final(void *a, const double *s, const double *ict, void *w_tau,
                           void *w_omega, int n, int n_omega, int n_tau, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// Analytic continuation by Thiele's reciprocal differences (FP64): f
+// [n_fun][n], z [n], w [m], coef [n_fun][n] (or null), out [n_fun][m], all
+// complex device arrays; n <= kPadeMaxPoints.
+// ---------------------------------------------------------------------------
+constexpr int kPadeMaxPoints = 32;
+hipError_t launch_pade(const void *f, int n_fun, int n, const void *z, const void *w, int m,
+                       void *coef, void *out, hipStream_t st);
+
 }  // namespace gw

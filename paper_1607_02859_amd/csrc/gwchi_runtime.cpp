@@ -122,6 +122,9 @@ struct gwchi_ctx {
   // being inverted, the pivot-block panels, the per-item tables, the pivot flag
   DevBuf b_wchi, b_wtau, b_womega, b_wa, b_wdinv, b_wrp, b_wcp, b_wtab, b_wflag;
   HostPinned h_wtab;
+  // analytic continuation: host-entry copies of f / out / coef, the points z and w
+  DevBuf b_pf, b_pout, b_pcoef, b_ptab;
+  HostPinned h_ptab;
   HostPinned h_tables, h_norm;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::vector<hipEvent_t> ev_pool;
@@ -1473,6 +1476,78 @@ gwchi_status run_w(gwchi_ctx *ctx, const gwchi_w_item *items, int n_items,
   return GWCHI_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Analytic continuation (Sec. II.E.1).
+// ---------------------------------------------------------------------------
+
+gwchi_status validate_pade(gwchi_ctx *ctx, const gwchi_pade_item *it) {
+  if (!it || !it->z || !it->f || (it->n_eval > 0 && (!it->w || !it->out))) {
+    set_err(ctx, "pade: item, z, f (and w, out when n_eval > 0) must not be NULL");
+    return GWCHI_EINVAL;
+  }
+  if (it->n_points < 1 || it->n_points > kPadeMaxPoints || it->n_fun < 1 || it->n_eval < 0) {
+    set_err(ctx, "pade: n_points must be in [1, " + std::to_string(kPadeMaxPoints) +
+                     "], n_fun >= 1, n_eval >= 0");
+    return GWCHI_EINVAL;
+  }
+  if (!finite_all(it->z, 2 * (int64_t)it->n_points) ||
+      (it->n_eval > 0 && !finite_all(it->w, 2 * (int64_t)it->n_eval))) {
+    set_err(ctx, "pade: z and w must be finite");
+    return GWCHI_EINVAL;
+  }
+  for (int a = 0; a < it->n_points; ++a)
+    for (int b = a + 1; b < it->n_points; ++b)
+      if (it->z[2 * a] == it->z[2 * b] && it->z[2 * a + 1] == it->z[2 * b + 1]) {
+        set_err(ctx, "pade: the points z must be distinct");
+        return GWCHI_EINVAL;
+      }
+  return GWCHI_OK;
+}
+
+// Enqueue the continuation of an item whose f, out and coef are device
+// pointers on the context's stream; with ms, wait and time it.
+gwchi_status run_pade(gwchi_ctx *ctx, const gwchi_pade_item *it, double *ms) {
+  hipStream_t st = ctx->stream;
+  const int64_t nz = it->n_points, nw = it->n_eval;
+  const int64_t tab = 2 * (nz + nw);
+  HIPCHK(ctx->b_ptab.ensure(tab * 8, nullptr));
+  HIPCHK(hipStreamSynchronize(st));      // the pinned staging may feed an earlier copy
+  HIPCHK(ctx->h_ptab.ensure(tab * 8));
+  double *h = reinterpret_cast<double *>(ctx->h_ptab.p);
+  std::memcpy(h, it->z, nz * 16);
+  if (nw > 0) std::memcpy(h + 2 * nz, it->w, nw * 16);
+  HIPCHK(hipMemcpyAsync(ctx->b_ptab.p, h, tab * 8, hipMemcpyHostToDevice, st));
+  const double *zd = reinterpret_cast<const double *>(ctx->b_ptab.p);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ms) {
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, st));
+  }
+  hipError_t e = launch_pade(it->f, it->n_fun, it->n_points, zd, zd + 2 * nz, it->n_eval,
+                             it->coef, it->out, st);
+  if (e != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    set_err(ctx, std::string("pade launch: ") + hipGetErrorString(e));
+    return GWCHI_EDEVICE;
+  }
+  if (ms) {
+    float t = 0.f;
+    e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) {
+      set_err(ctx, std::string("pade: ") + hipGetErrorString(e));
+      return GWCHI_EDEVICE;
+    }
+    *ms = t;
+  }
+  return GWCHI_OK;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -1557,10 +1632,12 @@ gwchi_status gwchi_destroy(gwchi_ctx *ctx) {
   for (DevBuf *b : {&ctx->b_phi, &ctx->b_out, &ctx->b_psi, &ctx->b_slab, &ctx->b_xr, &ctx->b_x,
                     &ctx->b_tmp, &ctx->b_tables, &ctx->b_norm, &ctx->b_ctr, &ctx->b_wchi,
                     &ctx->b_wtau, &ctx->b_womega, &ctx->b_wa, &ctx->b_wdinv, &ctx->b_wrp,
-                    &ctx->b_wcp, &ctx->b_wtab, &ctx->b_wflag})
+                    &ctx->b_wcp, &ctx->b_wtab, &ctx->b_wflag, &ctx->b_pf, &ctx->b_pout,
+                    &ctx->b_pcoef, &ctx->b_ptab})
     b->release();
   ctx->h_tables.release();
   ctx->h_wtab.release();
+  ctx->h_ptab.release();
   ctx->h_norm.release();
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -1775,6 +1852,77 @@ gwchi_status gwchi_w_build(gwchi_ctx *ctx, const gwchi_w_item *items, int32_t n_
       total.n_launches += r.n_launches;
     }
     if (report) *report = total;
+    return GWCHI_OK;
+  } catch (const std::bad_alloc &) {
+    set_err(ctx, "host allocation failed");
+    return GWCHI_ENOMEM;
+  } catch (...) {
+    set_err(ctx, "internal error");
+    return GWCHI_EDEVICE;
+  }
+}
+
+gwchi_status gwchi_pade_validate(const gwchi_pade_item *item) {
+  try {
+    return validate_pade(nullptr, item);
+  } catch (...) {
+    g_tls_error = "internal error";
+    return GWCHI_EDEVICE;
+  }
+}
+
+gwchi_status gwchi_pade_device(gwchi_ctx *ctx, const gwchi_pade_item *item, void *hip_stream,
+                               double *ms) {
+  if (!ctx) {
+    g_tls_error = "ctx is NULL";
+    return GWCHI_EINVAL;
+  }
+  try {
+    gwchi_status st = validate_pade(ctx, item);
+    if (st != GWCHI_OK) return st;
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t us = reinterpret_cast<hipStream_t>(hip_stream);
+    HIPCHK(hipEventRecord(ctx->ev_in, us));
+    HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->ev_in, 0));
+    st = run_pade(ctx, item, ms);
+    if (st != GWCHI_OK) return st;
+    HIPCHK(hipEventRecord(ctx->ev_out, ctx->stream));
+    HIPCHK(hipStreamWaitEvent(us, ctx->ev_out, 0));
+    return GWCHI_OK;
+  } catch (const std::bad_alloc &) {
+    set_err(ctx, "host allocation failed");
+    return GWCHI_ENOMEM;
+  } catch (...) {
+    set_err(ctx, "internal error");
+    return GWCHI_EDEVICE;
+  }
+}
+
+gwchi_status gwchi_pade(gwchi_ctx *ctx, const gwchi_pade_item *item, double *ms) {
+  if (!ctx) {
+    g_tls_error = "ctx is NULL";
+    return GWCHI_EINVAL;
+  }
+  try {
+    gwchi_status st = validate_pade(ctx, item);
+    if (st != GWCHI_OK) return st;
+    HIPCHK(hipSetDevice(ctx->device));
+    const size_t fb = (size_t)item->n_fun * item->n_points * 16;
+    const size_t ob = (size_t)item->n_fun * item->n_eval * 16;
+    HIPCHK(ctx->b_pf.ensure(fb, nullptr));
+    if (ob > 0) HIPCHK(ctx->b_pout.ensure(ob, nullptr));
+    if (item->coef) HIPCHK(ctx->b_pcoef.ensure(fb, nullptr));
+    HIPCHK(hipMemcpy(ctx->b_pf.p, item->f, fb, hipMemcpyHostToDevice));
+    gwchi_pade_item d = *item;
+    d.f = reinterpret_cast<const double *>(ctx->b_pf.p);
+    d.out = ob > 0 ? reinterpret_cast<double *>(ctx->b_pout.p) : nullptr;
+    d.coef = item->coef ? reinterpret_cast<double *>(ctx->b_pcoef.p) : nullptr;
+    double t = 0.0;
+    st = run_pade(ctx, &d, &t);
+    if (st != GWCHI_OK) return st;
+    if (ob > 0) HIPCHK(hipMemcpy(item->out, d.out, ob, hipMemcpyDeviceToHost));
+    if (item->coef) HIPCHK(hipMemcpy(item->coef, d.coef, fb, hipMemcpyDeviceToHost));
+    if (ms) *ms = t;
     return GWCHI_OK;
   } catch (const std::bad_alloc &) {
     set_err(ctx, "host allocation failed");

@@ -1,0 +1,98 @@
+// Analytic continuation by Thiele's reciprocal differences (gfx950), FP64.
+//
+// For each function f known at N points z_1..z_N (Sec. II.E.1, Eqs. (72)-(74)):
+//   g_1(z_j) = f_j,  g_n(z_j) = (g_{n-1}(z_{n-1}) - g_{n-1}(z_j)) / ((z_j - z_{n-1}) g_{n-1}(z_j)),
+//   a_n = g_n(z_n),
+//   P_N(w) = a_1 / (1 + a_2 (w - z_1) / (1 + ... a_N (w - z_{N-1}) / 1)),
+// the tail of the last denominator dropped; an exactly zero denominator in
+// the recursion ends the fraction (that difference and every deeper one are 0).
+//
+// One wave per function: every lane runs the O(N^2) recursion in registers
+// (the table g_n(z_j) is updated in place, j >= n), then the lanes share the
+// evaluation points, so that the outputs of a function are written in
+// contiguous runs.  The points z and w are shared by all functions.
+#include "common.h"
+
+namespace gw {
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  const double d = 1.0 / (b.x * b.x + b.y * b.y);
+  return make_double2((a.x * b.x + a.y * b.y) * d, (a.y * b.x - a.x * b.y) * d);
+}
+
+// f [n_fun][n], z [n], w [m] complex; coef [n_fun][n] (or null), out [n_fun][m]
+template <int NMAX>
+__global__ __launch_bounds__(256) void k_pade(const double2 *__restrict__ f, int n_fun, int n,
+                                              const double2 *__restrict__ z,
+                                              const double2 *__restrict__ w, int m,
+                                              double2 *__restrict__ coef,
+                                              double2 *__restrict__ out) {
+  const int fun = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  if (fun >= n_fun) return;
+  double2 g[NMAX];
+  const double2 *F = f + (int64_t)fun * n;
+#pragma unroll
+  for (int j = 0; j < NMAX; ++j) g[j] = j < n ? F[j] : make_double2(0.0, 0.0);
+  // level k + 1: g[j] <- (a_k - g[j]) / ((z_j - z_k) g[j]) for j > k - 1
+#pragma unroll
+  for (int k = 1; k < NMAX; ++k) {
+    const double2 prev = g[k - 1];
+    const double2 zk = z[min(k - 1, n - 1)];
+#pragma unroll
+    for (int j = k; j < NMAX; ++j) {
+      if (j < n) {                                // (j < n implies k < n)
+        const double2 zj = z[j];
+        const double2 den = cmul(make_double2(zj.x - zk.x, zj.y - zk.y), g[j]);
+        g[j] = (den.x == 0.0 && den.y == 0.0)
+                   ? make_double2(0.0, 0.0)
+                   : cdiv(make_double2(prev.x - g[j].x, prev.y - g[j].y), den);
+      }
+    }
+  }
+  if (coef != nullptr && l == 0) {
+    double2 *C = coef + (int64_t)fun * n;
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j)
+      if (j < n) C[j] = g[j];
+  }
+  double2 *O = out + (int64_t)fun * m;
+  for (int p = l; p < m; p += 64) {
+    const double2 wp = w[p];
+    double2 t = make_double2(1.0, 0.0);
+#pragma unroll
+    for (int k = NMAX - 1; k >= 1; --k) {
+      if (k < n) {
+        const double2 zk = z[k - 1];
+        const double2 q = cdiv(cmul(g[k], make_double2(wp.x - zk.x, wp.y - zk.y)), t);
+        t = make_double2(1.0 + q.x, q.y);
+      }
+    }
+    O[p] = cdiv(g[0], t);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_pade(const void *f, int n_fun, int n, const void *z, const void *w, int m,
+                       void *coef, void *out, hipStream_t st) {
+  if (n_fun < 1 || n < 1 || n > kPadeMaxPoints || m < 0) return hipErrorInvalidValue;
+  const int64_t blocks = ((int64_t)n_fun + 3) / 4;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  const double2 *F = (const double2 *)f, *Z = (const double2 *)z, *W = (const double2 *)w;
+  double2 *C = (double2 *)coef, *O = (double2 *)out;
+  const dim3 grid((unsigned)blocks), block(256);
+  if (n <= 8)
+    hipLaunchKernelGGL(k_pade<8>, grid, block, 0, st, F, n_fun, n, Z, W, m, C, O);
+  else if (n <= 16)
+    hipLaunchKernelGGL(k_pade<16>, grid, block, 0, st, F, n_fun, n, Z, W, m, C, O);
+  else
+    hipLaunchKernelGGL(k_pade<32>, grid, block, 0, st, F, n_fun, n, Z, W, m, C, O);
+  return hipGetLastError();
+}
+
+}  // namespace gw

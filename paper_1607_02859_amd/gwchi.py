@@ -21,7 +21,8 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTSUP", 5: "ENU
 
 EXPORTS = ["gwchi_create", "gwchi_destroy", "gwchi_set_options", "gwchi_get_options",
            "gwchi_validate", "gwchi_chi_build", "gwchi_chi_build_device", "gwchi_autotune",
-           "gwchi_last_error", "gwchi_version", "gwchi_w_build", "gwchi_w_build_device", "gwchi_w_validate"]
+           "gwchi_last_error", "gwchi_version", "gwchi_w_build", "gwchi_w_build_device", "gwchi_w_validate",
+           "gwchi_pade", "gwchi_pade_device", "gwchi_pade_validate"]
 
 
 class GwchiItem(C.Structure):
@@ -111,6 +112,19 @@ class GwchiWReport(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class GwchiPadeItem(C.Structure):
+    _fields_ = [
+        ("n_points", C.c_int32),
+        ("z", C.c_void_p),
+        ("n_fun", C.c_int32),
+        ("f", C.c_void_p),
+        ("n_eval", C.c_int32),
+        ("w", C.c_void_p),
+        ("out", C.c_void_p),
+        ("coef", C.c_void_p),
+    ]
+
+
 _lib = None
 
 
@@ -141,6 +155,9 @@ def load(path: str = LIB_PATH):
     lib.gwchi_autotune.argtypes = [C.c_void_p, P(GwchiItem), C.c_int32, C.c_int]
     lib.gwchi_w_build.argtypes = [C.c_void_p, P(GwchiWItem), C.c_int32, P(GwchiWReport)]
     lib.gwchi_w_validate.argtypes = [P(GwchiWItem), C.c_int32]
+    lib.gwchi_pade_validate.argtypes = [P(GwchiPadeItem)]
+    lib.gwchi_pade.argtypes = [C.c_void_p, P(GwchiPadeItem), P(C.c_double)]
+    lib.gwchi_pade_device.argtypes = [C.c_void_p, P(GwchiPadeItem), C.c_void_p, P(C.c_double)]
     lib.gwchi_w_build_device.argtypes = [C.c_void_p, P(GwchiWItem), C.c_int32, C.c_void_p,
                                          P(GwchiWReport)]
     lib.gwchi_last_error.argtypes = [C.c_void_p]
@@ -148,7 +165,8 @@ def load(path: str = LIB_PATH):
     lib.gwchi_version.restype = C.c_char_p
     for f in ("gwchi_create", "gwchi_destroy", "gwchi_set_options", "gwchi_get_options",
               "gwchi_validate", "gwchi_chi_build", "gwchi_chi_build_device", "gwchi_autotune",
-              "gwchi_w_build", "gwchi_w_build_device", "gwchi_w_validate"):
+              "gwchi_w_build", "gwchi_w_build_device", "gwchi_w_validate",
+              "gwchi_pade", "gwchi_pade_device", "gwchi_pade_validate"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -254,6 +272,35 @@ def w_validate(witems) -> int:
         its.append(make_w_item(keep, w, w_tau=t))
     arr = (GwchiWItem * len(its))(*its)
     return int(lib.gwchi_w_validate(arr, len(its)))
+
+
+def make_pade_item(keep: _Keep, z, f, w, out, coef=None) -> GwchiPadeItem:
+    """Fill a GwchiPadeItem: z [N] and w [M] host complex arrays; f [n_fun][N],
+    out [n_fun][M] and coef [n_fun][N] host arrays or device tensors (complex128)."""
+    it = GwchiPadeItem()
+    z = np.ascontiguousarray(z, dtype=np.complex128)
+    w = np.ascontiguousarray(w, dtype=np.complex128)
+    keep.refs += [z, w]
+    it.n_points = int(z.shape[0])
+    it.z = _ptr(z)
+    it.n_fun = int(f.shape[0])
+    it.f = _ptr(f)
+    it.n_eval = int(w.shape[0])
+    it.w = _ptr(w) if w.shape[0] > 0 else 0
+    it.out = _ptr(out)
+    it.coef = _ptr(coef)
+    return it
+
+
+def pade_validate(z, f, w) -> int:
+    """gwchi_pade_validate on host arrays; returns the status code."""
+    lib = load()
+    keep = _Keep()
+    f = np.ascontiguousarray(f, dtype=np.complex128)
+    out = np.zeros((f.shape[0], max(1, len(w))), np.complex128)
+    keep.refs += [f, out]
+    it = make_pade_item(keep, z, f, w, out)
+    return int(lib.gwchi_pade_validate(C.byref(it)))
 
 
 class Context:
@@ -383,3 +430,36 @@ class Context:
         if st != 0:
             raise self._err(st)
         return rep.as_dict() if report else None
+
+    def pade(self, z, f, w, coef=False, report=False):
+        """Host-memory continuation (gwchi_pade): f [n_fun][N] complex at the
+        points z [N]; returns P_N at w [M] as [n_fun][M] (and the coefficients
+        [n_fun][N] when ``coef``; the kernel time in ms when ``report``)."""
+        keep = _Keep()
+        f = np.ascontiguousarray(f, dtype=np.complex128)
+        out = np.empty((f.shape[0], len(w)), np.complex128)
+        cf = np.empty_like(f) if coef else None
+        keep.refs += [f, out]
+        it = make_pade_item(keep, z, f, w, out, cf)
+        ms = C.c_double(0.0)
+        st = self.lib.gwchi_pade(self.h, C.byref(it), C.byref(ms))
+        if st != 0:
+            raise self._err(st)
+        res = (out, cf) if coef else out
+        return (res, ms.value) if report else res
+
+    def pade_device(self, z, f, w, out, coef=None, stream=None, report=False):
+        """Device-memory continuation (gwchi_pade_device): f, out (and coef)
+        complex128 device tensors; z and w host arrays."""
+        keep = _Keep()
+        it = make_pade_item(keep, z, f, w, out, coef)
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream()
+        sh = int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream or 0)
+        ms = C.c_double(0.0)
+        st = self.lib.gwchi_pade_device(self.h, C.byref(it), C.c_void_p(sh),
+                                        C.byref(ms) if report else None)
+        if st != 0:
+            raise self._err(st)
+        return ms.value if report else None

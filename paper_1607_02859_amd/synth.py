@@ -41,6 +41,7 @@ __all__ = [
     "WItem",
     "coulomb_sqrt",
     "make_w_item",
+    "make_pade_input",
 ]
 
 
@@ -382,3 +383,27 @@ def make_w_item(seed, n, n_tau, *, rank=None, strength=1.0, alpha=1.0,
         chi[kk] = -(b * lw[None, :]) @ b.conj().T
         chi[kk] = 0.5 * (chi[kk] + chi[kk].conj().T)
     return WItem(chi=chi, sqrt_v=coulomb_sqrt(n, g_index, alpha, k), ct=ct, omega=omega)
+
+
+# ----------------------------------------------------------------------------
+# Inputs of the analytic continuation
+# ----------------------------------------------------------------------------
+
+def make_pade_input(seed, n_fun, n_points, n_eval, *, n_poles=4, span=5.0, eta=0.05,
+                    w_max=30.0):
+    """Seeded functions of the shape of diagonal self-energies on the
+    imaginary axis: f(z) = c + sum_p r_p / (z - e_p) with n_poles poles per
+    function, e_p with real parts in [-span, span] eV and imaginary parts of
+    the sign that keeps f analytic in the upper half plane (a retarded
+    function), residues of order one, c real.  z_j = i omega_j with omega_j
+    log-spaced in [0.05, w_max] eV; the evaluation points are a real
+    frequency grid in [-2 span, 2 span] shifted by i eta.
+    Returns (z [N], f [n_fun][N], w [M], e [n_fun][P], r [n_fun][P], c [n_fun])."""
+    rng = np.random.default_rng(seed)
+    z = 1j * np.exp(np.linspace(math.log(0.05), math.log(w_max), n_points))
+    e = rng.uniform(-span, span, (n_fun, n_poles)) - 1j * rng.uniform(0.05, 0.5, (n_fun, n_poles))
+    r = rng.uniform(0.1, 1.5, (n_fun, n_poles)) * np.exp(1j * rng.uniform(-0.2, 0.2, (n_fun, n_poles)))
+    c = rng.uniform(-2.0, 2.0, n_fun)
+    f = c[:, None] + (r[:, None, :] / (z[None, :, None] - e[:, None, :])).sum(axis=2)
+    w = np.linspace(-2 * span, 2 * span, n_eval) + 1j * eta
+    return z, f.astype(np.complex128), w, e, r, c

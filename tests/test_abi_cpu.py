@@ -107,7 +107,7 @@ def test_struct_layout_matches_header(lib, tmp_path):
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gwchi.h"', 'int main(void){']
     mirrors = [("gwchi_item", gwchi.GwchiItem), ("gwchi_report", gwchi.GwchiReport),
                ("gwchi_options", gwchi.GwchiOptions), ("gwchi_w_item", gwchi.GwchiWItem),
-               ("gwchi_w_report", gwchi.GwchiWReport)]
+               ("gwchi_w_report", gwchi.GwchiWReport), ("gwchi_pade_item", gwchi.GwchiPadeItem)]
     for cname, py in mirrors:
         lines.append(f'printf("%zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:
@@ -181,3 +181,37 @@ def test_w_validate_empty_and_null(lib, witem):
     arr = (gwchi.GwchiWItem * 1)(it)
     assert lib.gwchi_w_validate(arr, 1) == 1
     assert b"NULL" in lib.gwchi_last_error(None)
+
+
+# ---- analytic continuation: host-only validation ---------------------------
+
+@pytest.fixture(scope="module")
+def pade_in():
+    z, f, w, *_ = synth.make_pade_input(3, 5, 12, 40)
+    return z, f, w
+
+
+def test_pade_valid_passes(lib, pade_in):
+    assert gwchi.pade_validate(*pade_in) == 0
+
+
+@pytest.mark.parametrize("mut", ["repeated_z", "nan_z", "inf_w", "too_many_points", "no_points"])
+def test_pade_validate_rejects(lib, pade_in, mut):
+    z, f, w = (x.copy() for x in pade_in)
+    if mut == "repeated_z":
+        z[5] = z[2]
+    elif mut == "nan_z":
+        z[0] = np.nan
+    elif mut == "inf_w":
+        w[3] = np.inf
+    elif mut == "too_many_points":
+        z = 1j * np.arange(1, 34, dtype=float)
+        f = np.ones((5, 33), np.complex128)
+    else:
+        z = np.zeros(0, np.complex128)
+        f = np.ones((5, 0), np.complex128)
+    assert gwchi.pade_validate(z, f, w) == 1
+
+
+def test_pade_validate_null(lib):
+    assert lib.gwchi_pade_validate(None) == 1
