@@ -165,6 +165,67 @@ def bench_w(ctx, item, args):
     return out
 
 
+PADE_FUNCS, PADE_EVAL = 8192, 4096
+
+
+def pade_flops(n_fun, n, m):
+    """Nominal FP64 work of the continuation: 20 flops per complex level (one
+    complex product, one complex division, two additions), N - 1 levels per
+    evaluated point and N (N - 1) / 2 for the recursion of each function."""
+    return 20.0 * n_fun * ((n - 1) * m + n * (n - 1) / 2)
+
+
+def bench_pade(ctx, item, args):
+    """The analytic continuation (Sec. II.E.1): PADE_FUNCS seeded functions of
+    the shape of diagonal self-energies, known at the workload's N imaginary
+    frequencies, continued to PADE_EVAL real frequencies; inputs and outputs
+    in HBM.  One step is one call (coefficients and evaluation)."""
+    import torch
+    from paper_1607_02859_amd import synth
+    dev = torch.device("cuda:0")
+    n = item.n_tau
+    z, f, w, *_ = synth.make_pade_input(71, PADE_FUNCS, n, PADE_EVAL, n_poles=24)
+    fd = torch.from_numpy(f).to(dev)
+    od = torch.empty((PADE_FUNCS, PADE_EVAL), dtype=torch.complex128, device=dev)
+    for _ in range(max(1, args.warmup)):
+        ctx.pade_device(z, fd, w, od, report=True)
+    ms = sum(ctx.pade_device(z, fd, w, od, report=True) for _ in range(args.steps)) / args.steps
+    torch.cuda.synchronize()
+    fl = pade_flops(PADE_FUNCS, n, PADE_EVAL)
+    out = {
+        "metric": "analytic continuation (Thiele reciprocal differences): TFLOP/s "
+                  "(20 flops per complex level)",
+        "value": fl / ms * 1e-9, "unit": "TFLOP/s", "ms_per_step": ms, "dtype": "f64",
+        "config": {"n_functions": PADE_FUNCS, "n_points": n, "n_eval": PADE_EVAL,
+                   "data": "seeded 24-pole functions on the workload's imaginary frequencies"},
+        "roofline": {"bound": "alu", "kernel": "k_pade", "achieved": fl / ms * 1e-9,
+                     "peak": 78.6, "unit": "TFLOP/s", "frac": fl / ms * 1e-9 / 78.6,
+                     "traffic": None,
+                     "bytes_algorithmic": 16.0 * PADE_FUNCS * (n + PADE_EVAL)},
+    }
+    if not args.no_check:
+        from oracle import pade as op
+        rows = [0, PADE_FUNCS // 2, PADE_FUNCS - 1]
+        got = od[rows].cpu().numpy()
+        ref = op.continue_to(z, f[rows], w)
+        out["err_vs_oracle_sampled"] = float(np.abs(got - ref).max() / np.abs(ref).max())
+    if not args.no_cpu:
+        from oracle import pade as op
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        cores = max([i.get("num_threads", 1) for i in info] or [1])
+        sample = 256
+        t0 = time.perf_counter()
+        op.continue_to(z, f[:sample], w)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": pade_flops(sample, n, PADE_EVAL) / dt * 1e-12,
+                               "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+                               "sample": f"{sample} of {PADE_FUNCS} functions (NumPy), {dt:.1f} s"}
+    log(f"[bench] pade: {ms:.3f} ms/step, {out['value']:.1f} TFLOP/s, "
+        f"err {out.get('err_vs_oracle_sampled', float('nan')):.2e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +245,11 @@ def main():
     ap.add_argument("--w", type=int, default=None,
                     help="also time the screened-interaction step W~ from chi(i omega) on the "
                          "plane-wave sphere of the workload (default: on for configuration 2)")
+    ap.add_argument("--pade", type=int, default=None,
+                    help="also time the analytic continuation of many functions known at the "
+                         "workload's imaginary frequencies (default: on for configuration 2)")
+    ap.add_argument("--pade-only", action="store_true",
+                    help="time only the continuation (prints one JSON line with the pade object)")
     ap.add_argument("--w-only", action="store_true",
                     help="time only the W~ step (prints one JSON line with the w_tilde object)")
     ap.add_argument("--autotune", type=int, default=None,
@@ -213,9 +279,10 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    if args.w_only:
+    if args.w_only or args.pade_only:
         ctx = gwchi.Context(0)
-        out = {"w_tilde": bench_w(ctx, item, args)}
+        out = {"w_tilde": bench_w(ctx, item, args)} if args.w_only else {
+            "pade": bench_pade(ctx, item, args)}
         ctx.close()
         print(json.dumps(out), flush=True)
         return
@@ -349,6 +416,10 @@ def main():
         args.w = 1 if args.config == 2 else 0
     if args.w:
         res["w_tilde"] = bench_w(ctx, item, args)
+    if args.pade is None:
+        args.pade = 1 if args.config == 2 else 0
+    if args.pade:
+        res["pade"] = bench_pade(ctx, item, args)
     ctx.close()
     print(json.dumps(res), flush=True)
 

@@ -19,8 +19,19 @@ namespace {
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
+// 1 / x: the hardware estimate refined by two Newton-Raphson steps
+// r <- r (2 - x r) (each squares the relative error, so two steps reach full
+// FP64 precision from the estimate); the exact division where x is zero, huge
+// or not finite
+__device__ __forceinline__ double recip(double x) {
+  if (!(x > 1e-300 && x < 1e300)) return 1.0 / x;
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  return r;
+}
 __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
-  const double d = 1.0 / (b.x * b.x + b.y * b.y);
+  const double d = recip(b.x * b.x + b.y * b.y);
   return make_double2((a.x * b.x + a.y * b.y) * d, (a.y * b.x - a.x * b.y) * d);
 }
 
