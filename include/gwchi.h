@@ -189,7 +189,10 @@ gwchi_status gwchi_autotune(gwchi_ctx *ctx, const gwchi_item *items, int32_t n_i
  * matrix ct[k][j] = gamma_kj cos(omega_k tau_j) (Eq. (6)); the library
  * inverts ct on the host in FP64.  eps must be Hermitian positive definite,
  * which holds when chi(i omega) is Hermitian negative semidefinite (as the
- * build above returns it); it is inverted without pivoting.
+ * build above returns it; with its default Hermitian completion exactly so);
+ * it is inverted without pivoting.  chi is taken as Hermitian: only its
+ * 64 x 64 tiles on or below the block diagonal are read, the others being
+ * their conjugate transposes.
  * ------------------------------------------------------------------------ */
 typedef struct {
   int32_t n_g;              /* >= 1, at most 65535                                       */

@@ -511,14 +511,15 @@ hipError_t launch_w_block(void *a, void *dinv, void *rp, void *cp, int n, int n_
                      (double2 *)dinv, n, P0, flag);
   hipLaunchKernelGGL(k_w_panel, dim3(tiles, n_mat), dim3(256), 0, st, (const double2 *)a,
                      (const double2 *)dinv, (double2 *)rp, (double2 *)cp, n, P0);
-  static int num_cu = 0;
-  if (num_cu <= 0) {
-    int dev = 0;
+  // compute units of the device, queried once (initialisation is thread safe)
+  static const int num_cu = [] {
+    int dev = 0, cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        num_cu <= 0)
-      num_cu = 256;
-  }
+        hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cu <= 0)
+      cu = 256;
+    return cu;
+  }();
   const int64_t n_tiles = (int64_t)tiles * (tiles + 1) / 2 * n_mat;   // block-lower tiles
   if (n_tiles > 0x7fffffff) return hipErrorInvalidValue;
   const int grid = (int)std::min<int64_t>(n_tiles, 2 * num_cu);
