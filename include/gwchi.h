@@ -60,7 +60,8 @@ typedef enum {
 
 /* One independent problem: one k-point (complex orbitals on the unit-cell
  * grid; the q = 0 contribution of that k) or one Gamma-only system (real
- * orbitals).  Items of one call may differ in every size. */
+ * orbitals).  Items of one call may differ in every size; they are all real or
+ * all complex. */
 typedef struct {
   int32_t n[3];          /* FFT grid n0, n1, n2; each 7-smooth and in [1, 32] (else ENOTSUP) */
   int32_t is_complex;    /* 0: real orbitals, 1: complex orbitals interleaved (re, im)      */
@@ -150,8 +151,9 @@ gwchi_status gwchi_get_options(const gwchi_ctx *ctx, gwchi_options *opt);
  * pointer, n_d <= 0, n_occ or n_unocc < 1, n_tau or n_omega or n_g < 1,
  * non-finite eps / mu / tau / ct (and non-finite orbitals when orbital
  * pointers are host memory: check_orbitals != 0), tau <= 0, mu not strictly
- * inside the gap, g_index out of range or duplicated.  ENOTSUP when a grid
- * size is not 7-smooth or exceeds 32. */
+ * inside the gap, g_index out of range or duplicated, items of one call that
+ * mix real and complex orbitals.  ENOTSUP when a grid size is not 7-smooth or
+ * exceeds 32. */
 gwchi_status gwchi_validate(const gwchi_item *items, int32_t n_items, int32_t check_orbitals);
 
 /* Build chi(G,G',i omega) for every item; host buffers in and out.

@@ -235,6 +235,12 @@ gwchi_status validate_items(gwchi_ctx *ctx, const gwchi_item *items, int32_t n_i
       }
     }
   }
+  // one call runs one GEMM tile family: all real or all complex
+  for (int32_t t = 1; t < n_items; ++t)
+    if ((items[t].is_complex != 0) != (items[0].is_complex != 0)) {
+      set_err(ctx, "items of one call must be all real or all complex");
+      return GWCHI_EINVAL;
+    }
   return GWCHI_OK;
 }
 
@@ -299,8 +305,8 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
                         Plan &P) {
   P = Plan();
   P.prec = prec;
-  // all items of one call use one (precision, complexity) tile family; mixed real/complex
-  // items are allowed and use their own tile family each
+  // all items of one call use one (precision, complexity) tile family; items that mix
+  // real and complex orbitals are rejected (validate_items reports it first)
   for (int t = 0; t < n_items; ++t) (items[t].is_complex ? P.cplx_any : P.real_any) = 1;
   if (P.cplx_any && P.real_any) {
     set_err(ctx, "items of one call must be all real or all complex");

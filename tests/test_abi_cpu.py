@@ -215,3 +215,12 @@ def test_pade_validate_rejects(lib, pade_in, mut):
 
 def test_pade_validate_null(lib):
     assert lib.gwchi_pade_validate(None) == 1
+
+
+def test_validate_rejects_mixed_real_and_complex(lib):
+    real = synth.make_item(7, (4, 4, 4), 2, 6, False, 3, x_min=1.0)
+    cplx = synth.make_item(8, (4, 4, 4), 2, 6, True, 3, x_min=1.0)
+    assert gwchi.validate([real, real]) == 0
+    assert gwchi.validate([cplx, cplx]) == 0
+    assert gwchi.validate([real, cplx]) == 1
+    assert b"all real or all complex" in lib.gwchi_last_error(None)

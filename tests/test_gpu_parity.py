@@ -129,6 +129,15 @@ def test_batch_equals_single(ctx, prec):
         assert np.array_equal(s, b)
 
 
+def test_mixed_real_and_complex_rejected(ctx):
+    with pytest.raises(gwchi.GwchiError) as e:
+        ctx.build([case("real6")[0], case("cplx8")[0]], "fp32")
+    assert e.value.status == 1
+    # the context stays usable
+    it, ref = case("cplx8")
+    assert oc.rel_frobenius(ctx.build([it], "fp32")[0], ref) <= TOL["fp32"]
+
+
 def test_graph_replay_identical(ctx):
     it, ref = case("cplx8")
     ctx.set_options(use_graph=1)
