@@ -9,6 +9,7 @@
 #include <stdint.h>
 
 #include <type_traits>
+#include <vector>
 
 namespace gw {
 
@@ -235,10 +236,16 @@ constexpr int kWBlock = 64;
 constexpr int kWMaxTau = 32;
 hipError_t launch_w_eps(const void *chi, const double *s, void *a, int n, int n_mat,
                         hipStream_t st);
+// The block-lower 64 x 64 tiles of an n x n matrix as (row tile, column tile)
+// pairs, grouped by partition x = 0..7 at [off[x], off[x + 1]) (partition x,
+// served by the workgroups b with b % 8 == x, owns the column tiles x,
+// 15 - x, 16 + x, ...), row tile by row tile within a partition.
+void w_tile_table(int n, std::vector<int32_t> &pairs, int32_t off[9]);
 // one pivot block at P0: dinv [n_mat][kWBlock][kWBlock], rp [n_mat][kWBlock][n],
-// cp [n_mat][n][kWBlock]; *flag is set when a pivot is not positive
+// cp [n_mat][n][kWBlock]; tiles / toff: the table of w_tile_table in device
+// memory; *flag is set when a pivot is not positive
 hipError_t launch_w_block(void *a, void *dinv, void *rp, void *cp, int n, int n_mat, int P0,
-                          int *flag, hipStream_t st);
+                          const int32_t *tiles, const int32_t *toff, int *flag, hipStream_t st);
 // fills the tiles above the block diagonal of a from those below (Hermitian),
 // then ict [n_tau][n_omega]; w_omega may be null; n_tau <= kWMaxTau
 hipError_t launch_w_final(void *a, const double *s, const double *ict, void *w_tau,

@@ -1381,7 +1381,8 @@ gwchi_status run_w(gwchi_ctx *ctx, const gwchi_w_item *items, int n_items,
                    const std::vector<std::vector<double>> &ict, gwchi_w_report *rep) {
   hipStream_t st = ctx->stream;
   int64_t a_b = 0, p_b = 0, d_b = 0, tab = 0;
-  std::vector<int64_t> toff(n_items);
+  std::vector<int64_t> toff(n_items), tile_off(n_items);
+  std::vector<std::vector<int32_t>> tiles(n_items);   // per item: 9 offsets, then the pairs
   for (int t = 0; t < n_items; ++t) {
     const gwchi_w_item &it = items[t];
     const int64_t n = it.n_g, K = it.n_omega;
@@ -1390,6 +1391,14 @@ gwchi_status run_w(gwchi_ctx *ctx, const gwchi_w_item *items, int n_items,
     d_b = std::max(d_b, K * kWBlock * kWBlock * 16);
     toff[t] = tab;
     tab += round_up(n + (int64_t)it.n_tau * it.n_omega, 32);
+    std::vector<int32_t> pairs;
+    int32_t off[9];
+    w_tile_table((int)n, pairs, off);
+    tiles[t].assign(off, off + 9);
+    tiles[t].push_back(0);                       // the pairs start 8-byte aligned
+    tiles[t].insert(tiles[t].end(), pairs.begin(), pairs.end());
+    tile_off[t] = tab;
+    tab += round_up(((int64_t)tiles[t].size() + 1) / 2, 32);   // in doubles
   }
   HIPCHK(ctx->b_wa.ensure(a_b, nullptr));
   HIPCHK(ctx->b_wrp.ensure(p_b, nullptr));
@@ -1405,6 +1414,7 @@ gwchi_status run_w(gwchi_ctx *ctx, const gwchi_w_item *items, int n_items,
     const gwchi_w_item &it = items[t];
     std::memcpy(h + toff[t], it.sqrt_v, (size_t)it.n_g * 8);
     std::memcpy(h + toff[t] + it.n_g, ict[t].data(), ict[t].size() * 8);
+    std::memcpy(h + tile_off[t], tiles[t].data(), tiles[t].size() * 4);
   }
   HIPCHK(hipMemcpyAsync(ctx->b_wtab.p, h, tab * 8, hipMemcpyHostToDevice, st));
   int *flag = reinterpret_cast<int *>(ctx->b_wflag.p);
@@ -1430,11 +1440,14 @@ gwchi_status run_w(gwchi_ctx *ctx, const gwchi_w_item *items, int n_items,
     const int n = it.n_g, K = it.n_omega;
     const double *s_dev = reinterpret_cast<const double *>(ctx->b_wtab.p) + toff[t];
     const double *ict_dev = s_dev + n;
+    const int32_t *tile_dev =
+        reinterpret_cast<const int32_t *>(reinterpret_cast<const double *>(ctx->b_wtab.p) + tile_off[t]);
     hipError_t e = launch_w_eps(it.chi, s_dev, ctx->b_wa.p, n, K, st);
     ++launches;
     if (e == hipSuccess && (s0 = mark()) != GWCHI_OK) return cleanup(), s0;
     for (int p0 = 0; e == hipSuccess && p0 < n; p0 += kWBlock) {
-      e = launch_w_block(ctx->b_wa.p, ctx->b_wdinv.p, ctx->b_wrp.p, ctx->b_wcp.p, n, K, p0, flag, st);
+      e = launch_w_block(ctx->b_wa.p, ctx->b_wdinv.p, ctx->b_wrp.p, ctx->b_wcp.p, n, K, p0,
+                         tile_dev + 10, tile_dev, flag, st);
       launches += 3;
     }
     if (e == hipSuccess && (s0 = mark()) != GWCHI_OK) return cleanup(), s0;

@@ -28,6 +28,7 @@
 // forms W~(i omega_k) and the inverse cosine transform in one pass.
 #include <algorithm>
 #include <type_traits>
+#include <vector>
 
 #include "common.h"
 
@@ -238,12 +239,12 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
 // anti-Hermitian, so the tiles above the diagonal follow from those below
 // (the panels read them so, and k_w_mirror fills them at the end).
 // Workgroups are dealt to the XCDs in turn: workgroup b serves partition
-// b % XP (XP = 8, or the grid if smaller), which owns the column tiles x,
-// 2 XP - 1 - x, 2 XP + x, ... (a snake, so that the partitions get about
-// equal numbers of lower tiles) of every matrix, so the row panels its tiles
-// read stay in that XCD's L2 while A streams through.  Within a partition the
-// tiles run matrix by matrix, column by column, and its workgroups take every
-// nk-th of them.
+// b % 8, which owns the column tiles x, 15 - x, 16 + x, ... (a snake, so that
+// the partitions get about equal numbers of lower tiles) of every matrix, so
+// the panels its tiles read stay in that XCD's L2 while A streams through.
+// The host lists each partition's lower tiles, row tile by row tile, in a
+// table (w_tile_table); within a partition the tiles run matrix by matrix in
+// that order, and its workgroups take every nk-th of them.
 // Per tile: A[i][j] <- R[i - P0][j] for i in the pivot block P, else
 // A[i][j] [j outside P] - sum_p C[i][p] R[p][j].
 //
@@ -262,40 +263,6 @@ constexpr int UCH = NB / UKC;                 // chunks per tile
 struct UTile {
   int m, i0, j0;
 };
-// column tile number g of partition x (snake order), or T and above when past
-// the last
-__device__ __forceinline__ int ucol(int g, int x, int XP) {
-  return (g & 1) ? g * XP + XP - 1 - x : g * XP + x;
-}
-// lower tiles of one matrix in partition x
-__device__ __forceinline__ int ulower(int T, int x, int XP) {
-  int cnt = 0;
-  for (int g = 0;; ++g) {
-    const int tj = ucol(g, x, XP);
-    if (tj >= T) {
-      if (g * XP >= T) break;
-      continue;
-    }
-    cnt += T - tj;
-  }
-  return cnt;
-}
-// local tile q of partition x (L lower tiles per matrix)
-__device__ __forceinline__ UTile utile(int q, int T, int x, int XP, int L) {
-  UTile u;
-  u.m = q / L;
-  int r = q - u.m * L;
-  for (int g = 0;; ++g) {
-    const int tj = ucol(g, x, XP);
-    if (tj >= T) continue;                     // the last group is partial; q < L ends the walk
-    if (r < T - tj) {
-      u.j0 = tj * 64;
-      u.i0 = (tj + r) * 64;
-      return u;
-    }
-    r -= T - tj;
-  }
-}
 
 // one chunk of panel values per thread: 4 C entries and 4 R entries
 // (native vectors: arrays of them stay in registers across the tile loop)
@@ -325,24 +292,34 @@ __device__ __forceinline__ void ustore(const d2v (&hc)[4], const d2v (&hr)[4],
 __global__ __launch_bounds__(256, 2) void k_w_update(double2 *__restrict__ a,
                                                      const double2 *__restrict__ rp,
                                                      const double2 *__restrict__ cp, int n,
-                                                     int P0, int T, int n_mat) {
+                                                     int P0, int n_mat,
+                                                     const int2 *__restrict__ tl,
+                                                     const int *__restrict__ toff) {
   __shared__ double2 sc0[64][UKC + 1], sc1[64][UKC + 1];
   __shared__ double2 sr0[UKC][64], sr1[UKC][64];
   const int nb = min(NB, n - P0);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int wr = w >> 1, wc = w & 1;
-  const int G = gridDim.x;
-  const int XP = min(8, G);
-  const int x = (int)blockIdx.x % XP, k = (int)blockIdx.x / XP;
-  const int nk = (G - x + XP - 1) / XP;        // workgroups of partition x
-  const int L = ulower(T, x, XP);
+  const int G = gridDim.x;                     // at least 8
+  const int x = (int)blockIdx.x % 8, k = (int)blockIdx.x / 8;
+  const int nk = (G - x + 7) / 8;              // workgroups of partition x
+  const int lo = toff[x], L = toff[x + 1] - lo;
   const int part_tiles = n_mat * L;
   const int my_tiles = part_tiles > k ? (part_tiles - k + nk - 1) / nk : 0;
   if (my_tiles == 0) return;                   // the whole workgroup leaves together
   const int n_chunks = my_tiles * UCH;
   // chunk c: local tile k + (c / UCH) nk, band chunk c % UCH; chunks past the
   // end load the last tile again (never used)
-  auto chunk_tile = [&](int c) { return utile(k + min(c / UCH, my_tiles - 1) * nk, T, x, XP, L); };
+  auto chunk_tile = [&](int c) {
+    const int q = k + min(c / UCH, my_tiles - 1) * nk;
+    const int m = q / L;
+    const int2 t = tl[lo + q - m * L];
+    UTile u;
+    u.m = m;
+    u.i0 = t.x * 64;
+    u.j0 = t.y * 64;
+    return u;
+  };
   // register sets X and Y: before chunk c, X holds chunk c + 1 and Y chunk
   // c + 2 for even c, the other way round for odd c
   d2v xc[4], xr[4], yc[4], yr[4];
@@ -502,8 +479,28 @@ hipError_t launch_w_eps(const void *chi, const double *s, void *a, int n, int n_
   return hipGetLastError();
 }
 
+void w_tile_table(int n, std::vector<int32_t> &pairs, int32_t off[9]) {
+  const int T = (n + 63) / 64;
+  pairs.clear();
+  for (int x = 0; x < 8; ++x) {
+    off[x] = (int32_t)(pairs.size() / 2);
+    std::vector<int> cols;                     // snake: x, 15 - x, 16 + x, ... (increasing)
+    for (int g = 0; g * 8 < T; ++g) {
+      const int tj = (g & 1) ? g * 8 + 7 - x : g * 8 + x;
+      if (tj < T) cols.push_back(tj);
+    }
+    for (int ti = 0; ti < T; ++ti)
+      for (int tj : cols)
+        if (tj <= ti) {
+          pairs.push_back(ti);
+          pairs.push_back(tj);
+        }
+  }
+  off[8] = (int32_t)(pairs.size() / 2);
+}
+
 hipError_t launch_w_block(void *a, void *dinv, void *rp, void *cp, int n, int n_mat, int P0,
-                          int *flag, hipStream_t st) {
+                          const int32_t *tile_list, const int32_t *toff, int *flag, hipStream_t st) {
   if (P0 < 0 || P0 >= n) return hipErrorInvalidValue;
   if (n_mat > 65535) return hipErrorInvalidValue;
   const int tiles = (n + 63) / 64;
@@ -522,9 +519,9 @@ hipError_t launch_w_block(void *a, void *dinv, void *rp, void *cp, int n, int n_
   }();
   const int64_t n_tiles = (int64_t)tiles * (tiles + 1) / 2 * n_mat;   // block-lower tiles
   if (n_tiles > 0x7fffffff) return hipErrorInvalidValue;
-  const int grid = (int)std::min<int64_t>(n_tiles, 2 * num_cu);
+  const int grid = (int)std::max<int64_t>(8, std::min<int64_t>(n_tiles, 2 * num_cu));
   hipLaunchKernelGGL(k_w_update, dim3(grid), dim3(256), 0, st, (double2 *)a, (const double2 *)rp,
-                     (const double2 *)cp, n, P0, tiles, n_mat);
+                     (const double2 *)cp, n, P0, n_mat, (const int2 *)tile_list, toff);
   return hipGetLastError();
 }
 
