@@ -107,6 +107,19 @@ def test_device_entry_matches_host_entry(ctx):
     assert np.array_equal(taus[1].cpu().numpy(), host[0][1])
 
 
+def test_sphere18_full(ctx):
+    """The 18^3 sphere (1309 plane waves, 21 tiles per side: every XCD
+    partition owns several column tiles, including the second, reversed group
+    of the snake), compared in full."""
+    w = synth.make_w_item(65, (18, 18, 18), 6, strength=4.0)
+    say(f"[w] sphere18 n_g={w.n_g}")
+    (taus, oms) = ctx.w_build([w], omega=True)
+    ref_t, ref_w = ow.w_tilde_tau(w.chi, w.sqrt_v, w.ct, return_omega=True)
+    et, ew = rel(taus[0], ref_t), rel(oms[0], ref_w)
+    say(f"   err tau={et:.3e} omega={ew:.3e}")
+    assert et <= TOL and ew <= TOL
+
+
 def test_full_sphere24_sampled_rows(ctx):
     """The 24^3 sphere (2969 plane waves) and 12 frequencies, the size of the
     headline polarizability workload: sampled rows against linear solves."""
