@@ -51,13 +51,15 @@ __device__ __forceinline__ double2 cinv(double2 a) {
 
 constexpr int NB = kWBlock;
 
-// grid (ceil(n / 256), n, n_mat): a[m][g][h] = delta - s_g chi[m][g][h] s_h
+// grid (ceil(n / 256), n, n_mat): a[m][g][h] = delta - s_g chi[m][g][h] s_h on
+// the block-lower 64 x 64 tiles (the sweep reads no others; k_w_mirror fills
+// the upper ones at the end)
 __global__ __launch_bounds__(256) void k_w_eps(const double2 *__restrict__ chi,
                                                const double *__restrict__ s, double2 *__restrict__ a,
                                                int n) {
   const int h = blockIdx.x * 256 + threadIdx.x;
   const int g = blockIdx.y;
-  if (h >= n) return;
+  if (h >= n || h / 64 > g / 64) return;
   const int64_t e = ((int64_t)blockIdx.z * n + g) * n + h;
   const double sg = s[g] * s[h];
   const double2 x = chi[e];
