@@ -44,10 +44,6 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 __device__ __forceinline__ double2 csub(double2 a, double2 b) {
   return make_double2(a.x - b.x, a.y - b.y);
 }
-__device__ __forceinline__ double2 cinv(double2 a) {
-  const double d = a.x * a.x + a.y * a.y;
-  return make_double2(a.x / d, -a.y / d);
-}
 
 constexpr int NB = kWBlock;
 
@@ -69,53 +65,75 @@ __global__ __launch_bounds__(256) void k_w_eps(const double2 *__restrict__ chi,
 }
 
 // one workgroup of 1024 threads per matrix: the exchange of the nb pivots of
-// the diagonal block at P0, in LDS; rows and columns past nb are the
-// identity.  Each pivot reads one LDS copy of the block and writes the other
-// (one barrier per pivot).  A pivot whose real part is not positive and
-// finite (eps not positive definite) sets *flag.
+// the diagonal block at P0; rows and columns past nb are the identity.  The
+// block stays in registers (wave w holds rows w, w + 16, w + 32, w + 48, lane
+// l column l); per pivot only the pivot row and column pass through LDS, in a
+// double buffer: the owners of row and column p + 1 write them right after
+// pivot p, so one barrier per pivot suffices.  A pivot whose real part is not
+// positive and finite (eps not positive definite) sets *flag.
 constexpr int DT = 1024;
+constexpr int DR = NB * NB / DT;                 // rows per thread
+static_assert(DT == 16 * NB && DR * 16 == NB, "k_w_diag maps 16 waves onto 64 rows");
 __global__ __launch_bounds__(DT) void k_w_diag(const double2 *__restrict__ a,
                                                double2 *__restrict__ dinv, int n, int P0,
                                                int *flag) {
-  __shared__ double2 d[2][NB][NB + 1];
+  __shared__ double2 rowb[2][NB], colb[2][NB];
   const int m = blockIdx.x;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const double2 *A = a + (int64_t)m * n * n;
   const int nb = min(NB, n - P0);
-  for (int e = threadIdx.x; e < NB * NB; e += DT) {
-    const int i = e / NB, j = e % NB;
-    d[0][i][j] = (i < nb && j < nb) ? A[(int64_t)(P0 + i) * n + P0 + j]
-                                    : make_double2(i == j ? 1.0 : 0.0, 0.0);
+  double2 r[DR];
+#pragma unroll
+  for (int k = 0; k < DR; ++k) {
+    const int i = w + 16 * k;
+    r[k] = (i < nb && l < nb) ? A[(int64_t)(P0 + i) * n + P0 + l]
+                              : make_double2(i == l ? 1.0 : 0.0, 0.0);
+  }
+  if (w == 0) rowb[0][l] = r[0];
+  if (l == 0) {
+#pragma unroll
+    for (int k = 0; k < DR; ++k) colb[0][w + 16 * k] = r[k];
   }
   __syncthreads();
-  constexpr int PER = NB * NB / DT;
-  int cur = 0;
   for (int p = 0; p < nb; ++p) {
-    const double2 dpp = d[cur][p][p];
-    if (threadIdx.x == 0 && !(dpp.x > 0.0 && dpp.x < 1.0e300)) atomicOr(flag, 1);
-    const double2 piv = cinv(dpp);
+    const int cur = p & 1, nxt = cur ^ 1;
+    // every LDS read of the pivot first (one round trip), then the reciprocal
+    const double2 dpp = rowb[cur][p];
+    const double2 dpj = rowb[cur][l];
+    double2 dip[DR];
 #pragma unroll
-    for (int t = 0; t < PER; ++t) {
-      const int e = threadIdx.x + DT * t;
-      const int i = e / NB, j = e % NB;
-      const double2 dip = d[cur][i][p], dpj = d[cur][p][j];
-      double2 nv;
-      if (i != p && j != p) {
-        nv = csub(d[cur][i][j], cmul(cmul(dip, piv), dpj));
-      } else if (i != p) {
-        const double2 x = cmul(dip, piv);
-        nv = make_double2(-x.x, -x.y);
-      } else if (j != p) {
-        nv = cmul(piv, dpj);
-      } else {
-        nv = piv;
-      }
-      d[cur ^ 1][i][j] = nv;
+    for (int k = 0; k < DR; ++k) dip[k] = colb[cur][w + 16 * k];
+    if (threadIdx.x == 0 && !(dpp.x > 0.0 && dpp.x < 1.0e300)) atomicOr(flag, 1);
+    const double q = 1.0 / (dpp.x * dpp.x + dpp.y * dpp.y);
+    const double2 piv = make_double2(dpp.x * q, -dpp.y * q);
+    // the pivot row scaled once per lane; on the pivot column (l == p) the
+    // row entry is taken as 1 and the old value as 0, so that every element
+    // off the pivot row takes the same update r - d_ip (piv d_pj): -d_ip piv
+    // on the pivot column, and the pivot row becomes piv d_pj (piv at p)
+    const double2 dps = l == p ? piv : cmul(piv, dpj);
+#pragma unroll
+    for (int k = 0; k < DR; ++k) {
+      const double2 o = l == p ? make_double2(0.0, 0.0) : r[k];
+      const double2 u =
+          make_double2(__builtin_fma(-dip[k].x, dps.x, __builtin_fma(dip[k].y, dps.y, o.x)),
+                       __builtin_fma(-dip[k].x, dps.y, __builtin_fma(-dip[k].y, dps.x, o.y)));
+      r[k] = w + 16 * k == p ? dps : u;
     }
-    cur ^= 1;
+    const int p1 = p + 1;
+    if (p1 < nb) {
+#pragma unroll
+      for (int k = 0; k < DR; ++k)
+        if (w + 16 * k == p1) rowb[nxt][l] = r[k];
+      if (l == p1) {
+#pragma unroll
+        for (int k = 0; k < DR; ++k) colb[nxt][w + 16 * k] = r[k];
+      }
+    }
     __syncthreads();
   }
   double2 *D = dinv + (int64_t)m * NB * NB;
-  for (int e = threadIdx.x; e < NB * NB; e += DT) D[e] = d[cur][e / NB][e % NB];
+#pragma unroll
+  for (int k = 0; k < DR; ++k) D[(w + 16 * k) * NB + l] = r[k];
 }
 
 // grid (ceil(n / 64), n_mat): for the 64 columns j0 .. j0 + 63 the row panel
@@ -128,8 +146,12 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
                                                  double2 *__restrict__ rp, double2 *__restrict__ cp,
                                                  int n, int P0) {
   // the contraction over the block's 64 bands runs in two halves of PH, so
-  // that two workgroups share a CU
+  // that two workgroups share a CU.  Every copy loop below issues all its
+  // loads before its first store, so that they are in flight together.
   constexpr int PH = NB / 2;
+  constexpr int CPT = 64 * NB / 256;           // column-panel entries per thread
+  constexpr int HPT = NB * PH / 256;           // half-block entries per thread
+  static_assert(CPT == 16 && HPT == 8, "k_w_panel assumes 256 threads and 64-pivot blocks");
   __shared__ double2 sd[NB][PH + 1];
   __shared__ double2 sa[PH][64 + 1];
   const int m = blockIdx.y;
@@ -138,18 +160,31 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
   const int nb = min(NB, n - P0);
   const double2 *A = a + (int64_t)m * n * n;
   const double2 *D = dinv + (int64_t)m * NB * NB;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int t32 = threadIdx.x >> 5, l32 = threadIdx.x & 31;
   // column panel for the rows of this tile below the pivot block (stored);
-  // rows above it are written after the MFMAs, through LDS
+  // rows above it are written after the MFMAs, through LDS.  Thread entry t:
+  // row j0 + w + 4 t, band l.
   if (tile >= bp) {
-    for (int e = threadIdx.x; e < 64 * NB; e += 256) {
-      const int r = e / NB, p = e % NB, i = j0 + r;
-      if (i >= n) continue;
+    double2 x[CPT];
+#pragma unroll
+    for (int t = 0; t < CPT; ++t) {
+      const int i = j0 + w + 4 * t;
       const bool in_p = i >= P0 && i < P0 + nb;
-      cp[((int64_t)m * n + i) * NB + p] =
-          (p < nb && !in_p) ? A[(int64_t)i * n + P0 + p] : make_double2(0.0, 0.0);
+      x[t] = (i < n && l < nb && !in_p) ? A[(int64_t)i * n + P0 + l] : make_double2(0.0, 0.0);
+    }
+    // full tiles store without per-row conditions (each conditional store
+    // would get a wait for every store before it)
+    double2 *Cp = cp + ((int64_t)m * n + j0 + w) * NB + l;
+    if (j0 + 64 <= n) {
+#pragma unroll
+      for (int t = 0; t < CPT; ++t) Cp[4 * t * NB] = x[t];
+    } else {
+#pragma unroll
+      for (int t = 0; t < CPT; ++t)
+        if (j0 + w + 4 * t < n) Cp[4 * t * NB] = x[t];
     }
   }
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int wr = w >> 1, wc = w & 1;
   d4v re[2][2], im[2][2];
 #pragma unroll
@@ -158,24 +193,35 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
     for (int bj = 0; bj < 2; ++bj) re[bi][bj] = im[bi][bj] = d4v{0.0, 0.0, 0.0, 0.0};
   for (int h = 0; h < 2; ++h) {
     const int q0 = h * PH;
-    for (int e = threadIdx.x; e < NB * PH; e += 256) sd[e / PH][e % PH] = D[(e / PH) * NB + q0 + e % PH];
+    // D^-1 columns q0 .. q0 + PH - 1 (entry t: row t32 + 8 t, column l32)
+    // and M[P, j] for the bands of this half
+    double2 xd[HPT], xa[HPT];
+#pragma unroll
+    for (int t = 0; t < HPT; ++t) xd[t] = D[(t32 + 8 * t) * NB + q0 + l32];
     if (tile <= bp) {
-      // M[P, j] is stored (block-lower): lanes along j
-      for (int e = threadIdx.x; e < PH * 64; e += 256) {
-        const int q = e / 64, c = e % 64, j = j0 + c;
-        sa[q][c] = (q0 + q < nb && j < n) ? A[(int64_t)(P0 + q0 + q) * n + j] : make_double2(0.0, 0.0);
+      // M[P, j] is stored (block-lower): entry t band w + 4 t, column l
+#pragma unroll
+      for (int t = 0; t < HPT; ++t) {
+        const int q = w + 4 * t, j = j0 + l;
+        xa[t] = (q0 + q < nb && j < n) ? A[(int64_t)(P0 + q0 + q) * n + j] : make_double2(0.0, 0.0);
       }
     } else {
-      // M[P, j] = conj(M[j, P]) above the diagonal: lanes along the row j
-      for (int e = threadIdx.x; e < PH * 64; e += 256) {
-        const int c = e / PH, q = e % PH, j = j0 + c;
-        double2 x = make_double2(0.0, 0.0);
-        if (q0 + q < nb && j < n) {
-          x = A[(int64_t)j * n + P0 + q0 + q];
-          x.y = -x.y;
-        }
-        sa[q][c] = x;
+      // M[P, j] = conj(M[j, P]) above the diagonal: entry t row j0 + t32 + 8 t,
+      // band l32 (reads along the row)
+#pragma unroll
+      for (int t = 0; t < HPT; ++t) {
+        const int q = l32, j = j0 + t32 + 8 * t;
+        xa[t] = (q0 + q < nb && j < n) ? A[(int64_t)j * n + P0 + q0 + q] : make_double2(0.0, 0.0);
       }
+    }
+#pragma unroll
+    for (int t = 0; t < HPT; ++t) sd[t32 + 8 * t][l32] = xd[t];
+    if (tile <= bp) {
+#pragma unroll
+      for (int t = 0; t < HPT; ++t) sa[w + 4 * t][l] = xa[t];
+    } else {
+#pragma unroll
+      for (int t = 0; t < HPT; ++t) sa[l32][t32 + 8 * t] = make_double2(xa[t].x, -xa[t].y);
     }
     __syncthreads();
 #pragma unroll 4
@@ -197,19 +243,34 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
     }
     __syncthreads();
   }
+  // row panel: D^-1 itself on the block's own columns (only the tile at bp
+  // has them), the product elsewhere
+  double2 val[2][2][4];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
       const int j = j0 + wc * 32 + bj * 16 + (l & 15);
-      if (j >= n) continue;
       const bool in_p = j >= P0 && j < P0 + nb;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int p = wr * 32 + bi * 16 + (l >> 4) + 4 * v;
-        double2 val = make_double2(0.0, 0.0);
-        if (p < nb) val = in_p ? D[p * NB + (j - P0)] : make_double2(re[bi][bj][v], im[bi][bj][v]);
-        rp[((int64_t)m * NB + p) * n + j] = val;
+        double2 x = make_double2(0.0, 0.0);
+        if (p < nb && j < n) x = in_p ? D[p * NB + (j - P0)] : make_double2(re[bi][bj][v], im[bi][bj][v]);
+        val[bi][bj][v] = x;
+      }
+    }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const int j = j0 + wc * 32 + bj * 16 + (l & 15);
+      if (j0 + 64 <= n || j < n) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int p = wr * 32 + bi * 16 + (l >> 4) + 4 * v;
+          rp[((int64_t)m * NB + p) * n + j] = val[bi][bj][v];
+        }
       }
     }
   if (tile < bp) {
@@ -218,16 +279,27 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
     // run along rows
     for (int h = 0; h < 2; ++h) {
       const int q0 = h * PH;
-      for (int e = threadIdx.x; e < PH * 64; e += 256) {
-        const int q = e / 64, r = e % 64, i = j0 + r;
-        sa[q][r] = (q0 + q < nb && i < n) ? A[(int64_t)(P0 + q0 + q) * n + i] : make_double2(0.0, 0.0);
+      double2 x[HPT];
+#pragma unroll
+      for (int t = 0; t < HPT; ++t) {
+        const int q = w + 4 * t, i = j0 + l;
+        x[t] = (q0 + q < nb && i < n) ? A[(int64_t)(P0 + q0 + q) * n + i] : make_double2(0.0, 0.0);
       }
+#pragma unroll
+      for (int t = 0; t < HPT; ++t) sa[w + 4 * t][l] = x[t];
       __syncthreads();
-      for (int e = threadIdx.x; e < 64 * PH; e += 256) {
-        const int r = e / PH, q = e % PH, i = j0 + r;
-        if (i < n) {
-          const double2 x = sa[q][r];
-          cp[((int64_t)m * n + i) * NB + q0 + q] = make_double2(-x.x, x.y);
+      double2 *Cp = cp + ((int64_t)m * n + j0 + t32) * NB + q0 + l32;
+      if (j0 + 64 <= n) {
+#pragma unroll
+        for (int t = 0; t < HPT; ++t) {
+          const double2 y = sa[l32][t32 + 8 * t];
+          Cp[8 * t * NB] = make_double2(-y.x, y.y);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < HPT; ++t) {
+          const double2 y = sa[l32][t32 + 8 * t];
+          if (j0 + t32 + 8 * t < n) Cp[8 * t * NB] = make_double2(-y.x, y.y);
         }
       }
       __syncthreads();
