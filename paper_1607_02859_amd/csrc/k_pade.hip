@@ -11,6 +11,12 @@
 // (the table g_n(z_j) is updated in place, j >= n), then the lanes share the
 // evaluation points, so that the outputs of a function are written in
 // contiguous runs.  The points z and w are shared by all functions.
+//
+// The fraction is evaluated from the innermost level out, with the tail
+// t_k = 1 + c_k / t_{k+1} (c_k = a_k (w - z_{k-1}), t_N = 1) kept as a ratio
+// P / Q: t_k = (P + c_k Q) / P, so every level is one complex product and one
+// complex multiply-add, and P_N(w) = a_1 Q / P takes the only division.  P and
+// Q are rescaled together by a power of two when they leave [2^-400, 2^400].
 #include "common.h"
 
 namespace gw {
@@ -33,6 +39,51 @@ __device__ __forceinline__ double recip(double x) {
 __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
   const double d = recip(b.x * b.x + b.y * b.y);
   return make_double2((a.x * b.x + a.y * b.y) * d, (a.y * b.x - a.x * b.y) * d);
+}
+
+// P_N at the U points p, p + 64, ..., p + 64 (U - 1) (interleaved, so that
+// their chains overlap) from the coefficients g of one function
+template <int NMAX, int U>
+__device__ __forceinline__ void continue_points(const double2 *g, int n,
+                                                const double2 *__restrict__ z,
+                                                const double2 *__restrict__ w,
+                                                double2 *__restrict__ O, int p) {
+  constexpr double kHi = 0x1p400, kLo = 0x1p-400;
+  double2 wp[U], P[U], Q[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    wp[u] = w[p + 64 * u];
+    P[u] = Q[u] = make_double2(1.0, 0.0);
+  }
+#pragma unroll
+  for (int k = NMAX - 1; k >= 1; --k) {
+    if (k < n) {
+      const double2 zk = z[k - 1];
+      double mx[U];
+      bool resc = false;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const double2 c = cmul(g[k], make_double2(wp[u].x - zk.x, wp[u].y - zk.y));
+        const double2 pn =
+            make_double2(__builtin_fma(c.x, Q[u].x, __builtin_fma(-c.y, Q[u].y, P[u].x)),
+                         __builtin_fma(c.x, Q[u].y, __builtin_fma(c.y, Q[u].x, P[u].y)));
+        Q[u] = P[u];
+        P[u] = pn;
+        mx[u] = fmax(fmax(fabs(P[u].x), fabs(P[u].y)), fmax(fabs(Q[u].x), fabs(Q[u].y)));
+        resc |= !(mx[u] > kLo && mx[u] < kHi);
+      }
+      if (resc) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const double sc = mx[u] >= kHi ? 0x1p-450 : (mx[u] <= kLo && mx[u] > 0.0 ? 0x1p450 : 1.0);
+          P[u] = make_double2(P[u].x * sc, P[u].y * sc);
+          Q[u] = make_double2(Q[u].x * sc, Q[u].y * sc);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) O[p + 64 * u] = cmul(g[0], cdiv(Q[u], P[u]));
 }
 
 // f [n_fun][n], z [n], w [m] complex; coef [n_fun][n] (or null), out [n_fun][m]
@@ -71,20 +122,12 @@ __global__ __launch_bounds__(256) void k_pade(const double2 *__restrict__ f, int
     for (int j = 0; j < NMAX; ++j)
       if (j < n) C[j] = g[j];
   }
+  // evaluation, EU points per lane at a time, the last ones singly
   double2 *O = out + (int64_t)fun * m;
-  for (int p = l; p < m; p += 64) {
-    const double2 wp = w[p];
-    double2 t = make_double2(1.0, 0.0);
-#pragma unroll
-    for (int k = NMAX - 1; k >= 1; --k) {
-      if (k < n) {
-        const double2 zk = z[k - 1];
-        const double2 q = cdiv(cmul(g[k], make_double2(wp.x - zk.x, wp.y - zk.y)), t);
-        t = make_double2(1.0 + q.x, q.y);
-      }
-    }
-    O[p] = cdiv(g[0], t);
-  }
+  constexpr int EU = 4;
+  int p = l;
+  for (; p + 64 * (EU - 1) < m; p += 64 * EU) continue_points<NMAX, EU>(g, n, z, w, O, p);
+  for (; p < m; p += 64) continue_points<NMAX, 1>(g, n, z, w, O, p);
 }
 
 }  // namespace
