@@ -17,6 +17,9 @@
 // P / Q: t_k = (P + c_k Q) / P, so every level is one complex product and one
 // complex multiply-add, and P_N(w) = a_1 Q / P takes the only division.  P and
 // Q are rescaled together by a power of two when they leave [2^-400, 2^400].
+#include <array>
+#include <utility>
+
 #include "common.h"
 
 namespace gw {
@@ -87,12 +90,15 @@ __device__ __forceinline__ void continue_points(const double2 *g, int n,
 }
 
 // f [n_fun][n], z [n], w [m] complex; coef [n_fun][n] (or null), out [n_fun][m]
+// one instantiation per number of points N (NMAX = N): the level loops are
+// then fully unrolled with no run-time guards
 template <int NMAX>
-__global__ __launch_bounds__(256) void k_pade(const double2 *__restrict__ f, int n_fun, int n,
+__global__ __launch_bounds__(256) void k_pade(const double2 *__restrict__ f, int n_fun,
                                               const double2 *__restrict__ z,
                                               const double2 *__restrict__ w, int m,
                                               double2 *__restrict__ coef,
                                               double2 *__restrict__ out) {
+  constexpr int n = NMAX;
   const int fun = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int l = threadIdx.x & 63;
   if (fun >= n_fun) return;
@@ -132,20 +138,25 @@ __global__ __launch_bounds__(256) void k_pade(const double2 *__restrict__ f, int
 
 }  // namespace
 
+template <int N>
+void launch_pade_n(dim3 grid, hipStream_t st, const double2 *F, int n_fun, const double2 *Z,
+                   const double2 *W, int m, double2 *C, double2 *O) {
+  hipLaunchKernelGGL(k_pade<N>, grid, dim3(256), 0, st, F, n_fun, Z, W, m, C, O);
+}
+
+template <int... Ns>
+constexpr auto pade_table(std::integer_sequence<int, Ns...>) {
+  return std::array<decltype(&launch_pade_n<1>), sizeof...(Ns)>{&launch_pade_n<Ns + 1>...};
+}
+
 hipError_t launch_pade(const void *f, int n_fun, int n, const void *z, const void *w, int m,
                        void *coef, void *out, hipStream_t st) {
   if (n_fun < 1 || n < 1 || n > kPadeMaxPoints || m < 0) return hipErrorInvalidValue;
   const int64_t blocks = ((int64_t)n_fun + 3) / 4;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  const double2 *F = (const double2 *)f, *Z = (const double2 *)z, *W = (const double2 *)w;
-  double2 *C = (double2 *)coef, *O = (double2 *)out;
-  const dim3 grid((unsigned)blocks), block(256);
-  if (n <= 8)
-    hipLaunchKernelGGL(k_pade<8>, grid, block, 0, st, F, n_fun, n, Z, W, m, C, O);
-  else if (n <= 16)
-    hipLaunchKernelGGL(k_pade<16>, grid, block, 0, st, F, n_fun, n, Z, W, m, C, O);
-  else
-    hipLaunchKernelGGL(k_pade<32>, grid, block, 0, st, F, n_fun, n, Z, W, m, C, O);
+  static constexpr auto table = pade_table(std::make_integer_sequence<int, kPadeMaxPoints>{});
+  table[n - 1](dim3((unsigned)blocks), st, (const double2 *)f, n_fun, (const double2 *)z,
+               (const double2 *)w, m, (double2 *)coef, (double2 *)out);
   return hipGetLastError();
 }
 

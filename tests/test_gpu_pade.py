@@ -80,6 +80,21 @@ def test_many_points_interpolate(ctx, n_points):
     assert np.all(np.isfinite(ctx.pade(z, f, w)))
 
 
+@pytest.mark.parametrize("n_points", list(range(1, 33)))
+def test_every_point_count(ctx, n_points):
+    """The kernel is built once per N: each one interpolates, keeps a_1 = f_1
+    and stays finite; up to N = 12 it also matches the oracle.  300
+    evaluation points run both the four-point blocks and the single tail."""
+    z, f, w, *_ = synth.make_pade_input(600 + n_points, 5, n_points, 300, n_poles=24)
+    out, coef = ctx.pade(z, f, w, coef=True)
+    at_nodes = ctx.pade(z, f, z)
+    err = rel_rows(at_nodes, f)
+    par = rel_rows(out, op.continue_to(z, f, w)) if n_points <= 12 else 0.0
+    say(f"[pade] every N={n_points} interpolation err={err:.2e} parity={par:.2e}")
+    assert np.all(np.isfinite(out)) and np.array_equal(coef[:, 0], f[:, 0])
+    assert err <= 1e-8 and par <= TOL
+
+
 def test_constant_and_rational_degenerate(ctx):
     """A constant has a_2 = 0 exactly; the fraction ends there on both sides."""
     z = 1j * np.exp(np.linspace(np.log(0.05), np.log(30.0), 10))
