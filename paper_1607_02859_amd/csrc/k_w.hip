@@ -12,7 +12,8 @@
 // chi (its eigenvalues are >= 1), so it is inverted in place by the
 // Gauss-Jordan exchange (sweep) without pivoting, in blocks of kWBlock
 // pivots.  Per block P = [P0, P0 + nb) of every matrix of the batch:
-//   k_w_diag   D^-1 of the diagonal block (one workgroup per matrix, LDS);
+//   k_w_diag   D^-1 of the diagonal block (one workgroup per matrix, the
+//              block in registers, pivot row and column through LDS);
 //   k_w_panel  row panel R[p][j] = (D^-1 A[P, :])[p][j] for j outside P and
 //              D^-1 on P; column panel C[i][p] = A[i][P0 + p] for i outside P;
 //   k_w_update A[i][j] <- R[i - P0][j] for i in P, else
