@@ -490,9 +490,16 @@ __global__ __launch_bounds__(256) void k_w_mirror(double2 *__restrict__ a, int n
   __shared__ double2 t[64][64 + 1];
   double2 *A = a + (int64_t)blockIdx.z * n * n;
   const int r0 = J * 64, c0 = I * 64;          // source tile (J, I)
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-    const int r = e / 64, c = e % 64;
-    if (r0 + r < n && c0 + c < n) t[r][c] = A[(int64_t)(r0 + r) * n + c0 + c];
+  // all 16 loads of a thread in flight together, from clamped addresses (the
+  // slots past n are never read back)
+  {
+    const int c = threadIdx.x & 63, rw = threadIdx.x >> 6;
+    double2 x[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      x[q] = A[(int64_t)min(r0 + rw + 4 * q, n - 1) * n + min(c0 + c, n - 1)];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t[rw + 4 * q][c] = x[q];
   }
   __syncthreads();
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
