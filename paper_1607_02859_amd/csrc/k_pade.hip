@@ -7,10 +7,10 @@
 // the tail of the last denominator dropped; an exactly zero denominator in
 // the recursion ends the fraction (that difference and every deeper one are 0).
 //
-// One wave per function: every lane runs the O(N^2) recursion in registers
-// (the table g_n(z_j) is updated in place, j >= n), then the lanes share the
-// evaluation points, so that the outputs of a function are written in
-// contiguous runs.  The points z and w are shared by all functions.
+// One wave per function: lane j holds g_n(z_j) through the recursion (updated
+// in place, j >= n; a_{n-1} is broadcast from its lane at each level), then
+// every lane takes all coefficients and the lanes share the evaluation points,
+// so that the outputs of a function are written in contiguous runs.  The points z and w are shared by all functions.
 //
 // The fraction is evaluated from the innermost level out, with the tail
 // t_k = 1 + c_k / t_{k+1} (c_k = a_k (w - z_{k-1}), t_N = 1) kept as a ratio
@@ -38,6 +38,18 @@ __device__ __forceinline__ double recip(double x) {
   r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
   r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
   return r;
+}
+// the value of lane `lane` (a compile-time constant here) in every lane
+__device__ __forceinline__ double2 bcast(double2 v, int lane) {
+  const unsigned long long x = __builtin_bit_cast(unsigned long long, v.x);
+  const unsigned long long y = __builtin_bit_cast(unsigned long long, v.y);
+  const unsigned long long xb =
+      ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(x >> 32), lane) << 32) |
+      (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, lane);
+  const unsigned long long yb =
+      ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(y >> 32), lane) << 32) |
+      (unsigned)__builtin_amdgcn_readlane((int)(unsigned)y, lane);
+  return make_double2(__builtin_bit_cast(double, xb), __builtin_bit_cast(double, yb));
 }
 __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
   const double d = recip(b.x * b.x + b.y * b.y);
@@ -102,32 +114,27 @@ __global__ __launch_bounds__(256) void k_pade(const double2 *__restrict__ f, int
   const int fun = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int l = threadIdx.x & 63;
   if (fun >= n_fun) return;
-  double2 g[NMAX];
+  // the recursion with lane j holding g_k(z_j) (lanes j < n; the others idle):
+  // at level k + 1 every lane j >= k takes a_k = g_k(z_k) from lane k - 1
   const double2 *F = f + (int64_t)fun * n;
-#pragma unroll
-  for (int j = 0; j < NMAX; ++j) g[j] = j < n ? F[j] : make_double2(0.0, 0.0);
-  // level k + 1: g[j] <- (a_k - g[j]) / ((z_j - z_k) g[j]) for j > k - 1
+  const int jl = min(l, n - 1);
+  const double2 zj = z[jl];
+  double2 gl = F[jl];
 #pragma unroll
   for (int k = 1; k < NMAX; ++k) {
-    const double2 prev = g[k - 1];
-    const double2 zk = z[min(k - 1, n - 1)];
-#pragma unroll
-    for (int j = k; j < NMAX; ++j) {
-      if (j < n) {                                // (j < n implies k < n)
-        const double2 zj = z[j];
-        const double2 den = cmul(make_double2(zj.x - zk.x, zj.y - zk.y), g[j]);
-        g[j] = (den.x == 0.0 && den.y == 0.0)
-                   ? make_double2(0.0, 0.0)
-                   : cdiv(make_double2(prev.x - g[j].x, prev.y - g[j].y), den);
-      }
+    const double2 prev = bcast(gl, k - 1);
+    const double2 zk = z[k - 1];
+    if (l >= k && l < n) {
+      const double2 den = cmul(make_double2(zj.x - zk.x, zj.y - zk.y), gl);
+      gl = (den.x == 0.0 && den.y == 0.0) ? make_double2(0.0, 0.0)
+                                          : cdiv(make_double2(prev.x - gl.x, prev.y - gl.y), den);
     }
   }
-  if (coef != nullptr && l == 0) {
-    double2 *C = coef + (int64_t)fun * n;
+  if (coef != nullptr && l < n) coef[(int64_t)fun * n + l] = gl;
+  // every lane takes all coefficients a_j = g_j(z_j) from lane j
+  double2 g[NMAX];
 #pragma unroll
-    for (int j = 0; j < NMAX; ++j)
-      if (j < n) C[j] = g[j];
-  }
+  for (int j = 0; j < NMAX; ++j) g[j] = bcast(gl, j);
   // evaluation, EU points per lane at a time, the last ones singly
   double2 *O = out + (int64_t)fun * m;
   constexpr int EU = 4;
