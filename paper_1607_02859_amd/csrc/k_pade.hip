@@ -16,7 +16,8 @@
 // t_k = 1 + c_k / t_{k+1} (c_k = a_k (w - z_{k-1}), t_N = 1) kept as a ratio
 // P / Q: t_k = (P + c_k Q) / P, so every level is one complex product and one
 // complex multiply-add, and P_N(w) = a_1 Q / P takes the only division.  P and
-// Q are rescaled together by a power of two when they leave [2^-400, 2^400].
+// Q are rescaled together by a power of two (exact) when P leaves
+// [2^-400, 2^400].
 #include <array>
 #include <utility>
 
@@ -84,7 +85,8 @@ __device__ __forceinline__ void continue_points(const double2 *g, int n,
                          __builtin_fma(c.x, Q[u].y, __builtin_fma(c.y, Q[u].x, P[u].y)));
         Q[u] = P[u];
         P[u] = pn;
-        mx[u] = fmax(fmax(fabs(P[u].x), fabs(P[u].y)), fmax(fabs(Q[u].x), fabs(Q[u].y)));
+        // Q is the previous level's P, already in range
+        mx[u] = fmax(fabs(P[u].x), fabs(P[u].y));
         resc |= !(mx[u] > kLo && mx[u] < kHi);
       }
       if (resc) {
