@@ -10,7 +10,8 @@
 // One wave per function: lane j holds g_n(z_j) through the recursion (updated
 // in place, j >= n; a_{n-1} is broadcast from its lane at each level), then
 // every lane takes all coefficients and the lanes share the evaluation points,
-// so that the outputs of a function are written in contiguous runs.  The points z and w are shared by all functions.
+// so that the outputs of a function are written in contiguous runs.  The
+// points z and w are shared by all functions.
 //
 // The fraction is evaluated from the innermost level out, with the tail
 // t_k = 1 + c_k / t_{k+1} (c_k = a_k (w - z_{k-1}), t_N = 1) kept as a ratio

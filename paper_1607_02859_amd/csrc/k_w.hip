@@ -42,9 +42,6 @@ typedef double d2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) {
-  return make_double2(a.x - b.x, a.y - b.y);
-}
 
 constexpr int NB = kWBlock;
 
