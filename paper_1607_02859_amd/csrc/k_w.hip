@@ -143,13 +143,15 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
                                                  const double2 *__restrict__ dinv,
                                                  double2 *__restrict__ rp, double2 *__restrict__ cp,
                                                  int n, int P0) {
-  // the contraction over the block's 64 bands runs in two halves of PH, so
-  // that two workgroups share a CU.  Every copy loop below issues all its
-  // loads before its first store, so that they are in flight together.
-  constexpr int PH = NB / 2;
+  // the contraction over the block's 64 bands runs in NB / PH parts of PH
+  // bands, so that three workgroups share a CU and the whole grid is resident
+  // at once.  Every copy loop below issues all its loads before its first
+  // store, so that they are in flight together.
+  constexpr int PH = NB / 4;
+  constexpr int PQ = 256 / PH;                 // rows per pass of a part
   constexpr int CPT = 64 * NB / 256;           // column-panel entries per thread
-  constexpr int HPT = NB * PH / 256;           // half-block entries per thread
-  static_assert(CPT == 16 && HPT == 8, "k_w_panel assumes 256 threads and 64-pivot blocks");
+  constexpr int HPT = NB * PH / 256;           // part entries per thread
+  static_assert(CPT == 16 && HPT == 4 && PQ == 16, "k_w_panel assumes 256 threads and 64-pivot blocks");
   __shared__ double2 sd[NB][PH + 1];
   __shared__ double2 sa[PH][64 + 1];
   const int m = blockIdx.y;
@@ -159,7 +161,7 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
   const double2 *A = a + (int64_t)m * n * n;
   const double2 *D = dinv + (int64_t)m * NB * NB;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int t32 = threadIdx.x >> 5, l32 = threadIdx.x & 31;
+  const int tq = threadIdx.x / PH, lq = threadIdx.x % PH;
   // column panel for the rows of this tile below the pivot block (stored);
   // rows above it are written after the MFMAs, through LDS.  Thread entry t:
   // row j0 + w + 4 t, band l.
@@ -189,13 +191,13 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) re[bi][bj] = im[bi][bj] = d4v{0.0, 0.0, 0.0, 0.0};
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < NB / PH; ++h) {
     const int q0 = h * PH;
-    // D^-1 columns q0 .. q0 + PH - 1 (entry t: row t32 + 8 t, column l32)
-    // and M[P, j] for the bands of this half
+    // D^-1 columns q0 .. q0 + PH - 1 (entry t: row tq + PQ t, column lq)
+    // and M[P, j] for the bands of this part
     double2 xd[HPT], xa[HPT];
 #pragma unroll
-    for (int t = 0; t < HPT; ++t) xd[t] = D[(t32 + 8 * t) * NB + q0 + l32];
+    for (int t = 0; t < HPT; ++t) xd[t] = D[(tq + PQ * t) * NB + q0 + lq];
     if (tile <= bp) {
       // M[P, j] is stored (block-lower): entry t band w + 4 t, column l
 #pragma unroll
@@ -204,22 +206,22 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
         xa[t] = (q0 + q < nb && j < n) ? A[(int64_t)(P0 + q0 + q) * n + j] : make_double2(0.0, 0.0);
       }
     } else {
-      // M[P, j] = conj(M[j, P]) above the diagonal: entry t row j0 + t32 + 8 t,
-      // band l32 (reads along the row)
+      // M[P, j] = conj(M[j, P]) above the diagonal: entry t row j0 + tq + PQ t,
+      // band lq (reads along the row)
 #pragma unroll
       for (int t = 0; t < HPT; ++t) {
-        const int q = l32, j = j0 + t32 + 8 * t;
+        const int q = lq, j = j0 + tq + PQ * t;
         xa[t] = (q0 + q < nb && j < n) ? A[(int64_t)j * n + P0 + q0 + q] : make_double2(0.0, 0.0);
       }
     }
 #pragma unroll
-    for (int t = 0; t < HPT; ++t) sd[t32 + 8 * t][l32] = xd[t];
+    for (int t = 0; t < HPT; ++t) sd[tq + PQ * t][lq] = xd[t];
     if (tile <= bp) {
 #pragma unroll
       for (int t = 0; t < HPT; ++t) sa[w + 4 * t][l] = xa[t];
     } else {
 #pragma unroll
-      for (int t = 0; t < HPT; ++t) sa[l32][t32 + 8 * t] = make_double2(xa[t].x, -xa[t].y);
+      for (int t = 0; t < HPT; ++t) sa[lq][tq + PQ * t] = make_double2(xa[t].x, -xa[t].y);
     }
     __syncthreads();
 #pragma unroll 4
@@ -273,9 +275,9 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
     }
   if (tile < bp) {
     // rows i of this tile lie above the pivot block: M[i, p] = -conj(M[p, i]),
-    // M[p, i] stored; staged through LDS in halves so that reads and writes
+    // M[p, i] stored; staged through LDS in parts so that reads and writes
     // run along rows
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NB / PH; ++h) {
       const int q0 = h * PH;
       double2 x[HPT];
 #pragma unroll
@@ -286,18 +288,18 @@ __global__ __launch_bounds__(256) void k_w_panel(const double2 *__restrict__ a,
 #pragma unroll
       for (int t = 0; t < HPT; ++t) sa[w + 4 * t][l] = x[t];
       __syncthreads();
-      double2 *Cp = cp + ((int64_t)m * n + j0 + t32) * NB + q0 + l32;
+      double2 *Cp = cp + ((int64_t)m * n + j0 + tq) * NB + q0 + lq;
       if (j0 + 64 <= n) {
 #pragma unroll
         for (int t = 0; t < HPT; ++t) {
-          const double2 y = sa[l32][t32 + 8 * t];
-          Cp[8 * t * NB] = make_double2(-y.x, y.y);
+          const double2 y = sa[lq][tq + PQ * t];
+          Cp[PQ * t * NB] = make_double2(-y.x, y.y);
         }
       } else {
 #pragma unroll
         for (int t = 0; t < HPT; ++t) {
-          const double2 y = sa[l32][t32 + 8 * t];
-          if (j0 + t32 + 8 * t < n) Cp[8 * t * NB] = make_double2(-y.x, y.y);
+          const double2 y = sa[lq][tq + PQ * t];
+          if (j0 + tq + PQ * t < n) Cp[PQ * t * NB] = make_double2(-y.x, y.y);
         }
       }
       __syncthreads();
