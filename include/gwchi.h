@@ -171,10 +171,22 @@ gwchi_status gwchi_chi_build_device(gwchi_ctx *ctx, const gwchi_item *items, int
                                     gwchi_report *report);
 
 /* Time every GEMM tile configuration on these items (host memory, as for
- * gwchi_chi_build; chi_out is not written), keep the fastest per
- * (precision, real/complex) in the context and write the tune cache file. */
+ * gwchi_chi_build; chi_out is not written): each tile runs a warm-up build
+ * and a timed one, eagerly, with HIP events around every band-GEMM launch,
+ * whatever the context's timing and graph options.  The tile with the
+ * smallest summed GEMM time is kept in the context under the key
+ * "<arch>/<precision>/<r|c>" (e.g. "gfx950/fp32/c") and the tune cache file
+ * is rewritten.  Later builds of that family with tile_id = 0 use it. */
 gwchi_status gwchi_autotune(gwchi_ctx *ctx, const gwchi_item *items, int32_t n_items,
                             gwchi_precision prec);
+
+/* The GEMM times (ms, summed over the launches of one build) that the last
+ * gwchi_autotune of this context measured for each tile of the (prec,
+ * is_complex) family: ms[t] for menu entry t + 1, t < n (-1 past the menu),
+ * and *chosen (may be NULL) = the index t that was kept.  EINVAL when this
+ * context has not tuned that family. */
+gwchi_status gwchi_autotune_times(const gwchi_ctx *ctx, gwchi_precision prec, int32_t is_complex,
+                                  double *ms, int32_t n, int32_t *chosen);
 
 /* ------------------------------------------------------------------------
  * Screened interaction W~ from chi (Sec. II.C steps (iii)-(iv)), FP64.

@@ -221,7 +221,10 @@ int fft_supported(int n);
 // block diagonal (T (T + 1) / 2 per item, T = ceil(n_g / 32)), each written
 // with its mirror.  hermitian = 0: 32x16 tiles over the full matrix.
 hipError_t launch_ct(const CtLaunch &L, int dbl, int max_omega, int hermitian, hipStream_t s);
-// mode 0: |chi(tau_j)|_F^2 of the taus held in x; mode 1: |chi(i omega_k)|_F^2 of out
+// mode 0: |chi(tau_j)|_F^2 of the taus held in x; mode 1: |chi(i omega_k)|_F^2 of out.
+// Matrix m's squared norm is left as kNormParts partial sums at
+// norm[m * kNormParts + p], to be added in order by the caller.
+constexpr int kNormParts = 64;
 hipError_t launch_norms_impl(const CtLaunch &L, int dbl, int mode, double *norm_tau,
                              double *norm_omega, const int32_t *tau_off,
                              const int32_t *omega_off, int max_mats, hipStream_t s);

@@ -16,6 +16,7 @@
 #include <fstream>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <sstream>
 #include <string>
@@ -27,9 +28,43 @@
 
 using namespace gw;
 
+// Fixed device scratch of the allocation-free entry point
+// (gwchi_chi_build_device_noalloc).  Each device holds its own copy of this
+// array for the life of the process.  In host code the name is only a
+// stand-in: its device address comes from hipGetSymbolAddress, taken once per
+// device (scratch_of_device) and kept in the context.
+constexpr int64_t kNoAllocBytes = (int64_t)96 << 20;
+static __device__ __align__(256) char g_noalloc_scratch[kNoAllocBytes];
+
 namespace {
 
 thread_local std::string g_tls_error;
+
+// regions of the fixed scratch: the launch tables, the ticket counters, then
+// the plan's buffers
+constexpr int64_t kNoAllocTables = (int64_t)4 << 20;
+constexpr int64_t kNoAllocCounters = (int64_t)64 << 10;
+
+// Device address of the fixed scratch on `device` (which must be current):
+// looked up once per device, nullptr if the lookup failed.
+void *scratch_of_device(int device, std::string *why) {
+  static std::mutex mu;
+  static std::map<int, std::pair<void *, std::string>> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it == addr.end()) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(g_noalloc_scratch));
+    std::string msg;
+    if (e != hipSuccess) {
+      msg = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      ptr = nullptr;
+    }
+    it = addr.emplace(device, std::make_pair(ptr, msg)).first;
+  }
+  if (why) *why = it->second.second;
+  return it->second.first;
+}
 
 struct DevBuf {
   void *p = nullptr;
@@ -116,7 +151,9 @@ struct gwchi_ctx {
   gwchi_options opt{};
   std::string err;
   std::string tune_path;
+  std::string arch = "gfx950";       // device architecture, the first part of every tune key
   std::map<std::string, int> tune;   // key -> tile index
+  std::map<std::string, std::vector<double>> tune_ms;   // key -> GEMM ms per tile, last autotune
   DevBuf b_phi, b_out, b_psi, b_slab, b_xr, b_x, b_tmp, b_tables, b_norm, b_ctr;
   // screened-interaction step: chi / outputs of the host entry, the matrices
   // being inverted, the pivot-block panels, the per-item tables, the pivot flag
@@ -126,6 +163,12 @@ struct gwchi_ctx {
   DevBuf b_pf, b_pout, b_pcoef, b_ptab;
   HostPinned h_ptab;
   HostPinned h_tables, h_norm;
+  // allocation-free entry: device address of the fixed scratch on this
+  // context's device (nullptr when unavailable, with the reason), and the
+  // host copy of the last launch tables (read by the asynchronous upload)
+  void *noalloc_scratch = nullptr;
+  std::string noalloc_why;
+  std::vector<char> noalloc_blob;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::vector<hipEvent_t> ev_pool;
   // graph cache: one entry keyed by the structural signature of the plan
@@ -296,13 +339,16 @@ int bpb_of(int prec, int cplx) {   // operand bytes per band element
 int elem_c(int prec) { return prec == P_FP64 ? 16 : 8; }            // complex working element
 int elem_slab(int prec, int cplx) { return cplx ? elem_c(prec) : elem_c(prec) / 2; }
 
-std::string tune_key(int prec, int cplx) {
-  return std::string(prec == P_FP64 ? "fp64" : prec == P_FP32 ? "fp32" : "bf16x3") +
+// tune-cache key: architecture / precision / real or complex, e.g. "gfx950/fp32/c"
+std::string tune_key(const gwchi_ctx *ctx, int prec, int cplx) {
+  return ctx->arch + "/" + (prec == P_FP64 ? "fp64" : prec == P_FP32 ? "fp32" : "bf16x3") +
          (cplx ? "/c" : "/r");
 }
 
+// arena_bytes > 0: the plan's buffers must fit in that many bytes of fixed
+// scratch (the allocation-free entry); otherwise the context's budget applies.
 gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int prec,
-                        Plan &P) {
+                        Plan &P, int64_t arena_bytes = 0) {
   P = Plan();
   P.prec = prec;
   // all items of one call use one (precision, complexity) tile family; items that mix
@@ -322,7 +368,7 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
       return GWCHI_EINVAL;
     }
   } else {
-    auto it = ctx->tune.find(tune_key(prec, cplx));
+    auto it = ctx->tune.find(tune_key(ctx, prec, cplx));
     if (it != ctx->tune.end() && it->second >= 0 && it->second < ntile) tile = it->second;
   }
   P.tile = tile;
@@ -433,12 +479,14 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
   // slab, chi(G, r'), the pencil scratch and chi(tau_j); consecutive jobs of
   // one item keep consecutive chi(tau) slots, which the cosine transform reads.
   size_t free_b = 0, total_b = 0;
-  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)64 << 30;
+  if (arena_bytes == 0 && hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)64 << 30;
   // scratch the context already holds is released before a larger plan allocates
   const size_t held = ctx->b_psi.n + ctx->b_slab.n + ctx->b_xr.n + ctx->b_x.n + ctx->b_tmp.n;
-  const int64_t budget = ctx->opt.max_device_bytes > 0 ? ctx->opt.max_device_bytes
-                                                       : (int64_t)((free_b + held) * 0.6);
-  const int64_t fixed = (int64_t)64 << 20;
+  const int64_t budget = arena_bytes > 0 ? arena_bytes
+                         : ctx->opt.max_device_bytes > 0 ? ctx->opt.max_device_bytes
+                                                         : (int64_t)((free_b + held) * 0.6);
+  // the arena holds the five buffers only (each rounded up to 256 bytes)
+  const int64_t fixed = arena_bytes > 0 ? 5 * 256 : (int64_t)64 << 20;
   const int n_jobs = (int)P.jobs.size();
   const int want = ctx->opt.tau_batch > 0 ? std::min(ctx->opt.tau_batch, n_jobs) : n_jobs;
   int W = ctx->opt.slab_width > 0 ? (int)round_up(ctx->opt.slab_width, 256) : 2048;
@@ -498,7 +546,11 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
       break;
     }
     if (W <= 256 || ctx->opt.slab_width > 0) {
-      set_err(ctx, "device memory budget too small for one job with a 256-column slab");
+      if (arena_bytes > 0)
+        set_err(ctx, "allocation-free build: one (item, tau) job with a 256-column slab needs more "
+                     "than the fixed scratch of " + std::to_string(arena_bytes) + " bytes");
+      else
+        set_err(ctx, "device memory budget too small for one job with a 256-column slab");
       return GWCHI_ENOMEM;
     }
     W /= 2;
@@ -520,6 +572,14 @@ struct Blob {
   size_t addv(const std::vector<T> &v) {
     return add(v.data(), v.size() * sizeof(T));
   }
+};
+
+// Device base addresses of a build's buffers.
+struct Bases {
+  char *psi = nullptr, *slab = nullptr, *xr = nullptr, *tmp = nullptr, *x = nullptr;
+  double *norm = nullptr;
+  int32_t *ctr = nullptr;
+  char *tables = nullptr;
 };
 
 struct Built {
@@ -585,19 +645,18 @@ void emit_fft(Built &B, const Plan &P, std::vector<FftJob> &jobs, int phase, int
 
 // Build every launch descriptor.  Pointers into the blob are stored as offsets
 // and patched by patch_blob once the device address of the blob is known.
-void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
-  (void)ctx;
+void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, const Bases &D, Built &B) {
   B.launches.clear();
   B.blob.h.clear();
   const int cplx = P.cplx_any;
   const int ec = elem_c(P.prec);
   const int es = elem_slab(P.prec, cplx);
   const int n_items = (int)P.items.size();
-  char *psi_base = reinterpret_cast<char *>(ctx->b_psi.p);
-  char *slab_base = reinterpret_cast<char *>(ctx->b_slab.p);
-  char *xr_base = reinterpret_cast<char *>(ctx->b_xr.p);
-  char *x_base = reinterpret_cast<char *>(ctx->b_x.p);
-  char *tmp_base = reinterpret_cast<char *>(ctx->b_tmp.p);
+  char *psi_base = D.psi;
+  char *slab_base = D.slab;
+  char *xr_base = D.xr;
+  char *x_base = D.x;
+  char *tmp_base = D.tmp;
   std::ostringstream key;
   key << "p" << P.prec << "t" << P.tile << "w" << P.slab_w << "h" << ctx->opt.hermitian << "n"
       << want_norms << "|";
@@ -658,8 +717,8 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
     Launch Z{};
     Z.phase = PH_NORM;
     Z.kind = 5;
-    Z.fill_ptr = ctx->b_norm.p;
-    Z.fill_bytes = (int64_t)(nt + nw) * 8;
+    Z.fill_ptr = D.norm;
+    Z.fill_bytes = (int64_t)(nt + nw) * kNormParts * 8;
     B.launches.push_back(Z);
   }
   for (int ps = 0; ps < B.n_passes; ++ps) {
@@ -813,7 +872,7 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
       G.gemm.n_units = (int)units.size();
       G.gemm.hermitian = ctx->opt.hermitian;
       if (ctx->opt.persistent) {
-        G.gemm.counter = reinterpret_cast<int32_t *>(ctx->b_ctr.p) + B.n_gemm * kGemmQueues;
+        G.gemm.counter = D.ctr + B.n_gemm * kGemmQueues;
         G.gemm_grid = 0;
       } else {
         G.gemm.counter = nullptr;
@@ -928,7 +987,7 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, Built &B) {
     Launch Z{};
     Z.phase = PH_STAGE;
     Z.kind = 5;
-    Z.fill_ptr = ctx->b_ctr.p;
+    Z.fill_ptr = D.ctr;
     Z.fill_bytes = (int64_t)B.n_gemm * kGemmQueues * 4;
     B.launches.insert(B.launches.begin(), Z);
   }
@@ -991,7 +1050,7 @@ void patch_geos(Built &B, const char *base, size_t off_geos, int n_items) {
   }
 }
 
-gwchi_status enqueue(gwchi_ctx *ctx, const Plan &P, Built &B, bool timing,
+gwchi_status enqueue(gwchi_ctx *ctx, const Plan &P, Built &B, const Bases &D, bool timing,
                      std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> *evs) {
   hipStream_t s = ctx->stream;
   const int cplx = P.cplx_any;
@@ -1030,8 +1089,8 @@ gwchi_status enqueue(gwchi_ctx *ctx, const Plan &P, Built &B, bool timing,
         HIPCHK(launch_ct(L.ct, dbl, L.max_omega, ctx->opt.hermitian, s));
         break;
       case 4:
-        HIPCHK(launch_norms_impl(L.ct, dbl, L.norm_mode, reinterpret_cast<double *>(ctx->b_norm.p),
-                                 reinterpret_cast<double *>(ctx->b_norm.p) + B.n_norm_tau,
+        HIPCHK(launch_norms_impl(L.ct, dbl, L.norm_mode, D.norm,
+                                 D.norm + (int64_t)B.n_norm_tau * kNormParts,
                                  L.toff, L.woff, L.max_mats, s));
         break;
       case 5:
@@ -1046,14 +1105,44 @@ gwchi_status enqueue(gwchi_ctx *ctx, const Plan &P, Built &B, bool timing,
   return GWCHI_OK;
 }
 
+// noalloc: carve every buffer from the fixed device scratch instead of the
+// context's allocations (no report, no graph, no kappa norms).
 gwchi_status run_build(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int prec,
-                       gwchi_report *rep) {
+                       gwchi_report *rep, bool noalloc = false) {
   Plan P;
-  gwchi_status st = build_plan(ctx, items, n_items, prec, P);
+  const int64_t arena = noalloc ? kNoAllocBytes - kNoAllocTables - kNoAllocCounters : 0;
+  gwchi_status st = build_plan(ctx, items, n_items, prec, P, arena);
   if (st != GWCHI_OK) return st;
   // every buffer and table below may still be read by the previous build
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  {
+  const bool want_norms = !noalloc && rep != nullptr && ctx->opt.kappa != 0;
+  int n_norm = 0;
+  for (auto &I : P.items) n_norm += I.n_tau + I.n_omega;
+  int max_slabs = 0;
+  for (auto &I : P.items) max_slabs = std::max<int>(max_slabs, (int)((I.n_r + P.slab_w - 1) / P.slab_w));
+  const size_t n_ctr = (size_t)((int)P.pass_begin.size() - 1) * max_slabs + 16;
+  Bases D;
+  bool moved = false;
+  if (noalloc) {
+    char *base = reinterpret_cast<char *>(ctx->noalloc_scratch);
+    if ((int64_t)(n_ctr * kGemmQueues * 4) > kNoAllocCounters) {
+      set_err(ctx, "allocation-free build: too many GEMM launches for the counter region");
+      return GWCHI_ENOMEM;
+    }
+    D.tables = base;
+    D.ctr = reinterpret_cast<int32_t *>(base + kNoAllocTables);
+    char *p = base + kNoAllocTables + kNoAllocCounters;
+    char **dst[5] = {&D.psi, &D.slab, &D.xr, &D.tmp, &D.x};
+    const int64_t need[5] = {P.psi_bytes, P.slab_bytes, P.xr_bytes, P.tmp_bytes, P.x_bytes};
+    for (int k = 0; k < 5; ++k) {
+      *dst[k] = p;
+      p += round_up(need[k], 256);
+    }
+    if (p > base + kNoAllocBytes) {       // the planner sized the buffers to fit
+      set_err(ctx, "allocation-free build: plan exceeds the fixed scratch");
+      return GWCHI_ENOMEM;
+    }
+  } else {
     // scratch for the plan; when any buffer must grow, drop all of them first so
     // that old and new never coexist
     DevBuf *bufs[5] = {&ctx->b_psi, &ctx->b_slab, &ctx->b_xr, &ctx->b_tmp, &ctx->b_x};
@@ -1064,20 +1153,18 @@ gwchi_status run_build(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int
       for (int k = 0; k < 5; ++k) bufs[k]->release();
       for (int k = 0; k < 5; ++k) HIPCHK(bufs[k]->ensure((size_t)need[k], nullptr));
     }
-  }
-  bool moved = false;
-  const bool want_norms = rep != nullptr && ctx->opt.kappa != 0;
-  int n_norm = 0;
-  for (auto &I : P.items) n_norm += I.n_tau + I.n_omega;
-  HIPCHK(ctx->b_norm.ensure((size_t)n_norm * 8 + 64, &moved));
-  {
-    int max_slabs = 0;
-    for (auto &I : P.items) max_slabs = std::max<int>(max_slabs, (int)((I.n_r + P.slab_w - 1) / P.slab_w));
-    const size_t n_ctr = (size_t)((int)P.pass_begin.size() - 1) * max_slabs + 16;
+    HIPCHK(ctx->b_norm.ensure((size_t)n_norm * kNormParts * 8 + 64, &moved));
     HIPCHK(ctx->b_ctr.ensure(n_ctr * kGemmQueues * 4, &moved));
+    D.psi = reinterpret_cast<char *>(ctx->b_psi.p);
+    D.slab = reinterpret_cast<char *>(ctx->b_slab.p);
+    D.xr = reinterpret_cast<char *>(ctx->b_xr.p);
+    D.tmp = reinterpret_cast<char *>(ctx->b_tmp.p);
+    D.x = reinterpret_cast<char *>(ctx->b_x.p);
+    D.norm = reinterpret_cast<double *>(ctx->b_norm.p);
+    D.ctr = reinterpret_cast<int32_t *>(ctx->b_ctr.p);
   }
   Built B;
-  build_launches(ctx, P, want_norms, B);
+  build_launches(ctx, P, want_norms, D, B);
   // geos offset: locate it as the table referenced by the first FFT launch
   size_t off_geos = 0;
   for (auto &L : B.launches)
@@ -1085,13 +1172,29 @@ gwchi_status run_build(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int
       off_geos = reinterpret_cast<uintptr_t>(L.fft.geos);
       break;
     }
-  HIPCHK(ctx->b_tables.ensure(B.blob.h.size() + 64, &moved));
-  const char *tbase = reinterpret_cast<const char *>(ctx->b_tables.p);
-  patch_geos(B, tbase, off_geos, n_items);
-  patch_blob(B, tbase);
+  if (noalloc) {
+    if ((int64_t)B.blob.h.size() > kNoAllocTables) {
+      set_err(ctx, "allocation-free build: launch tables of " + std::to_string(B.blob.h.size()) +
+                       " bytes exceed the " + std::to_string(kNoAllocTables) + "-byte table region");
+      return GWCHI_ENOMEM;
+    }
+  } else {
+    HIPCHK(ctx->b_tables.ensure(B.blob.h.size() + 64, &moved));
+    D.tables = reinterpret_cast<char *>(ctx->b_tables.p);
+  }
+  patch_geos(B, D.tables, off_geos, n_items);
+  patch_blob(B, D.tables);
+  if (noalloc) {
+    // the host copy lives in the context until the next build (which first
+    // waits for this one's stream), so the asynchronous copy may read it late
+    ctx->noalloc_blob.assign(B.blob.h.begin(), B.blob.h.end());
+    HIPCHK(hipMemcpyAsync(D.tables, ctx->noalloc_blob.data(), ctx->noalloc_blob.size(),
+                          hipMemcpyHostToDevice, ctx->stream));
+    return enqueue(ctx, P, B, D, false, nullptr);
+  }
   HIPCHK(ctx->h_tables.ensure(B.blob.h.size() + 64));
   std::memcpy(ctx->h_tables.p, B.blob.h.data(), B.blob.h.size());
-  HIPCHK(hipMemcpyAsync(ctx->b_tables.p, ctx->h_tables.p, B.blob.h.size(),
+  HIPCHK(hipMemcpyAsync(D.tables, ctx->h_tables.p, B.blob.h.size(),
                         hipMemcpyHostToDevice, ctx->stream));
   const bool timing = ctx->opt.timing != 0;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> evs;
@@ -1127,7 +1230,7 @@ gwchi_status run_build(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int
       }
       ctx->graph_key.clear();
       HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-      st = enqueue(ctx, P, B, false, nullptr);
+      st = enqueue(ctx, P, B, D, false, nullptr);
       hipGraph_t g = nullptr;
       hipError_t ec = hipStreamEndCapture(ctx->stream, &g);
       if (st != GWCHI_OK) {
@@ -1152,7 +1255,7 @@ gwchi_status run_build(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int
       HIPCHK(hipGraphLaunch(ctx->graph_exec, ctx->stream));
     }
   } else {
-    st = enqueue(ctx, P, B, timing, &evs);
+    st = enqueue(ctx, P, B, D, timing, &evs);
     if (st != GWCHI_OK) return st;
   }
   if (rep) {
@@ -1186,9 +1289,11 @@ gwchi_status run_build(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int
     rep->kappa_F_max = -1.0;
   }
   if (rep && want_norms) {
-    // kappa_F from the norms
-    std::vector<double> nrm(n_norm);
-    HIPCHK(hipMemcpy(nrm.data(), ctx->b_norm.p, (size_t)n_norm * 8, hipMemcpyDeviceToHost));
+    // kappa_F from the norms: each squared norm is the in-order sum of its partial slots
+    std::vector<double> part((size_t)n_norm * kNormParts), nrm(n_norm, 0.0);
+    HIPCHK(hipMemcpy(part.data(), D.norm, part.size() * 8, hipMemcpyDeviceToHost));
+    for (int m = 0; m < n_norm; ++m)
+      for (int p = 0; p < kNormParts; ++p) nrm[m] += part[(size_t)m * kNormParts + p];
     double kmax = 0.0;
     int ot = 0, ow = B.n_norm_tau;
     for (auto &I : P.items) {
@@ -1616,6 +1721,7 @@ gwchi_status gwchi_create(gwchi_ctx **out, int32_t device_id, const char *tune_c
     }
     std::unique_ptr<gwchi_ctx> ctx(new gwchi_ctx());
     ctx->device = device_id;
+    ctx->arch = std::string(prop.gcnArchName).substr(0, 6);
     ctx->num_cu = prop.multiProcessorCount;
     ctx->lds_max = prop.sharedMemPerBlock;
     if (hipSetDevice(device_id) != hipSuccess ||
@@ -1625,6 +1731,8 @@ gwchi_status gwchi_create(gwchi_ctx **out, int32_t device_id, const char *tune_c
       g_tls_error = "stream/event creation failed";
       return GWCHI_EDEVICE;
     }
+    // the fixed scratch of the allocation-free entry, with this device current
+    ctx->noalloc_scratch = scratch_of_device(device_id, &ctx->noalloc_why);
     ctx->opt.use_graph = 1;
     ctx->opt.hermitian = 1;
     ctx->opt.persistent = 1;
@@ -1752,6 +1860,10 @@ gwchi_status gwchi_autotune(gwchi_ctx *ctx, const gwchi_item *items, int32_t n_i
                             gwchi_precision prec) {
   if (!ctx) return GWCHI_EINVAL;
   try {
+    if (prec != GWCHI_FP64 && prec != GWCHI_FP32 && prec != GWCHI_BF16X3) {
+      set_err(ctx, "unknown precision");
+      return GWCHI_EINVAL;
+    }
     gwchi_status st = validate_items(ctx, items, n_items, true);
     if (st != GWCHI_OK) return st;
     HIPCHK(hipSetDevice(ctx->device));
@@ -1761,23 +1873,30 @@ gwchi_status gwchi_autotune(gwchi_ctx *ctx, const gwchi_item *items, int32_t n_i
     const int cplx = items[0].is_complex;
     const int n = gemm_tile_count((int)prec, cplx);
     const gwchi_options saved = ctx->opt;
+    // every tile runs the same eager launch list with per-launch events, so
+    // that the band-GEMM time of each tile is measured (a warm-up build, then
+    // the timed one)
+    std::vector<double> ms(n, 0.0);
     double best = 1e300;
     int best_t = 0;
     for (int t = 0; t < n; ++t) {
       ctx->opt = saved;
       ctx->opt.tile_id = t + 1;
       ctx->opt.use_graph = 0;
+      ctx->opt.timing = 1;
       gwchi_report rep;
-      // warm-up, then timed
-      st = run_build(ctx, dev_items.data(), n_items, (int)prec, &rep);
-      if (st != GWCHI_OK) {
-        ctx->opt = saved;
-        return st;
+      for (int rep_i = 0; rep_i < 2; ++rep_i) {
+        st = run_build(ctx, dev_items.data(), n_items, (int)prec, &rep);
+        if (st != GWCHI_OK) {
+          ctx->opt = saved;
+          return st;
+        }
       }
-      st = run_build(ctx, dev_items.data(), n_items, (int)prec, &rep);
-      if (st != GWCHI_OK) {
+      ms[t] = rep.ms_gemm;
+      if (!(rep.ms_gemm > 0.0)) {
         ctx->opt = saved;
-        return st;
+        set_err(ctx, "autotune: tile " + std::to_string(t + 1) + " measured no GEMM time");
+        return GWCHI_EDEVICE;
       }
       if (rep.ms_gemm < best) {
         best = rep.ms_gemm;
@@ -1785,12 +1904,30 @@ gwchi_status gwchi_autotune(gwchi_ctx *ctx, const gwchi_item *items, int32_t n_i
       }
     }
     ctx->opt = saved;
-    ctx->tune[tune_key((int)prec, cplx)] = best_t;
+    const std::string key = tune_key(ctx, (int)prec, cplx);
+    ctx->tune[key] = best_t;
+    ctx->tune_ms[key] = ms;
     save_tune(ctx);
     return GWCHI_OK;
   } catch (...) {
     set_err(ctx, "internal error");
     return GWCHI_EDEVICE;
+  }
+}
+
+gwchi_status gwchi_autotune_times(const gwchi_ctx *ctx, gwchi_precision prec, int32_t is_complex,
+                                  double *ms, int32_t n, int32_t *chosen) {
+  if (!ctx || !ms || n < 0) return GWCHI_EINVAL;
+  try {
+    const std::string key = tune_key(ctx, (int)prec, is_complex ? 1 : 0);
+    auto it = ctx->tune_ms.find(key);
+    auto ch = ctx->tune.find(key);
+    if (it == ctx->tune_ms.end() || ch == ctx->tune.end()) return GWCHI_EINVAL;
+    for (int32_t t = 0; t < n; ++t) ms[t] = t < (int32_t)it->second.size() ? it->second[t] : -1.0;
+    if (chosen) *chosen = ch->second;
+    return GWCHI_OK;
+  } catch (...) {
+    return GWCHI_EINVAL;
   }
 }
 

@@ -239,7 +239,10 @@ __global__ __launch_bounds__(512) void k_ct_herm(CtLaunch L, int k0) {
 }
 
 // sum of |x|^2: mode 0 over the taus held in x (with Hermitian completion
-// when set), mode 1 over the omegas of out; one atomic add per block and matrix
+// when set), mode 1 over the omegas of out.  Block x of the grid writes its
+// partial sum of matrix m to slot [m][x] (kNormParts slots per matrix); the
+// host adds the slots in order, so the result does not depend on the order
+// in which blocks finish.
 template <typename T>
 __global__ __launch_bounds__(256) void k_norms(CtLaunch L, int mode, double *norm_tau,
                                                double *norm_omega, const int32_t *tau_off,
@@ -271,8 +274,8 @@ __global__ __launch_bounds__(256) void k_norms(CtLaunch L, int mode, double *nor
     __syncthreads();
     if (threadIdx.x == 0) {
       const double t = red[0] + red[1] + red[2] + red[3];
-      if (mode == 0) atomicAdd(&norm_tau[tau_off[it.item] + it.j0 + m], t);
-      else atomicAdd(&norm_omega[omega_off[it.item] + m], t);
+      const int64_t slot = mode == 0 ? tau_off[it.item] + it.j0 + m : omega_off[it.item] + m;
+      (mode == 0 ? norm_tau : norm_omega)[slot * kNormParts + blockIdx.x] = t;
     }
     __syncthreads();
   }
@@ -324,7 +327,7 @@ hipError_t launch_norms_impl(const CtLaunch &L, int dbl, int mode, double *nt, d
                              const int32_t *toff, const int32_t *woff, int max_mats,
                              hipStream_t s) {
   if (L.n_items <= 0 || max_mats <= 0) return hipSuccess;
-  dim3 grid(64, L.n_items, max_mats < 64 ? max_mats : 64);
+  dim3 grid(kNormParts, L.n_items, max_mats < 64 ? max_mats : 64);
   if (dbl) hipLaunchKernelGGL((k_norms<double>), grid, dim3(256), 0, s, L, mode, nt, nw, toff, woff);
   else hipLaunchKernelGGL((k_norms<float>), grid, dim3(256), 0, s, L, mode, nt, nw, toff, woff);
   return hipGetLastError();

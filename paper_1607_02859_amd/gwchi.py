@@ -21,8 +21,9 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTSUP", 5: "ENU
 
 EXPORTS = ["gwchi_create", "gwchi_destroy", "gwchi_set_options", "gwchi_get_options",
            "gwchi_validate", "gwchi_chi_build", "gwchi_chi_build_device", "gwchi_autotune",
-           "gwchi_last_error", "gwchi_version", "gwchi_w_build", "gwchi_w_build_device", "gwchi_w_validate",
-           "gwchi_pade", "gwchi_pade_device", "gwchi_pade_validate"]
+           "gwchi_autotune_times", "gwchi_last_error", "gwchi_version", "gwchi_w_build",
+           "gwchi_w_build_device", "gwchi_w_validate", "gwchi_pade", "gwchi_pade_device",
+           "gwchi_pade_validate"]
 
 
 class GwchiItem(C.Structure):
@@ -153,6 +154,8 @@ def load(path: str = LIB_PATH):
     lib.gwchi_chi_build_device.argtypes = [C.c_void_p, P(GwchiItem), C.c_int32, C.c_int,
                                            C.c_void_p, P(GwchiReport)]
     lib.gwchi_autotune.argtypes = [C.c_void_p, P(GwchiItem), C.c_int32, C.c_int]
+    lib.gwchi_autotune_times.argtypes = [C.c_void_p, C.c_int, C.c_int32, P(C.c_double), C.c_int32,
+                                         P(C.c_int32)]
     lib.gwchi_w_build.argtypes = [C.c_void_p, P(GwchiWItem), C.c_int32, P(GwchiWReport)]
     lib.gwchi_w_validate.argtypes = [P(GwchiWItem), C.c_int32]
     lib.gwchi_pade_validate.argtypes = [P(GwchiPadeItem)]
@@ -165,7 +168,7 @@ def load(path: str = LIB_PATH):
     lib.gwchi_version.restype = C.c_char_p
     for f in ("gwchi_create", "gwchi_destroy", "gwchi_set_options", "gwchi_get_options",
               "gwchi_validate", "gwchi_chi_build", "gwchi_chi_build_device", "gwchi_autotune",
-              "gwchi_w_build", "gwchi_w_build_device", "gwchi_w_validate",
+              "gwchi_autotune_times", "gwchi_w_build", "gwchi_w_build_device", "gwchi_w_validate",
               "gwchi_pade", "gwchi_pade_device", "gwchi_pade_validate"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
@@ -383,10 +386,20 @@ class Context:
         outs = [np.empty((np.asarray(it.ct).shape[0], len(it.g_index), len(it.g_index)),
                          np.complex128) for it in items]
         arr = (GwchiItem * len(items))(*[make_item(keep, it, chi_out=o) for it, o in zip(items, outs)])
-        # autotune works on device copies made by a host build first
         st = self.lib.gwchi_autotune(self.h, arr, len(items), PRECISIONS[prec])
         if st != 0:
             raise self._err(st)
+
+    def autotune_times(self, prec="fp32", is_complex=True, n=6):
+        """(GEMM ms per tile measured by the last autotune of this family,
+        index of the tile kept)."""
+        ms = (C.c_double * n)()
+        chosen = C.c_int32(-1)
+        st = self.lib.gwchi_autotune_times(self.h, PRECISIONS[prec], 1 if is_complex else 0, ms, n,
+                                           C.byref(chosen))
+        if st != 0:
+            raise self._err(st)
+        return list(ms), int(chosen.value)
 
     def w_build(self, witems: Sequence, omega=False, report=False):
         """Host-memory W~ (gwchi_w_build): returns a list of complex128 arrays

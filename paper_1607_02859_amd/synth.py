@@ -42,6 +42,10 @@ __all__ = [
     "coulomb_sqrt",
     "make_w_item",
     "make_pade_input",
+    "st_fit",
+    "gauss_legendre_st",
+    "SigmaItem",
+    "make_sigma_item",
 ]
 
 
@@ -196,6 +200,45 @@ def ct_grid(n_tau: int, x_min: float, x_max: float, ridge: float = 1e-6):
     """
     tau, omega, ct, err = _ct_grid_cached(int(n_tau), float(x_min), float(x_max), float(ridge))
     return tau.copy(), omega.copy(), ct.copy(), err
+
+
+def st_fit(tau: np.ndarray, omega: np.ndarray, x_min: float, x_max: float, ridge: float = 1e-6):
+    """Sine-transform coefficients st[k][j] = lambda_kj sin(omega_k tau_j) on a
+    given tau/omega grid: for each omega_k, the least-squares minimisation of the
+    relative residual of Eq. (8), 2 omega_k/(x^2 + omega_k^2) - sum_j st_kj exp(-x tau_j),
+    on 1500 log-spaced x in [x_min, x_max], with the same small ridge on
+    column-scaled coefficients as the cosine fit.  Returns (st, fit_err)."""
+    tau = np.asarray(tau, dtype=np.float64)
+    x = np.geomspace(x_min, x_max, 1500)
+    E = np.exp(-np.outer(x, tau))
+    S = np.empty((len(omega), len(tau)))
+    err = 0.0
+    for k, w in enumerate(omega):
+        f = 2.0 * w / (x * x + w * w)
+        A = E / f[:, None]
+        sc = np.sqrt((A * A).sum(0))
+        As = A / sc
+        M = np.vstack([As, ridge * np.eye(len(tau))]) if ridge > 0.0 else As
+        rhs = np.concatenate([np.ones(len(x)), np.zeros(len(tau))]) if ridge > 0.0 else np.ones(len(x))
+        c = np.linalg.lstsq(M, rhs, rcond=None)[0] / sc
+        S[k] = c
+        err = max(err, float(np.abs(A @ c - 1.0).max()))
+    return S, err
+
+
+def gauss_legendre_st(omega: np.ndarray, t_max: float, panel: float = 0.1, nodes: int = 8):
+    """Dense-quadrature sine coefficients on the nodes of ``gauss_legendre_ct``:
+    st[k][j] = 2 w_j sin(omega_k tau_j), so that sum_j st[k][j] exp(-x tau_j) ->
+    2 int_0^inf sin(omega tau) exp(-x tau) dtau = 2 omega/(x^2 + omega^2), the
+    closed form under the brace of Eq. (8)."""
+    n_pan = int(math.ceil(t_max / panel))
+    h = t_max / n_pan
+    xg, wg = np.polynomial.legendre.leggauss(nodes)
+    left = np.arange(n_pan) * h
+    tau = (left[:, None] + (xg[None, :] + 1.0) * 0.5 * h).ravel()
+    w = np.tile(wg * 0.5 * h, n_pan)
+    st = 2.0 * w[None, :] * np.sin(np.outer(omega, tau))
+    return tau, st
 
 
 def gauss_legendre_ct(omega: np.ndarray, t_max: float, panel: float = 0.1, nodes: int = 8):
@@ -407,3 +450,91 @@ def make_pade_input(seed, n_fun, n_points, n_eval, *, n_poles=4, span=5.0, eta=0
     f = c[:, None] + (r[:, None, :] / (z[None, :, None] - e[:, None, :])).sum(axis=2)
     w = np.linspace(-2 * span, 2 * span, n_eval) + 1j * eta
     return z, f.astype(np.complex128), w, e, r, c
+
+
+# ----------------------------------------------------------------------------
+# Inputs of the self-energy step
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class SigmaItem:
+    """One self-energy problem at the Gamma point: orbitals and eigenvalues as
+    for the polarizability, the tau/omega grid with its cosine (ct) and sine
+    (st) coefficients, the correlated screened interaction W~(G, G', i tau_j)
+    on the plane-wave list, and the states whose diagonal elements are wanted
+    (index b < n_occ: occupied band b; otherwise unoccupied band b - n_occ)."""
+
+    n: tuple
+    phi_occ: np.ndarray      # (n_occ, N_r) complex128
+    phi_unocc: np.ndarray    # (n_unocc, N_r)
+    eps_occ: np.ndarray
+    eps_unocc: np.ndarray
+    mu: float
+    tau: np.ndarray          # (n_tau,)
+    omega: np.ndarray        # (n_omega,)
+    ct: np.ndarray           # (n_omega, n_tau)
+    st: np.ndarray           # (n_omega, n_tau)
+    g_index: np.ndarray      # (n_g,) int32
+    w_tau: np.ndarray        # (n_tau, n_g, n_g) complex128, Hermitian per tau
+    states: np.ndarray       # (n_states,) int32
+
+    @property
+    def n_r(self) -> int:
+        return int(self.n[0] * self.n[1] * self.n[2])
+
+    @property
+    def n_occ(self) -> int:
+        return self.phi_occ.shape[0]
+
+    @property
+    def n_unocc(self) -> int:
+        return self.phi_unocc.shape[0]
+
+    @property
+    def n_tau(self) -> int:
+        return self.tau.shape[0]
+
+    @property
+    def n_omega(self) -> int:
+        return self.ct.shape[0]
+
+    @property
+    def n_g(self) -> int:
+        return self.g_index.shape[0]
+
+    @property
+    def n_states(self) -> int:
+        return self.states.shape[0]
+
+
+def make_sigma_item(seed, n, n_occ, n_unocc, n_tau, n_states, *, gap=1.0, x_min=0.5,
+                    x_max=75.0, n_g=None, rank=None, strength=1.0) -> SigmaItem:
+    """One seeded self-energy item with complex orbitals.
+
+    Orbitals, eigenvalues, grid and cosine coefficients are those of
+    ``make_item``; the sine coefficients come from ``st_fit`` on the same grid.
+    The screened interaction is a Hermitian, negative semidefinite stand-in
+    that decays in tau like the correlated interaction:
+        W~(i tau_j) = -strength sum_m exp(-x_m tau_j) b_m b_m^H,
+    ``rank`` terms (default n_g / 4), b_m complex Gaussian over the plane waves
+    (variance 1/n_g), x_m log-spaced in [x_min, x_max].  The states are the
+    n_states bands nearest the gap, half below and half above it."""
+    it = make_item(seed, n, n_occ, n_unocc, True, n_tau, gap=gap, x_min=x_min, x_max=x_max,
+                   n_g=n_g)
+    st, _ = st_fit(it.tau, it.omega, x_min, x_max)
+    rng = np.random.default_rng([seed, 77])
+    g = it.g_index.shape[0]
+    rank = max(1, g // 4) if rank is None else int(rank)
+    b = (rng.standard_normal((g, rank)) + 1j * rng.standard_normal((g, rank))) / math.sqrt(2.0 * g)
+    x = np.exp(np.linspace(math.log(x_min), math.log(x_max), rank))
+    w = np.empty((it.tau.shape[0], g, g), dtype=np.complex128)
+    for j, t in enumerate(it.tau):
+        w[j] = -(b * (strength * np.exp(-x * t))[None, :]) @ b.conj().T
+        w[j] = 0.5 * (w[j] + w[j].conj().T)
+    n_below = min(n_occ, (n_states + 1) // 2)
+    n_above = min(n_unocc, n_states - n_below)
+    states = np.concatenate([np.arange(n_occ - n_below, n_occ),
+                             np.arange(n_occ, n_occ + n_above)]).astype(np.int32)
+    return SigmaItem(n=it.n, phi_occ=it.phi_occ, phi_unocc=it.phi_unocc, eps_occ=it.eps_occ,
+                     eps_unocc=it.eps_unocc, mu=it.mu, tau=it.tau, omega=it.omega, ct=it.ct,
+                     st=np.ascontiguousarray(st), g_index=it.g_index, w_tau=w, states=states)

@@ -1,6 +1,8 @@
-"""Full-size workload configurations on the GPU, checked against the oracle on
-sampled rows of chi(i omega) (pair sum + one FFT over r' per row) and by
-Hermiticity of every result.
+"""Full-size workload configurations on the GPU, in the launch configuration
+the benchmark times (Hermitian completion, persistent launch, graph),
+checked against the oracle on sampled rows of chi(i omega) (pair sum + one FFT
+over r' per row).  Hermiticity is checked where it is not built in (the
+full-matrix tests of the parity suite run without completion).
 
 * 8 k-points on 24^3 with uneven band counts, all in one call;
 * 32^3 with 128 + 2048 complex bands;
@@ -58,10 +60,8 @@ def check(cfg, outs, sample, prec):
         assert out.shape == (it.n_omega, it.n_g, it.n_g)
         assert np.all(np.isfinite(out))
         err = oc.rel_frobenius(out[:, list(rows), :], ref_rows(cfg, t, rows))
-        herm = np.abs(out - np.conj(np.transpose(out, (0, 2, 1)))).max() / np.abs(out).max()
-        say(f"   item {t} rows {rows}: err={err:.3e} herm={herm:.1e}")
+        say(f"   item {t} (n={it.n[0]}, K={it.n_occ}+{it.n_unocc}) rows {rows}: err={err:.3e}")
         worst = max(worst, err)
-        assert herm < (1e-12 if prec == "fp64" else 1e-5)
     assert worst <= TOL[prec]
 
 
@@ -72,7 +72,7 @@ def test_kpoint_batch_uneven_bands(ctx, prec):
     ctx.set_options(use_graph=1, hermitian=1, slab_width=0, tile_id=0)
     outs, rep = ctx.build(items, prec, report=True)
     say(f"   ms={rep['ms_total']:.1f} kappa_F={rep['kappa_F_max']:.2f} tau_batch={rep['tau_batch']}")
-    check(3, outs, [(0, (0, 700)), (5, (3, 2968))], prec)
+    check(3, outs, [(0, (0, 700)), (2, (11, 2000)), (5, (3, 2968)), (7, (1, 1234))], prec)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
@@ -82,7 +82,7 @@ def test_32cubed(ctx, prec):
     ctx.set_options(use_graph=1, hermitian=1, slab_width=0, tile_id=0)
     outs, rep = ctx.build(items, prec, report=True)
     say(f"   ms={rep['ms_total']:.1f} kappa_F={rep['kappa_F_max']:.2f} slab={rep['slab_width']}")
-    check(4, outs, [(0, (1, 7122))], prec)
+    check(4, outs, [(0, (1, 100, 2500, 5000, 7122))], prec)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
@@ -92,4 +92,7 @@ def test_multi_system_batch(ctx, prec):
     ctx.set_options(use_graph=1, hermitian=1, slab_width=0, tile_id=0)
     outs, rep = ctx.build(items, prec, report=True)
     say(f"   ms={rep['ms_total']:.1f} kappa_F={rep['kappa_F_max']:.2f}")
-    check(5, outs, [(0, (0, 5)), (9, (2, 100)), (20, (1, 1000)), (31, (7, 4000))], prec)
+    # one system of every grid size (16, 18, 20, 24, 28), the smallest and
+    # largest gaps among them
+    check(5, outs, [(0, (0, 5)), (9, (2, 100)), (16, (3, 1700)), (20, (1, 1000)),
+                    (31, (7, 4000))], prec)

@@ -95,6 +95,27 @@ def test_every_point_count(ctx, n_points):
     assert err <= 1e-8 and par <= TOL
 
 
+@pytest.mark.parametrize("n_points", list(range(13, 33)))
+def test_generic_data_parity_beyond_twelve_points(ctx, n_points):
+    """Coefficients and values for N = 13..32 on generic (non-rational) data:
+    random complex values at the usual imaginary-axis points.  The recursion is
+    well conditioned there (the oracle matches exact rational arithmetic to
+    1e-12 up to 32 points, pinned on the CPU), so the GPU coefficients must
+    match the oracle to 1e-8, and so must the values at evaluation points on
+    the imaginary axis between the nodes, where the fraction has no pole."""
+    rng = np.random.default_rng(900 + n_points)
+    z = 1j * np.exp(np.linspace(np.log(0.05), np.log(30.0), n_points))
+    f = rng.standard_normal((33, n_points)) + 1j * rng.standard_normal((33, n_points))
+    w = 1j * np.sqrt(np.abs(z[:-1]) * np.abs(z[1:]))          # between the nodes
+    out, coef = ctx.pade(z, f, w, coef=True)
+    ref_c = op.coefficients(z, f)
+    ref_o = op.evaluate(z, ref_c, w)
+    cerr = float((np.abs(coef - ref_c) / np.abs(ref_c)).max())
+    oerr = rel_rows(out, ref_o)
+    say(f"[pade] generic N={n_points} coef err={cerr:.2e} value err={oerr:.2e}")
+    assert cerr <= TOL and oerr <= TOL
+
+
 def test_constant_and_rational_degenerate(ctx):
     """A constant has a_2 = 0 exactly; the fraction ends there on both sides."""
     z = 1j * np.exp(np.linspace(np.log(0.05), np.log(30.0), 10))

@@ -2,10 +2,12 @@
 (iii)-(iv)) against the CPU FP64 oracle, through the C ABI.
 
 The path is FP64 throughout; every comparison uses the FP64 bound of
-1e-10 max relative Frobenius error.  Cases span several 64 x 64 update tiles
-and 32-pivot blocks with ragged tails, sizes below one block, several items
+1e-10 on the maximum, over the tau (or omega) matrices, of the relative
+Frobenius error of each matrix.  Cases span several 64 x 64 update tiles
+and 64-pivot blocks with ragged tails, sizes below one block, several items
 of different sizes in one call, the device entry, the full 24^3 sphere
-(2969 plane waves, 12 frequencies) on sampled rows, and the error paths.
+(2969 plane waves, 12 frequencies) and the 32^3 sphere (7123 plane waves) on
+sampled rows, and the error paths.
 """
 import sys
 
@@ -27,7 +29,10 @@ def say(*a):
 
 
 def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    """max over the leading (tau or omega) index of ||a_j - b_j||_F / ||b_j||_F"""
+    a = np.asarray(a).reshape(np.shape(b)[0], -1)
+    b = np.asarray(b).reshape(np.shape(b)[0], -1)
+    return float((np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)).max())
 
 
 @pytest.fixture(scope="module")
@@ -138,6 +143,27 @@ def test_full_sphere24_sampled_rows(ctx):
     assert np.abs(m - m.conj().T).max() <= 1e-10 * np.abs(m).max()
     ev = np.linalg.eigvalsh(0.5 * (m + m.conj().T))
     assert ev.max() <= 1e-10 * np.abs(ev).max()
+
+
+def test_sphere32_sampled_rows(ctx):
+    """The 32^3 sphere (7123 plane waves, 112 pivot blocks, a ragged last
+    block of 19), the plane-wave count of the largest polarizability
+    workload, with 4 frequencies: sampled rows against linear solves."""
+    w = synth.make_w_item(67, (32, 32, 32), 4, strength=4.0)
+    say(f"[w] sphere32 n_g={w.n_g} n_omega={w.n_omega}")
+    (taus, oms), rep = ctx.w_build([w], omega=True, report=True)
+    say(f"   ms total={rep['ms_total']:.2f} invert={rep['ms_invert']:.2f}")
+    rows = [0, 1, 64, 3000, 7040, w.n_g - 1]
+    ref_w = np.stack([ow.w_tilde_omega_rows(w.chi[k], w.sqrt_v, rows) for k in range(w.n_omega)])
+    ict = ow.inverse_ct(w.ct)
+    ref = np.zeros_like(ref_w)
+    for j in range(ict.shape[0]):
+        for k in range(ict.shape[1]):                   # Eq. (50), increasing k
+            ref[j] += ict[j, k] * ref_w[k]
+    err = rel(taus[0][:, rows, :], ref)
+    err_w = rel(oms[0][:, rows, :], ref_w)
+    say(f"   err(sampled rows) tau={err:.3e} omega={err_w:.3e}")
+    assert err <= TOL and err_w <= TOL
 
 
 def test_not_positive_definite_is_reported(ctx):

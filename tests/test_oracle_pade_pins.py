@@ -143,3 +143,51 @@ def test_batched_shapes():
     out = op.continue_to(z, f, w)
     assert out.shape == (3, 4, 6)
     assert np.allclose(out[2, 1], op.continue_to(z, f[2, 1], w))
+
+
+# ---------------------------------------------------------------------------
+# The recursion against exact rational arithmetic.  The inputs are FP64
+# numbers, hence exact rationals; the recursion of Eqs. (73)-(74) run in
+# fractions.Fraction gives the exact coefficients, which the FP64 oracle must
+# reproduce to its rounding error.  Generic (non-rational) data keep every
+# level well conditioned, so this holds for every point count up to 32.
+# ---------------------------------------------------------------------------
+
+def _exact_coefficients(z, f):
+    from fractions import Fraction as Fr
+
+    def cx(c):
+        return (Fr(float(c.real)), Fr(float(c.imag)))
+
+    def sub(a, b):
+        return (a[0] - b[0], a[1] - b[1])
+
+    def mul(a, b):
+        return (a[0] * b[0] - a[1] * b[1], a[0] * b[1] + a[1] * b[0])
+
+    def div(a, b):
+        d = b[0] * b[0] + b[1] * b[1]
+        return ((a[0] * b[0] + a[1] * b[1]) / d, (a[1] * b[0] - a[0] * b[1]) / d)
+
+    zz = [cx(c) for c in z]
+    g = [cx(c) for c in f]
+    n = len(zz)
+    a = [g[0]]
+    for k in range(1, n):
+        prev = g[k - 1]
+        for j in range(k, n):
+            den = mul(sub(zz[j], zz[k - 1]), g[j])
+            g[j] = (Fr(0), Fr(0)) if den == (0, 0) else div(sub(prev, g[j]), den)
+        a.append(g[k])
+    return np.array([complex(float(c[0]), float(c[1])) for c in a])
+
+
+@pytest.mark.parametrize("n", [13, 16, 20, 24, 32])
+def test_coefficients_match_exact_rational_arithmetic(n):
+    rng = np.random.default_rng(700 + n)
+    z = 1j * np.exp(np.linspace(np.log(0.05), np.log(30.0), n))
+    f = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    exact = _exact_coefficients(z, f)
+    got = op.coefficients(z, f)
+    err = np.abs(got - exact) / np.abs(exact)
+    assert err.max() <= 1e-12

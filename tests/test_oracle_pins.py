@@ -287,3 +287,69 @@ def test_validate_rejects():
     bad = synth.Item(**{**item.__dict__, "tau": -item.tau})
     with pytest.raises(ValueError):
         oc.validate(bad)
+
+
+# ---------------------------------------------------------------------------
+# kappa_F, the amplification of the cosine transform, pinned by hand-derived
+# cases (kappa_F(k) = sum_j |c_kj| ||chi(tau_j)||_F / ||chi(i omega_k)||_F).
+# ---------------------------------------------------------------------------
+
+class _CtOnly:
+    def __init__(self, ct):
+        self.ct = np.asarray(ct, dtype=np.float64)
+
+
+def test_kappa_single_tau_is_one():
+    """One tau point: chi(i w_k) = c_k chi(tau), so kappa = |c_k| ||chi|| / ||c_k chi|| = 1
+    for every nonzero coefficient, whatever the matrix."""
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((1, 7, 7)) + 1j * rng.standard_normal((1, 7, 7))
+    ct = np.array([[0.3], [-2.5], [1e-3]])
+    w = np.stack([ct[k, 0] * x[0] for k in range(3)])
+    kap = oc.kappa_F(_CtOnly(ct), x, w)
+    assert np.allclose(kap, 1.0, rtol=0, atol=1e-15)
+
+
+def test_kappa_two_point_hand_cases():
+    """chi_2 = 2 chi_1 with coefficients (1, -1): chi(i w) = -chi_1 and
+    kappa = (||A|| + 2||A||) / ||A|| = 3.  Two orthogonal unit-norm matrices with
+    coefficients (1, 1): kappa = 2 / sqrt(2).  Coefficients (1, 1) on equal
+    matrices add without cancellation: kappa = 1."""
+    a = np.zeros((4, 4), complex)
+    a[0, 1] = 3.0 + 4.0j                       # ||a||_F = 5
+    b = np.zeros((4, 4), complex)
+    b[2, 3] = 1.0
+    a1 = a / 5.0
+    kap = oc.kappa_F(_CtOnly([[1.0, -1.0]]), np.stack([a, 2 * a]), np.stack([-a]))
+    assert kap[0] == pytest.approx(3.0, abs=1e-15)
+    kap = oc.kappa_F(_CtOnly([[1.0, 1.0]]), np.stack([a1, b]), np.stack([a1 + b]))
+    assert kap[0] == pytest.approx(math.sqrt(2.0), abs=1e-15)
+    kap = oc.kappa_F(_CtOnly([[1.0, 1.0]]), np.stack([a, a]), np.stack([2 * a]))
+    assert kap[0] == pytest.approx(1.0, abs=1e-15)
+
+
+def test_kappa_of_a_build_is_at_least_one():
+    """By the triangle inequality kappa >= 1 for any build; equality needs
+    terms of one sign, which a cosine grid with mixed-sign coefficients and
+    an alternating-free chi(tau) does not give, so the synthetic grid shows a
+    value above one (the stored chi(tau) stack from the oracle itself)."""
+    it = synth.make_item(41, (5, 5, 4), 3, 11, True, 6, x_min=1.0)
+    w, xs = oc.chi_omega(it, return_tau=True)
+    kap = oc.kappa_F(it, xs, w)
+    assert np.all(kap >= 1.0 - 1e-12)
+    assert kap.max() > 1.0
+
+
+def test_planted_kappa_without_absolute_values_is_caught():
+    """Dropping the absolute value of the coefficients turns the (1, -1) hand case
+    into (||A|| - 2||A||) / ||A|| = -1, which the pin above rejects."""
+    a = np.zeros((3, 3), complex)
+    a[1, 2] = 2.0
+
+    def planted(item, xs, w):
+        nt = np.sqrt((np.abs(xs) ** 2).sum(axis=(1, 2)))
+        nw = np.sqrt((np.abs(w) ** 2).sum(axis=(1, 2)))
+        return (item.ct @ nt) / nw
+
+    got = planted(_CtOnly([[1.0, -1.0]]), np.stack([a, 2 * a]), np.stack([-a]))
+    assert got[0] != pytest.approx(3.0)
