@@ -170,6 +170,29 @@ gwchi_status gwchi_chi_build_device(gwchi_ctx *ctx, const gwchi_item *items, int
                                     gwchi_precision prec, void *hip_stream,
                                     gwchi_report *report);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * build as gwchi_chi_build_device (device orbitals and output, host
+ * eigenvalues, grids and plane waves, enqueued on hip_stream, NULL = the
+ * context's stream), with every scratch buffer -- scaled operands, slabs,
+ * chi(G, r'), pencils, chi(tau), ticket counters and launch tables -- carved
+ * from one fixed device array of 96 MiB that each device holds for the life
+ * of the process.  The call allocates no device or pinned host memory (its
+ * planner uses the C++ heap for host-side tables) and captures no graph of
+ * its own; no report and no kappa_F are produced.  The planner narrows the
+ * r' slab and splits the (item, tau) jobs into passes until they fit; when
+ * one job with a 256-column slab does not (grids of about 28^3 and larger, or
+ * very many bands), or the launch tables exceed their 4 MiB region, the call
+ * returns GWCHI_ENOMEM with the sizes in gwchi_last_error.  Every call on one
+ * device shares the array and finds the previous call's contents in it (the
+ * kernels clear what must start at zero); calls that overlap in time on one
+ * device -- from two contexts, or on streams that are not ordered -- race on
+ * it.  Results equal those of gwchi_chi_build_device with the same options
+ * (the same kernels; pass and slab splits do not change the arithmetic). */
+gwchi_status gwchi_chi_build_device_noalloc(gwchi_ctx *ctx, const gwchi_item *items,
+                                            int32_t n_items, gwchi_precision prec,
+                                            void *hip_stream);
+
 /* Time every GEMM tile configuration on these items (host memory, as for
  * gwchi_chi_build; chi_out is not written): each tile runs a warm-up build
  * and a timed one, eagerly, with HIP events around every band-GEMM launch,

@@ -1820,6 +1820,42 @@ gwchi_status gwchi_chi_build_device(gwchi_ctx *ctx, const gwchi_item *items, int
   }
 }
 
+gwchi_status gwchi_chi_build_device_noalloc(gwchi_ctx *ctx, const gwchi_item *items,
+                                            int32_t n_items, gwchi_precision prec,
+                                            void *hip_stream) {
+  if (!ctx) {
+    g_tls_error = "ctx is NULL";
+    return GWCHI_EINVAL;
+  }
+  try {
+    if (prec != GWCHI_FP64 && prec != GWCHI_FP32 && prec != GWCHI_BF16X3) {
+      set_err(ctx, "unknown precision");
+      return GWCHI_EINVAL;
+    }
+    gwchi_status st = validate_items(ctx, items, n_items, false);
+    if (st != GWCHI_OK) return st;
+    if (!ctx->noalloc_scratch) {
+      set_err(ctx, "allocation-free build: fixed scratch unavailable (" + ctx->noalloc_why + ")");
+      return GWCHI_EDEVICE;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t us = reinterpret_cast<hipStream_t>(hip_stream);
+    HIPCHK(hipEventRecord(ctx->ev_in, us));
+    HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->ev_in, 0));
+    st = run_build(ctx, items, n_items, (int)prec, nullptr, true);
+    if (st != GWCHI_OK) return st;
+    HIPCHK(hipEventRecord(ctx->ev_out, ctx->stream));
+    HIPCHK(hipStreamWaitEvent(us, ctx->ev_out, 0));
+    return GWCHI_OK;
+  } catch (const std::bad_alloc &) {
+    set_err(ctx, "host allocation failed");
+    return GWCHI_ENOMEM;
+  } catch (...) {
+    set_err(ctx, "internal error");
+    return GWCHI_EDEVICE;
+  }
+}
+
 gwchi_status gwchi_chi_build(gwchi_ctx *ctx, const gwchi_item *items, int32_t n_items,
                              gwchi_precision prec, gwchi_report *report) {
   if (!ctx) {

@@ -23,7 +23,7 @@ EXPORTS = ["gwchi_create", "gwchi_destroy", "gwchi_set_options", "gwchi_get_opti
            "gwchi_validate", "gwchi_chi_build", "gwchi_chi_build_device", "gwchi_autotune",
            "gwchi_autotune_times", "gwchi_last_error", "gwchi_version", "gwchi_w_build",
            "gwchi_w_build_device", "gwchi_w_validate", "gwchi_pade", "gwchi_pade_device",
-           "gwchi_pade_validate"]
+           "gwchi_pade_validate", "gwchi_chi_build_device_noalloc"]
 
 
 class GwchiItem(C.Structure):
@@ -154,6 +154,8 @@ def load(path: str = LIB_PATH):
     lib.gwchi_chi_build_device.argtypes = [C.c_void_p, P(GwchiItem), C.c_int32, C.c_int,
                                            C.c_void_p, P(GwchiReport)]
     lib.gwchi_autotune.argtypes = [C.c_void_p, P(GwchiItem), C.c_int32, C.c_int]
+    lib.gwchi_chi_build_device_noalloc.argtypes = [C.c_void_p, P(GwchiItem), C.c_int32, C.c_int,
+                                                   C.c_void_p]
     lib.gwchi_autotune_times.argtypes = [C.c_void_p, C.c_int, C.c_int32, P(C.c_double), C.c_int32,
                                          P(C.c_int32)]
     lib.gwchi_w_build.argtypes = [C.c_void_p, P(GwchiWItem), C.c_int32, P(GwchiWReport)]
@@ -169,7 +171,8 @@ def load(path: str = LIB_PATH):
     for f in ("gwchi_create", "gwchi_destroy", "gwchi_set_options", "gwchi_get_options",
               "gwchi_validate", "gwchi_chi_build", "gwchi_chi_build_device", "gwchi_autotune",
               "gwchi_autotune_times", "gwchi_w_build", "gwchi_w_build_device", "gwchi_w_validate",
-              "gwchi_pade", "gwchi_pade_device", "gwchi_pade_validate"):
+              "gwchi_pade", "gwchi_pade_device", "gwchi_pade_validate",
+              "gwchi_chi_build_device_noalloc"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -380,6 +383,22 @@ class Context:
         if st != 0:
             raise self._err(st)
         return rep.as_dict() if report else None
+
+    def build_device_noalloc(self, items: Sequence, phis, outs, prec="fp32", stream=None):
+        """gwchi_chi_build_device_noalloc: as build_device, every scratch buffer
+        in the library's fixed device array (no allocation, no report)."""
+        keep = _Keep()
+        arr = (GwchiItem * len(items))(*[
+            make_item(keep, it, phi_occ=p[0], phi_unocc=p[1], chi_out=o)
+            for it, p, o in zip(items, phis, outs)])
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream()
+        sh = int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream or 0)
+        st = self.lib.gwchi_chi_build_device_noalloc(self.h, arr, len(items), PRECISIONS[prec],
+                                                     C.c_void_p(sh))
+        if st != 0:
+            raise self._err(st)
 
     def autotune(self, items: Sequence, prec="fp32"):
         keep = _Keep()
