@@ -2,9 +2,10 @@
 
 `value` is the effective throughput: the method's algorithmic flops for the
 full r x r' square, 8 N_r^2 (N_occ + N_unocc) per tau, divided by the wall
-time of a build.  With Hermitian completion (the default) the GEMM computes
-only the lower block triangle, so the roofline of the dominant kernel is
-taken on the flops it actually executes.
+time of a build ("value_kind" says so; "executed_tflops" beside it counts the
+flops the band-GEMM tiles actually execute).  With Hermitian completion (the
+default) the GEMM computes only the lower block triangle, so the roofline of
+the dominant kernel is taken on the flops it actually executes.
 
 Workload: the Gamma-only complex configuration -- 24^3 grid, 64 occupied +
 960 unoccupied orbitals, 12 tau/omega points, r' streamed in 2048-column
@@ -75,6 +76,17 @@ def gemm_traffic(kernel_prefix: str, profile: str = TRAFFIC_PROFILE, source: str
     return None
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux /proc/cpuinfo), or "unknown"."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(item, n_tau_sample: int = 1):
     """The oracle (unchanged) on a bounded sample: n_tau_sample tau points of
     the same item through the full space-time path, FP64 on the host."""
@@ -91,6 +103,7 @@ def cpu_baseline(item, n_tau_sample: int = 1):
     dt = time.perf_counter() - t0
     flops = 8.0 * item.n_r ** 2 * (item.n_occ + item.n_unocc) * n_tau_sample
     return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{n_tau_sample} of {item.n_tau} tau points of the same workload "
                       f"(space-time steps 1-4, FP64 NumPy/SciPy), {dt:.1f} s"}
 
@@ -226,6 +239,68 @@ def bench_pade(ctx, item, args):
     return out
 
 
+def bench_batched(args):
+    """The 32-system batch (configuration 5: real orbitals, 16^3-28^3 grids,
+    16/256 .. 96/1536 bands, gaps 0.1-10 eV, 20 taus, one persistent launch per
+    slab over every (system, tau) job) on every path: tiles autotuned on the
+    six 24^3 systems, one warm-up, then two builds timed with per-launch events
+    (GEMM time) and by the wall clock; error against the oracle on sampled rows
+    of one system of every grid size."""
+    import torch
+    from paper_1607_02859_amd import gwchi, synth
+    dev = torch.device("cuda:0")
+    items = synth.make_config(5)
+    phis = [(torch.from_numpy(it.phi_occ).to(dev), torch.from_numpy(it.phi_unocc).to(dev))
+            for it in items]
+    outs = [torch.empty((it.n_omega, it.n_g, it.n_g), dtype=torch.complex128, device=dev)
+            for it in items]
+    alg = sum(synth.algorithmic_flops(it) for it in items)
+    sample = [(0, [0, 5]), (9, [2, 100]), (16, [3, 1700]), (20, [1, 1000]), (31, [7, 4000])]
+    refs = None
+    if not args.no_check:
+        from oracle import chi as oc
+        refs = {t: oc.chi_rows(items[t], rows) for t, rows in sample}
+    ctx = gwchi.Context(0)
+    ctx.set_options(use_graph=1, timing=1, hermitian=1, kappa=0)
+    stream = torch.cuda.current_stream()
+    out = {"config": {"workload": WORKLOADS[5], "items": len(items)}, "paths": {}}
+    for prec in args.precisions.split(","):
+        ctx.autotune([it for it in items if it.n[0] == 24], prec)
+        ctx.build_device(items, phis, outs, prec, stream=stream, report=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = [ctx.build_device(items, phis, outs, prec, stream=stream, report=True)
+                for _ in range(2)]
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / 2
+        gemm_ms = sum(r["ms_gemm"] for r in reps) / 2
+        issued = reps[-1]["mfma_flops"] / (gemm_ms * 1e-3) / 1e12
+        p = {"ms_per_step": 1e3 * wall, "tflops": alg / wall / 1e12, "gemm_ms": gemm_ms,
+             "mfma_tflops_issued": issued, "mfma_frac_of_peak": issued / PEAK_TFLOPS[prec],
+             "phase_ms": {k: sum(r[k] for r in reps) / 2
+                          for k in ("ms_stage", "ms_gemm", "ms_fft_r", "ms_fft_rp", "ms_ct")},
+             "tile_id": reps[-1]["tile_id"]}
+        ctx.set_options(kappa=1)
+        p["kappa_F"] = ctx.build_device(items, phis, outs, prec, stream=stream,
+                                        report=True)["kappa_F_max"]
+        ctx.set_options(kappa=0)
+        if refs is not None:
+            from oracle import chi as oc
+            errs = [oc.rel_frobenius(outs[t].cpu().numpy()[:, rows, :], refs[t])
+                    for t, rows in sample]
+            p["err_vs_oracle_sampled_rows"] = max(errs)
+            p["within_tol"] = bool(max(errs) <= TOL[prec])
+        out["paths"][prec] = p
+        log(f"[bench] batched {prec}: {p['ms_per_step']:.0f} ms/step, {p['tflops']:.1f} TFLOP/s, "
+            f"gemm {issued:.1f} TFLOP/s issued ({100 * p['mfma_frac_of_peak']:.0f}% of peak), "
+            f"kappa_F {p['kappa_F']:.2f}, err {p.get('err_vs_oracle_sampled_rows', float('nan')):.2e}")
+    ctx.close()
+    if "fp64" in out["paths"]:
+        for prec, p in out["paths"].items():
+            p["speedup_vs_fp64"] = out["paths"]["fp64"]["ms_per_step"] / p["ms_per_step"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,12 +327,13 @@ def main():
                     help="time only the continuation (prints one JSON line with the pade object)")
     ap.add_argument("--w-only", action="store_true",
                     help="time only the W~ step (prints one JSON line with the w_tilde object)")
-    ap.add_argument("--autotune", type=int, default=None,
+    ap.add_argument("--autotune", type=int, default=1,
                     help="time every GEMM tile on the workload before the warm-up and use the "
-                         "fastest (default: on for the k-point batch, configuration 3)")
+                         "fastest (default on)")
+    ap.add_argument("--batched", type=int, default=None,
+                    help="also time the 32-system batch (configuration 5) on every path, one "
+                         "warm-up and two timed builds (default: on for configuration 2)")
     args = ap.parse_args()
-    if args.autotune is None:
-        args.autotune = 1 if args.config == 3 else 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is a design note only)", file=sys.stderr)
@@ -373,6 +449,9 @@ def main():
         "metric": METRIC,
         "value": H["tflops"],
         "unit": "TFLOP/s",
+        "value_kind": "effective: full-square algorithmic flops 8 N_r^2 K per tau / build time",
+        "executed_tflops": H["mfma_flops_per_step"] / (H["ms_per_step"] * 1e-3) / 1e12
+        / (3.0 if head == "bf16x3" else 1.0),
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -421,6 +500,12 @@ def main():
     if args.pade:
         res["pade"] = bench_pade(ctx, item, args)
     ctx.close()
+    del phis, outs
+    torch.cuda.empty_cache()
+    if args.batched is None:
+        args.batched = 1 if args.config == 2 else 0
+    if args.batched:
+        res["batched"] = bench_batched(args)
     print(json.dumps(res), flush=True)
 
 
