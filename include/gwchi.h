@@ -323,6 +323,95 @@ gwchi_status gwchi_pade(gwchi_ctx *ctx, const gwchi_pade_item *item, double *ms)
 gwchi_status gwchi_pade_device(gwchi_ctx *ctx, const gwchi_pade_item *item, void *hip_stream,
                                double *ms);
 
+/* ------------------------------------------------------------------------
+ * Correlation self-energy in space and imaginary time (Sec. II.D), diagonal
+ * elements on the imaginary frequency axis, for Gamma-point items with
+ * complex orbitals.  Per item and imaginary time tau_j > 0:
+ *
+ *   W~(r, r')           = sum_{G,G'} exp(+i G.r) W~(G, G', i tau_j) exp(-i G'.r')
+ *                                                   (Eqs. (51)-(52) at k = 0)
+ *   Gbar(r, r', i tau)  = -sum_a phi_a(r) conj(phi_a(r')) exp(-(eps_a - mu) tau)
+ *   Gund(r, r', -i tau) = +sum_i phi_i(r) conj(phi_i(r')) exp(+(eps_i - mu) tau)
+ *                                                   (Eqs. (1)-(2))
+ *   Sigma_bar_nn(i tau)  = -sum_{r,r'} conj(psi_n(r)) Gbar(r,r') W~(r,r') psi_n(r')
+ *   Sigma_und_nn(-i tau) = -sum_{r,r'} conj(psi_n(r)) Gund(r,r') W~(r,r') psi_n(r')
+ *                                                   (Eq. (53); Sigma^(1) of Eqs. (55), (62))
+ *   Sigma^c = (Sigma_bar + Sigma_und) / 2,  Sigma^s = (Sigma_bar - Sigma_und) / 2
+ *                                                   (Eqs. (67)-(68))
+ *   Sigma_nn(i omega_k) = sum_j ct[k][j] Sigma^c_j + i sum_j st[k][j] Sigma^s_j
+ *                                                   (Eqs. (69)-(71))
+ *
+ * W~(i tau) is taken as Hermitian in (G, G') and even in tau (as the W~ step
+ * returns it); then G o W~ is Hermitian in (r, r'), each tau-domain element is
+ * real, and the library forms only the lower triangle r >= r' of the
+ * products.  No 1/N_r or volume factor.  The band contractions run in the
+ * requested precision (FP32 and split-BF16 as for the polarizability, with
+ * W~(r, r') and the matrix-element sums of each tile in FP32); the weights,
+ * the sums over tiles and the transforms are FP64 on every path.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t n[3];             /* FFT grid, as gwchi_item                                     */
+  int32_t is_complex;       /* must be 1 (real orbitals: ENOTSUP)                          */
+  int32_t n_occ, n_unocc;   /* >= 1 each                                                   */
+  /* orbitals, band-major complex FP64 as gwchi_item; gwchi_sigma_build: host,
+   * gwchi_sigma_build_device: device memory */
+  const double *phi_occ;
+  const double *phi_unocc;
+  const double *eps_occ;    /* [n_occ]   eV, host                                          */
+  const double *eps_unocc;  /* [n_unocc] eV, host                                          */
+  double mu;                /* strictly inside the gap                                     */
+  int32_t n_tau, n_omega;   /* >= 1 each                                                   */
+  const double *tau;        /* [n_tau] > 0, host                                           */
+  const double *ct;         /* [n_omega][n_tau] gamma_kj cos(omega_k tau_j) (Eq. (4)), host  */
+  const double *st;         /* [n_omega][n_tau] lambda_kj sin(omega_k tau_j) (Eq. (7)), host */
+  int32_t n_g;              /* >= 1 */
+  const int32_t *g_index;   /* [n_g] distinct flat FFT indices, host                       */
+  /* W~(G, G', i tau_j), [n_tau][n_g][n_g] complex FP64 (row G, column G', the
+   * layout of gwchi_w_item.w_tau_out); same memory kind as the orbitals */
+  const double *w_tau;
+  int32_t n_states;         /* in [1, 1024]                                                */
+  const int32_t *states;    /* [n_states] host: b < n_occ is occupied band b, otherwise
+                               unoccupied band b - n_occ (input order, as the orbitals)  */
+  /* Outputs, same memory kind as the orbitals: sigma_out [n_states][n_omega]
+   * complex interleaved (Sigma_nn(i omega_k)); sigma_tau_out [n_states][n_tau][2]
+   * real (Sigma_und(-i tau_j), Sigma_bar(i tau_j)) or NULL */
+  double *sigma_out;
+  double *sigma_tau_out;
+} gwchi_sigma_item;
+
+typedef struct {
+  double ms_total;          /* stream time of the whole call                           */
+  double ms_stage;          /* weights, scaled operands and the states                 */
+  double ms_fft;            /* W~(G, G') -> W~(r, r'), both transforms                 */
+  double ms_gemm;           /* fused band contractions, products and matrix elements   */
+  double ms_final;          /* sums over tiles, even/odd parts, cosine and sine        */
+  int32_t n_gemm_launches;
+  int32_t slab_width;
+  int32_t tau_batch;        /* (item, tau) jobs per pass                               */
+  double alg_flops;         /* 8 N_r^2 K per tau (the two Green's functions), summed   */
+  double mfma_flops;        /* flops issued on MFMA by the band contractions           */
+} gwchi_sigma_report;
+
+/* Host-only check (no device is touched): the EINVAL cases of gwchi_validate
+ * for the shared fields (orbitals checked when check_orbitals != 0), plus NULL
+ * st / w_tau / states / sigma_out, non-finite st, n_states outside [1, 1024],
+ * a state index outside [0, n_occ + n_unocc); ENOTSUP for real orbitals and
+ * for the grid sizes gwchi_validate refuses. */
+gwchi_status gwchi_sigma_validate(const gwchi_sigma_item *items, int32_t n_items,
+                                  int32_t check_orbitals);
+
+/* Diagonal self-energies for every item; host buffers in and out; blocking.
+ * report may be NULL. */
+gwchi_status gwchi_sigma_build(gwchi_ctx *ctx, const gwchi_sigma_item *items, int32_t n_items,
+                               gwchi_precision prec, gwchi_sigma_report *report);
+
+/* Same with phi_occ, phi_unocc, w_tau, sigma_out and sigma_tau_out in device
+ * memory; enqueued on hip_stream (NULL = the context's stream); returns once
+ * enqueued unless report is non-NULL (then it waits and fills the report). */
+gwchi_status gwchi_sigma_build_device(gwchi_ctx *ctx, const gwchi_sigma_item *items,
+                                      int32_t n_items, gwchi_precision prec, void *hip_stream,
+                                      gwchi_sigma_report *report);
+
 /* Message of the last failure on this context (never NULL). */
 const char *gwchi_last_error(const gwchi_ctx *ctx);
 

@@ -55,7 +55,7 @@ import os
 import numpy as np
 import scipy.fft as sfft
 
-__all__ = ["validate", "weights", "w_real_space_rows", "sigma_tau", "sigma_omega",
+__all__ = ["validate", "weights", "w_first_index", "w_real_space_rows", "sigma_tau", "sigma_omega",
            "sigma_from_tau", "sigma_pairsum_tau", "sigma_laplace", "state_orbitals",
            "rel_l2"]
 
@@ -97,18 +97,28 @@ def state_orbitals(item):
     return phi[np.asarray(item.states, dtype=np.int64)]
 
 
-def w_real_space_rows(item, j, rows):
-    """Step 1: W~(r, r', i tau_j) for the grid points r in ``rows`` and every
-    r', shape (len(rows), N_r)."""
+def w_first_index(item, j):
+    """Step 1, first transform: W~(r, G', i tau_j) = sum_G exp(+i G.r) W~(G, G'),
+    shape (N_r, n_g)."""
     n0, n1, n2 = (int(v) for v in item.n)
     n_r = n0 * n1 * n2
     g = np.asarray(item.g_index, dtype=np.int64)
-    w = np.asarray(item.w_tau[j], dtype=np.complex128)
-    # W~(r, G') = sum_G exp(+i G.r) W~(G, G'): scatter each column, N_r * inverse DFT
     cube = np.zeros((n_r, g.size), dtype=np.complex128)
-    cube[g, :] = w
-    w_rg = sfft.ifftn(cube.reshape(n0, n1, n2, g.size), axes=(0, 1, 2),
+    cube[g, :] = np.asarray(item.w_tau[j], dtype=np.complex128)
+    # scatter each column onto the grid, N_r * inverse DFT
+    return sfft.ifftn(cube.reshape(n0, n1, n2, g.size), axes=(0, 1, 2),
                       workers=_WORKERS).reshape(n_r, g.size) * n_r
+
+
+def w_real_space_rows(item, j, rows, w_rg=None):
+    """Step 1: W~(r, r', i tau_j) for the grid points r in ``rows`` and every
+    r', shape (len(rows), N_r); ``w_rg`` is the first transform when already
+    computed."""
+    n0, n1, n2 = (int(v) for v in item.n)
+    n_r = n0 * n1 * n2
+    g = np.asarray(item.g_index, dtype=np.int64)
+    if w_rg is None:
+        w_rg = w_first_index(item, j)
     # W~(r, r') = sum_G' W~(r, G') exp(-i G'.r'): scatter each row, forward DFT
     sel = w_rg[np.asarray(rows, dtype=np.int64)]
     cube = np.zeros((sel.shape[0], n_r), dtype=np.complex128)
@@ -129,9 +139,10 @@ def sigma_tau(item, j, block=1024):
     psi = state_orbitals(item)                       # (n_s, N_r)
     s_und = np.zeros(psi.shape[0], dtype=np.complex128)
     s_bar = np.zeros(psi.shape[0], dtype=np.complex128)
+    w_rg = w_first_index(item, j)
     for r0 in range(0, n_r, block):
         rows = np.arange(r0, min(n_r, r0 + block))
-        wt = w_real_space_rows(item, j, rows)                       # W~(r in block, r')
+        wt = w_real_space_rows(item, j, rows, w_rg)                 # W~(r in block, r')
         g_und = (phi_o[:, rows].T * w_o[None, :]) @ phi_o.conj()    # Gund(r, r', -i tau)
         g_bar = -(phi_u[:, rows].T * w_u[None, :]) @ phi_u.conj()   # Gbar(r, r', i tau)
         sig_und = -g_und * wt                                       # step 3

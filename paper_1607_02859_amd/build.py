@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgwchi.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["k_stage.hip", "k_gemm.hip", "k_fft.hip", "k_ct.hip", "k_w.hip", "k_pade.hip", "gwchi_runtime.cpp"]
+SOURCES = ["k_stage.hip", "k_gemm.hip", "k_fft.hip", "k_ct.hip", "k_w.hip", "k_pade.hip", "k_sigma.hip",
+           "gwchi_runtime.cpp"]
 
 
 def hipcc() -> str:

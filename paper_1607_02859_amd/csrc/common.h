@@ -81,7 +81,14 @@ struct GemmJob {
   int32_t n_r;
   int32_t s0, w;            // slab column range [s0, s0 + w)
   int32_t cg_shift;         // slab columns are grouped by 2^cg_shift
-  void *slab;               // [w / 2^cg_shift][n_r][2^cg_shift] output
+  void *slab;               // [w / 2^cg_shift][n_r][2^cg_shift]: chi out (polarizability),
+                            // W~(r, r') in (self-energy), complex working precision
+  // self-energy only: the states psi_n [n_states][ld_states] (complex working
+  // precision) and this job's partial sums, [slot][n_states][2] (occupied,
+  // unoccupied), the slot being the fourth field of a unit
+  const void *states;
+  int32_t n_states, ld_states;
+  double *part;
 };
 
 // Work queues of a persistent launch: units [q_off[q], q_off[q + 1]) form
@@ -154,6 +161,55 @@ struct CtLaunch {
   int32_t n_tiles;          // sum over items of the output tiles
 };
 
+// ---------------------------------------------------------------------------
+// Sphere-to-grid FFT (the self-energy's W~(G, G') -> W~(r, r')), two launches:
+//   pencils: per (pencil d, 256 columns), the sphere points of the pencil
+//            along k0 (zero elsewhere), transformed along axis 0 into tmp;
+//   planes : per block of `cols` columns x `planes` i0-planes, the pencils
+//            placed in their (k1, k2) plane (zero elsewhere), transformed
+//            along axes 1 and 2, every grid point written to out.
+// ---------------------------------------------------------------------------
+struct SfftJob {
+  const void *in;           // element (slot s, column c) at in[s * i_slot + (col0 + c) * i_col]
+  int64_t i_slot, i_col;
+  void *tmp;                // pencils [(i0 * n_disk + d) * n_cols + c]
+  void *out;                // o_shift >= 0: column-grouped [c >> o_shift][n_r][1 << o_shift];
+  int64_t o_col;            // o_shift < 0: out[c * o_col + r]
+  int32_t o_shift;
+  int32_t col0, n_cols, geo;
+  int32_t unit0_pencils, unit0_planes;
+};
+
+struct SfftLaunch {
+  const SfftJob *jobs;
+  int32_t n_jobs;
+  const Geo *geos;
+  int32_t n_units_pencils, n_units_planes;
+  int32_t in_f64;           // input complex FP64 (else the working precision)
+  int32_t conj_in;          // read the complex conjugate of each input element
+};
+
+// ---------------------------------------------------------------------------
+// Self-energy reductions: per (job, state) the partial sums of the tiles, in
+// slot order, into sums; then per item the tau-domain elements and the cosine
+// and sine transforms.
+// ---------------------------------------------------------------------------
+struct SigmaRed {
+  const double *part;       // [n_slots][n_states][2]
+  int32_t n_slots, n_states;
+  double *sum;              // sum[n * sum_stride + {0, 1}]
+  int32_t sum_stride;
+};
+
+struct SigmaFin {
+  const double *sum;        // [n_states][n_tau][2] quadratic forms of the edge-scaled G
+  const double *ct, *st;    // [n_omega][n_tau]
+  const double *edge_o, *edge_u;   // [n_tau] exp((HOMO - mu) tau_j), exp(-(LUMO - mu) tau_j)
+  int32_t n_states, n_tau, n_omega;
+  double *out;              // [n_states][n_omega] complex
+  double *out_tau;          // [n_states][n_tau][2] (Sigma_und(-i tau), Sigma_bar(i tau)) or null
+};
+
 // Host-side launch wrappers (defined in the .hip files).
 hipError_t launch_stage(const StageLaunch &L, int prec, hipStream_t s);
 // grid <= 0: persistent (resident blocks x num_cu)
@@ -167,6 +223,22 @@ int gemm_tile_kc(int prec, int cplx, int tile);
 const char *gemm_tile_name(int prec, int cplx, int tile);
 hipError_t launch_fft(const FftLaunch &L, int dbl, int sign, int lds_bytes, int cubic_n,
                       hipStream_t s);
+// sphere-to-grid transform; lds_bytes as fft_lds_bytes + 4 * n_disk for the block shape
+hipError_t launch_sfft(const SfftLaunch &L, int dbl, int sign, int lds_bytes, hipStream_t s);
+// self-energy: fused band contractions, products with W~ and the diagonal
+// matrix elements (one tile shape per precision, complex orbitals)
+hipError_t launch_gemm_sigma(const GemmLaunch &L, int prec, int grid, int num_cu, hipStream_t s);
+int gemm_sigma_bm(int prec);
+int gemm_sigma_bn(int prec);
+int gemm_sigma_kc(int prec);
+int gemm_sigma_per_cu(int prec);
+// states psi_n in the working precision: out[n][r] for r < n_r_pad (zero past n_r)
+hipError_t launch_sigma_states(const double *phi_o, const double *phi_u, const int32_t *states,
+                               int n_states, int n_occ, int n_r, int n_r_pad, int dbl, void *out,
+                               hipStream_t s);
+hipError_t launch_sigma_reduce(const SigmaRed *jobs, int n_jobs, int max_states, hipStream_t s);
+hipError_t launch_sigma_final(const SigmaFin *items, int n_items, int max_states, int max_omega,
+                              hipStream_t s);
 
 // Plane-FFT block shape, shared by the planner and the kernels: runs of
 // 128 bytes of adjacent columns, about 256 line transforms per step, at most

@@ -159,6 +159,9 @@ struct gwchi_ctx {
   // being inverted, the pivot-block panels, the per-item tables, the pivot flag
   DevBuf b_wchi, b_wtau, b_womega, b_wa, b_wdinv, b_wrp, b_wcp, b_wtab, b_wflag;
   HostPinned h_wtab;
+  // self-energy: states operands, per-(state, tau) sums, host-entry copies of
+  // W~ and of the outputs
+  DevBuf b_sstates, b_ssum, b_sw, b_sout, b_stau;
   // analytic continuation: host-entry copies of f / out / coef, the points z and w
   DevBuf b_pf, b_pout, b_pcoef, b_ptab;
   HostPinned h_ptab;
@@ -347,8 +350,11 @@ std::string tune_key(const gwchi_ctx *ctx, int prec, int cplx) {
 
 // arena_bytes > 0: the plan's buffers must fit in that many bytes of fixed
 // scratch (the allocation-free entry); otherwise the context's budget applies.
+// sigma_states > 0: plan a self-energy call (its own tile per precision; the
+// slab holds complex W~(r, r') in groups of 128 bytes; the fifth buffer holds
+// the per-tile partial sums of at most sigma_states states).
 gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int prec,
-                        Plan &P, int64_t arena_bytes = 0) {
+                        Plan &P, int64_t arena_bytes = 0, int sigma_states = 0) {
   P = Plan();
   P.prec = prec;
   // all items of one call use one (precision, complexity) tile family; items that mix
@@ -375,6 +381,12 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
   P.bm = gemm_tile_bm(prec, cplx, tile);
   P.bn = gemm_tile_bn(prec, cplx, tile);
   P.kc = gemm_tile_kc(prec, cplx, tile);
+  if (sigma_states > 0) {
+    P.tile = 0;
+    P.bm = gemm_sigma_bm(prec);
+    P.bn = gemm_sigma_bn(prec);
+    P.kc = gemm_sigma_kc(prec);
+  }
 
   const int ec = elem_c(prec);
   const int es = elem_slab(prec, cplx);
@@ -452,7 +464,7 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
   }
   // jobs, with optional exact-zero band truncation
   const double thr = std::ldexp(1.0, -152);
-  const bool skip = ctx->opt.skip_zero_bands && prec != P_FP64;
+  const bool skip = ctx->opt.skip_zero_bands && prec != P_FP64 && sigma_states == 0;
   for (int t = 0; t < n_items; ++t) {
     ItemPlan &I = P.items[t];
     I.job0 = (int)P.jobs.size();
@@ -494,10 +506,17 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
     auto sizes = [&](const ItemPlan &I, int64_t *b) {
       const int64_t wmax = std::min<int64_t>(W, I.n_r);
       b[0] = round_up(I.n_r_pad * (I.k_o_pad + I.k_u_pad) * bpb, 256);
-      b[1] = round_up(round_up(wmax, I.cols) * I.n_r * es, 256);
+      b[1] = sigma_states > 0 ? round_up(round_up(wmax, 128 / ec) * I.n_r * ec, 256)
+                              : round_up(round_up(wmax, I.cols) * I.n_r * es, 256);
       b[2] = round_up((int64_t)I.n_g * I.n_r * ec, 256);
       b[3] = round_up((int64_t)I.n0 * I.n_disk * std::max<int64_t>(wmax, I.n_g) * ec, 256);
       b[4] = (int64_t)I.n_g * I.n_g * ec;
+      if (sigma_states > 0) {
+        // tiles of one job over every slab, bounded by the full square
+        const int64_t nrt = (I.n_r + P.bm - 1) / P.bm;
+        const int64_t nct = (I.n_r + P.bn - 1) / P.bn + (I.n_r + W - 1) / W;
+        b[4] = round_up(nrt * nct * sigma_states * 16, 256);
+      }
     };
     bool ok = true;
     P.pass_begin.assign(1, 0);
@@ -643,6 +662,67 @@ void emit_fft(Built &B, const Plan &P, std::vector<FftJob> &jobs, int phase, int
   }
 }
 
+// The staging launch of jobs [jb, je) of a pass: one op per (item, occ|unocc)
+// over all of the item's taus in the pass, blocks of 64 grid points x 32 bands.
+// Table pointers are blob offsets (patched later); off_* are the per-item
+// offsets of the band permutations and sorted eigenvalues.
+StageLaunch make_stage(Blob &blob, const Plan &P, int jb, int je, char *psi_base,
+                       const std::vector<size_t> &off_perm_o, const std::vector<size_t> &off_perm_u,
+                       const std::vector<size_t> &off_eps_o, const std::vector<size_t> &off_eps_u) {
+  const int cplx = P.cplx_any;
+  std::vector<StageOp> ops;
+  std::vector<int4> blocks;
+  std::vector<std::vector<void *>> psi_lists;
+  std::vector<std::vector<double>> tau_lists;
+  int jj = jb;
+  while (jj < je) {
+    const int t = P.jobs[jj].item;
+    int je2 = jj;
+    while (je2 < je && P.jobs[je2].item == t) ++je2;
+    const ItemPlan &I = P.items[t];
+    for (int side = 0; side < 2; ++side) {
+      StageOp op{};
+      op.phi = side == 0 ? I.phi_o : I.phi_u;
+      op.perm = reinterpret_cast<const int32_t *>(side == 0 ? off_perm_o[t] : off_perm_u[t]);
+      op.eps = reinterpret_cast<const double *>(side == 0 ? off_eps_o[t] : off_eps_u[t]);
+      op.edge = side == 0 ? I.homo : I.lumo;
+      op.sign = side == 0 ? 1.0 : -1.0;
+      op.k = side == 0 ? I.k_o : I.k_u;
+      op.k_pad = side == 0 ? I.k_o_pad : I.k_u_pad;
+      op.n_r = (int32_t)I.n_r;
+      op.n_r_pad = (int32_t)I.n_r_pad;
+      op.cplx = I.cplx;
+      op.n_jobs = je2 - jj;
+      std::vector<void *> pl;
+      std::vector<double> tl;
+      for (int q = jj; q < je2; ++q) {
+        char *slot = psi_base + P.jobs[q].o_psi;
+        const int64_t o_bytes = I.n_r_pad * I.k_o_pad * bpb_of(P.prec, cplx);
+        pl.push_back(side == 0 ? slot : slot + o_bytes);
+        tl.push_back(I.tau[P.jobs[q].j]);
+      }
+      psi_lists.push_back(pl);
+      tau_lists.push_back(tl);
+      const int opi = (int)ops.size();
+      ops.push_back(op);
+      const int rt = (int)(I.n_r_pad / 64), kt = op.k_pad / 32;
+      for (int a = 0; a < rt; ++a)
+        for (int b = 0; b < kt; ++b) blocks.push_back(make_int4(opi, a, b, 0));
+    }
+    jj = je2;
+  }
+  for (size_t i = 0; i < ops.size(); ++i) {
+    ops[i].tau = reinterpret_cast<const double *>(blob.addv(tau_lists[i]));
+    ops[i].psi = reinterpret_cast<void *const *>(blob.addv(psi_lists[i]));
+  }
+  StageLaunch S{};
+  S.ops = reinterpret_cast<const StageOp *>(blob.addv(ops));
+  S.blocks = reinterpret_cast<const int4 *>(blob.addv(blocks));
+  S.n_blocks = (int)blocks.size();
+  S.prec = P.prec;
+  return S;
+}
+
 // Build every launch descriptor.  Pointers into the blob are stored as offsets
 // and patched by patch_blob once the device address of the blob is known.
 void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, const Bases &D, Built &B) {
@@ -725,58 +805,11 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, const Bases &D, Bu
     const int jb = P.pass_begin[ps], je = P.pass_begin[ps + 1];
     // ---- stage: one op per (item in pass, occ|unocc)
     {
-      std::vector<StageOp> ops;
-      std::vector<int4> blocks;
-      std::vector<std::vector<void *>> psi_lists;
-      std::vector<std::vector<double>> tau_lists;
-      int jj = jb;
-      while (jj < je) {
-        const int t = P.jobs[jj].item;
-        int je2 = jj;
-        while (je2 < je && P.jobs[je2].item == t) ++je2;
-        const ItemPlan &I = P.items[t];
-        for (int side = 0; side < 2; ++side) {
-          StageOp op{};
-          op.phi = side == 0 ? I.phi_o : I.phi_u;
-          op.perm = reinterpret_cast<const int32_t *>(side == 0 ? off_perm_o[t] : off_perm_u[t]);
-          op.eps = reinterpret_cast<const double *>(side == 0 ? off_eps_o[t] : off_eps_u[t]);
-          op.edge = side == 0 ? I.homo : I.lumo;
-          op.sign = side == 0 ? 1.0 : -1.0;
-          op.k = side == 0 ? I.k_o : I.k_u;
-          op.k_pad = side == 0 ? I.k_o_pad : I.k_u_pad;
-          op.n_r = (int32_t)I.n_r;
-          op.n_r_pad = (int32_t)I.n_r_pad;
-          op.cplx = I.cplx;
-          op.n_jobs = je2 - jj;
-          std::vector<void *> pl;
-          std::vector<double> tl;
-          for (int q = jj; q < je2; ++q) {
-            char *slot = psi_base + P.jobs[q].o_psi;
-            const int64_t o_bytes = I.n_r_pad * I.k_o_pad * bpb_of(P.prec, cplx);
-            pl.push_back(side == 0 ? slot : slot + o_bytes);
-            tl.push_back(I.tau[P.jobs[q].j]);
-          }
-          psi_lists.push_back(pl);
-          tau_lists.push_back(tl);
-          const int opi = (int)ops.size();
-          ops.push_back(op);
-          const int rt = (int)(I.n_r_pad / 64), kt = op.k_pad / 32;
-          for (int a = 0; a < rt; ++a)
-            for (int b = 0; b < kt; ++b) blocks.push_back(make_int4(opi, a, b, 0));
-        }
-        jj = je2;
-      }
-      for (size_t i = 0; i < ops.size(); ++i) {
-        ops[i].tau = reinterpret_cast<const double *>(B.blob.addv(tau_lists[i]));
-        ops[i].psi = reinterpret_cast<void *const *>(B.blob.addv(psi_lists[i]));
-      }
       Launch L{};
       L.phase = PH_STAGE;
       L.kind = 0;
-      L.stage.ops = reinterpret_cast<const StageOp *>(B.blob.addv(ops));
-      L.stage.blocks = reinterpret_cast<const int4 *>(B.blob.addv(blocks));
-      L.stage.n_blocks = (int)blocks.size();
-      L.stage.prec = P.prec;
+      L.stage = make_stage(B.blob, P, jb, je, psi_base, off_perm_o, off_perm_u, off_eps_o,
+                           off_eps_u);
       B.launches.push_back(L);
     }
     // ---- per slab: gemm + fft over r
@@ -1004,24 +1037,27 @@ T *dev(const char *base, const T *off) {
   return reinterpret_cast<T *>(const_cast<char *>(base) + reinterpret_cast<uintptr_t>(off));
 }
 
+void patch_stage(StageLaunch &S, char *h, const char *base) {
+  StageOp *ops = reinterpret_cast<StageOp *>(h + reinterpret_cast<uintptr_t>(S.ops));
+  // the op count is implied by the blocks: walk the ops the blocks reference
+  const int4 *blk = reinterpret_cast<const int4 *>(h + reinterpret_cast<uintptr_t>(S.blocks));
+  int n_ops = 0;
+  for (int i = 0; i < S.n_blocks; ++i) n_ops = std::max(n_ops, blk[i].x + 1);
+  for (int i = 0; i < n_ops; ++i) {
+    ops[i].perm = dev(base, ops[i].perm);
+    ops[i].eps = dev(base, ops[i].eps);
+    ops[i].tau = dev(base, ops[i].tau);
+    ops[i].psi = dev(base, ops[i].psi);
+  }
+  S.ops = dev(base, S.ops);
+  S.blocks = dev(base, S.blocks);
+}
+
 void patch_blob(Built &B, const char *base) {
   char *h = B.blob.h.data();
   for (auto &L : B.launches) {
     if (L.kind == 0) {
-      StageOp *ops = reinterpret_cast<StageOp *>(h + reinterpret_cast<uintptr_t>(L.stage.ops));
-      for (int i = 0; i < L.stage.n_blocks; ++i) (void)i;
-      // ops count is implied by the blocks; walk the ops referenced by blocks
-      const int4 *blk = reinterpret_cast<const int4 *>(h + reinterpret_cast<uintptr_t>(L.stage.blocks));
-      int n_ops = 0;
-      for (int i = 0; i < L.stage.n_blocks; ++i) n_ops = std::max(n_ops, blk[i].x + 1);
-      for (int i = 0; i < n_ops; ++i) {
-        ops[i].perm = dev(base, ops[i].perm);
-        ops[i].eps = dev(base, ops[i].eps);
-        ops[i].tau = dev(base, ops[i].tau);
-        ops[i].psi = dev(base, ops[i].psi);
-      }
-      L.stage.ops = dev(base, L.stage.ops);
-      L.stage.blocks = dev(base, L.stage.blocks);
+      patch_stage(L.stage, h, base);
     } else if (L.kind == 1) {
       L.gemm.jobs = dev(base, L.gemm.jobs);
       L.gemm.units = dev(base, L.gemm.units);
@@ -1041,8 +1077,8 @@ void patch_blob(Built &B, const char *base) {
   }
 }
 
-void patch_geos(Built &B, const char *base, size_t off_geos, int n_items) {
-  Geo *g = reinterpret_cast<Geo *>(B.blob.h.data() + off_geos);
+void patch_geos(Blob &blob, const char *base, size_t off_geos, int n_items) {
+  Geo *g = reinterpret_cast<Geo *>(blob.h.data() + off_geos);
   for (int i = 0; i < n_items; ++i) {
     g[i].disk_i12 = dev(base, g[i].disk_i12);
     g[i].slot_of = dev(base, g[i].slot_of);
@@ -1182,7 +1218,7 @@ gwchi_status run_build(gwchi_ctx *ctx, const gwchi_item *items, int n_items, int
     HIPCHK(ctx->b_tables.ensure(B.blob.h.size() + 64, &moved));
     D.tables = reinterpret_cast<char *>(ctx->b_tables.p);
   }
-  patch_geos(B, D.tables, off_geos, n_items);
+  patch_geos(B.blob, D.tables, off_geos, n_items);
   patch_blob(B, D.tables);
   if (noalloc) {
     // the host copy lives in the context until the next build (which first
@@ -1601,6 +1637,529 @@ gwchi_status run_w(gwchi_ctx *ctx, const gwchi_w_item *items, int n_items,
 }
 
 // ---------------------------------------------------------------------------
+// Self-energy (Sec. II.D): diagonal elements on the imaginary axis.
+//
+// One call is planned like a polarizability build (jobs = (item, tau_j),
+// passes sized to the device budget, r' slabs).  Per pass:
+//   stage (weights, scaled operands)                      - all jobs
+//   W~(G, G') -> W~(G, r') (sphere-to-grid over G')       - all jobs
+//   for every r' slab: W~(G, r') -> W~(r, r'), then the fused band GEMM with
+//   the products and the matrix elements                  - one launch each
+//   sums over the tiles per (job, state)                  - one launch
+// and after the last pass one launch for the even/odd parts and transforms.
+// ---------------------------------------------------------------------------
+
+constexpr int kSigmaMaxStates = 1024;
+enum SPhase { SP_STAGE = 0, SP_FFT, SP_GEMM, SP_FINAL, SP_COUNT };
+
+// The fields a self-energy item shares with a polarizability item, for the
+// shared validation and planner (sigma_out stands in for chi_out; it is
+// never written through this copy).
+gwchi_item sigma_as_item(const gwchi_sigma_item &s) {
+  gwchi_item it{};
+  for (int d = 0; d < 3; ++d) it.n[d] = s.n[d];
+  it.is_complex = s.is_complex;
+  it.n_occ = s.n_occ;
+  it.n_unocc = s.n_unocc;
+  it.phi_occ = s.phi_occ;
+  it.phi_unocc = s.phi_unocc;
+  it.eps_occ = s.eps_occ;
+  it.eps_unocc = s.eps_unocc;
+  it.mu = s.mu;
+  it.n_tau = s.n_tau;
+  it.n_omega = s.n_omega;
+  it.tau = s.tau;
+  it.ct = s.ct;
+  it.n_g = s.n_g;
+  it.g_index = s.g_index;
+  it.chi_out = s.sigma_out;
+  return it;
+}
+
+gwchi_status validate_sigma_items(gwchi_ctx *ctx, const gwchi_sigma_item *items, int32_t n_items,
+                                  bool check_orbitals) {
+  if (!items || n_items < 1) {
+    set_err(ctx, "items is NULL or n_items < 1");
+    return GWCHI_EINVAL;
+  }
+  std::vector<gwchi_item> conv(n_items);
+  for (int t = 0; t < n_items; ++t) {
+    const gwchi_sigma_item &it = items[t];
+    const std::string pre = "sigma item " + std::to_string(t) + ": ";
+    if (!it.st || !it.w_tau || !it.states || !it.sigma_out) {
+      set_err(ctx, pre + "st, w_tau, states and sigma_out must not be NULL");
+      return GWCHI_EINVAL;
+    }
+    if (it.is_complex == 0) {
+      set_err(ctx, pre + "real orbitals are not supported by the self-energy step");
+      return GWCHI_ENOTSUP;
+    }
+    if (it.n_states < 1 || it.n_states > kSigmaMaxStates) {
+      set_err(ctx, pre + "n_states must be in [1, " + std::to_string(kSigmaMaxStates) + "]");
+      return GWCHI_EINVAL;
+    }
+    conv[t] = sigma_as_item(it);
+  }
+  gwchi_status st = validate_items(ctx, conv.data(), n_items, check_orbitals);
+  if (st != GWCHI_OK) return st;
+  for (int t = 0; t < n_items; ++t) {
+    const gwchi_sigma_item &it = items[t];
+    const std::string pre = "sigma item " + std::to_string(t) + ": ";
+    if (!finite_all(it.st, (int64_t)it.n_tau * it.n_omega)) {
+      set_err(ctx, pre + "st is not finite");
+      return GWCHI_EINVAL;
+    }
+    for (int k = 0; k < it.n_states; ++k)
+      if (it.states[k] < 0 || it.states[k] >= it.n_occ + it.n_unocc) {
+        set_err(ctx, pre + "state index out of range");
+        return GWCHI_EINVAL;
+      }
+  }
+  return GWCHI_OK;
+}
+
+struct SLaunch {
+  int phase = 0;
+  int kind = 0;   // 0 stage, 5 fill, 6 states, 7 sphere-to-grid FFT, 8 GEMM, 9 reduce, 10 final
+  StageLaunch stage{};
+  SfftLaunch sfft{};
+  int sign = 0;
+  GemmLaunch gemm{};
+  const double *phi_o = nullptr, *phi_u = nullptr;
+  const int32_t *states = nullptr;
+  int n_states = 0, n_occ = 0, n_r = 0, n_r_pad = 0;
+  void *out = nullptr;
+  const SigmaRed *red = nullptr;
+  const SigmaFin *fin = nullptr;
+  int n = 0, max_states = 0, max_omega = 0;
+  void *fill_ptr = nullptr;
+  int64_t fill_bytes = 0;
+};
+
+// Unit counts of a sphere-to-grid launch: job prefix offsets and totals.
+void sfft_units(std::vector<SfftJob> &jobs, const std::vector<Geo> &geos, SfftLaunch &L) {
+  int up = 0, un = 0;
+  for (auto &j : jobs) {
+    const Geo &g = geos[j.geo];
+    j.unit0_pencils = un;
+    j.unit0_planes = up;
+    un += g.n_disk * ((j.n_cols + 255) / 256);
+    up += ((j.n_cols + g.cols - 1) / g.cols) * ((g.n0 + g.planes - 1) / g.planes);
+  }
+  L.n_units_pencils = un;
+  L.n_units_planes = up;
+}
+
+gwchi_status run_sigma(gwchi_ctx *ctx, const gwchi_sigma_item *items, int n_items, int prec,
+                       gwchi_sigma_report *rep) {
+  std::vector<gwchi_item> conv(n_items);
+  int max_states = 0, max_omega = 0;
+  for (int t = 0; t < n_items; ++t) {
+    conv[t] = sigma_as_item(items[t]);
+    max_states = std::max(max_states, items[t].n_states);
+    max_omega = std::max(max_omega, items[t].n_omega);
+  }
+  Plan P;
+  gwchi_status st = build_plan(ctx, conv.data(), n_items, prec, P, 0, max_states);
+  if (st != GWCHI_OK) return st;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  {
+    DevBuf *bufs[5] = {&ctx->b_psi, &ctx->b_slab, &ctx->b_xr, &ctx->b_tmp, &ctx->b_x};
+    const int64_t need[5] = {P.psi_bytes, P.slab_bytes, P.xr_bytes, P.tmp_bytes, P.x_bytes};
+    bool grow = false;
+    for (int k = 0; k < 5; ++k) grow |= (size_t)need[k] > bufs[k]->n;
+    if (grow) {
+      for (int k = 0; k < 5; ++k) bufs[k]->release();
+      for (int k = 0; k < 5; ++k) HIPCHK(bufs[k]->ensure((size_t)need[k], nullptr));
+    }
+  }
+  const int ec = elem_c(prec);
+  const int dbl = prec == P_FP64 ? 1 : 0;
+  const int sh = ec == 16 ? 3 : 4;           // W~ slab columns in groups of 128 bytes
+  std::vector<int64_t> st_off(n_items), sum_off(n_items);
+  int64_t st_bytes = 0, sum_n = 0;
+  for (int t = 0; t < n_items; ++t) {
+    st_off[t] = st_bytes;
+    st_bytes += round_up((int64_t)items[t].n_states * P.items[t].n_r_pad * ec, 256);
+    sum_off[t] = sum_n;
+    sum_n += (int64_t)items[t].n_states * items[t].n_tau * 2;
+  }
+  HIPCHK(ctx->b_sstates.ensure((size_t)st_bytes + 256, nullptr));
+  HIPCHK(ctx->b_ssum.ensure((size_t)sum_n * 8 + 64, nullptr));
+  int max_slabs = 0;
+  for (auto &I : P.items) max_slabs = std::max<int>(max_slabs, (int)((I.n_r + P.slab_w - 1) / P.slab_w));
+  const int n_passes = (int)P.pass_begin.size() - 1;
+  HIPCHK(ctx->b_ctr.ensure(((size_t)n_passes * max_slabs + 16) * kGemmQueues * 4, nullptr));
+  char *psi_base = reinterpret_cast<char *>(ctx->b_psi.p);
+  char *slab_base = reinterpret_cast<char *>(ctx->b_slab.p);
+  char *xr_base = reinterpret_cast<char *>(ctx->b_xr.p);
+  char *tmp_base = reinterpret_cast<char *>(ctx->b_tmp.p);
+  char *x_base = reinterpret_cast<char *>(ctx->b_x.p);
+  char *sst_base = reinterpret_cast<char *>(ctx->b_sstates.p);
+  double *ssum = reinterpret_cast<double *>(ctx->b_ssum.p);
+  int32_t *ctr = reinterpret_cast<int32_t *>(ctx->b_ctr.p);
+
+  Blob blob;
+  std::vector<SLaunch> L;
+  // per-item tables
+  std::vector<size_t> off_perm_o(n_items), off_perm_u(n_items), off_eps_o(n_items),
+      off_eps_u(n_items), off_states(n_items), off_ct(n_items), off_st(n_items),
+      off_eo(n_items), off_eu(n_items);
+  std::vector<Geo> geos(n_items);
+  int lds = 0;
+  for (int t = 0; t < n_items; ++t) {
+    const ItemPlan &I = P.items[t];
+    const gwchi_sigma_item &it = items[t];
+    off_perm_o[t] = blob.addv(I.perm_o);
+    off_perm_u[t] = blob.addv(I.perm_u);
+    off_eps_o[t] = blob.addv(I.eps_o);
+    off_eps_u[t] = blob.addv(I.eps_u);
+    off_states[t] = blob.add(it.states, (size_t)it.n_states * 4);
+    off_ct[t] = blob.add(it.ct, (size_t)it.n_omega * it.n_tau * 8);
+    off_st[t] = blob.add(it.st, (size_t)it.n_omega * it.n_tau * 8);
+    std::vector<double> eo(it.n_tau), eu(it.n_tau);
+    for (int j = 0; j < it.n_tau; ++j) {
+      eo[j] = std::exp((I.homo - it.mu) * it.tau[j]);     // occupied edge factor at -tau
+      eu[j] = std::exp(-(I.lumo - it.mu) * it.tau[j]);    // unoccupied edge factor at +tau
+    }
+    off_eo[t] = blob.addv(eo);
+    off_eu[t] = blob.addv(eu);
+    Geo g{};
+    g.n0 = I.n0;
+    g.n1 = I.n1;
+    g.n2 = I.n2;
+    g.n_r = (int32_t)I.n_r;
+    g.n_g = I.n_g;
+    g.n_disk = I.n_disk;
+    g.cols = fft_cols(I.n1, I.n2, ec);
+    g.planes = fft_planes(I.n0, I.n1, I.n2, ec);
+    g.disk_i12 = reinterpret_cast<const int32_t *>(blob.addv(I.disk_i12));
+    g.slot_of = reinterpret_cast<const int32_t *>(blob.addv(I.slot_of));
+    g.disk_of = reinterpret_cast<const int32_t *>(blob.addv(I.disk_of));
+    geos[t] = g;
+    lds = std::max(lds, fft_lds_bytes(I.n1, I.n2, g.cols, g.planes, ec) + 4 * I.n_disk);
+  }
+  const size_t off_geos = blob.addv(geos);
+  // ticket counters start at zero (fill kernel), then the states operands
+  {
+    SLaunch Z;
+    Z.phase = SP_STAGE;
+    Z.kind = 5;
+    Z.fill_ptr = ctr;
+    Z.fill_bytes = ((int64_t)n_passes * max_slabs + 16) * kGemmQueues * 4;
+    L.push_back(Z);
+  }
+  for (int t = 0; t < n_items; ++t) {
+    SLaunch S;
+    S.phase = SP_STAGE;
+    S.kind = 6;
+    S.phi_o = items[t].phi_occ;
+    S.phi_u = items[t].phi_unocc;
+    S.states = reinterpret_cast<const int32_t *>(off_states[t]);
+    S.n_states = items[t].n_states;
+    S.n_occ = items[t].n_occ;
+    S.n_r = (int)P.items[t].n_r;
+    S.n_r_pad = (int)P.items[t].n_r_pad;
+    S.out = sst_base + st_off[t];
+    L.push_back(S);
+  }
+  const int per_cu = std::max(1, gemm_sigma_per_cu(prec));
+  const int group = std::max(1, per_cu * ctx->num_cu / kGemmQueues);
+  int gc_want = 1;
+  while (gc_want * gc_want < group) gc_want *= 2;
+  double mfma = 0.0;
+  int n_gemm = 0;
+  std::vector<int> job_slots(P.jobs.size(), 0);
+  for (int ps = 0; ps < n_passes; ++ps) {
+    const int jb = P.pass_begin[ps], je = P.pass_begin[ps + 1];
+    {
+      SLaunch S;
+      S.phase = SP_STAGE;
+      S.kind = 0;
+      S.stage = make_stage(blob, P, jb, je, psi_base, off_perm_o, off_perm_u, off_eps_o, off_eps_u);
+      L.push_back(S);
+    }
+    // W~(G, G') -> W~(G, r'): element (slot G', column G) = conj(W~(G', G)) by
+    // Hermiticity, so consecutive columns are consecutive in memory
+    {
+      std::vector<SfftJob> fj;
+      for (int q = jb; q < je; ++q) {
+        const JobPlan &J = P.jobs[q];
+        const ItemPlan &I = P.items[J.item];
+        SfftJob f{};
+        f.in = items[J.item].w_tau + (int64_t)J.j * I.n_g * I.n_g * 2;
+        f.i_slot = I.n_g;
+        f.i_col = 1;
+        f.tmp = tmp_base + J.o_tmp;
+        f.out = xr_base + J.o_xr;
+        f.o_col = I.n_r;
+        f.o_shift = -1;
+        f.col0 = 0;
+        f.n_cols = I.n_g;
+        f.geo = J.item;
+        fj.push_back(f);
+      }
+      SLaunch S;
+      S.phase = SP_FFT;
+      S.kind = 7;
+      S.sign = -1;
+      sfft_units(fj, geos, S.sfft);
+      S.sfft.jobs = reinterpret_cast<const SfftJob *>(blob.addv(fj));
+      S.sfft.n_jobs = (int)fj.size();
+      S.sfft.geos = reinterpret_cast<const Geo *>(off_geos);
+      S.sfft.in_f64 = 1;
+      S.sfft.conj_in = 1;
+      L.push_back(S);
+    }
+    std::vector<int> order;
+    for (int q = jb; q < je; ++q) order.push_back(q);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      return P.jobs[a].k_o_eff + P.jobs[a].k_u_eff > P.jobs[b].k_o_eff + P.jobs[b].k_u_eff;
+    });
+    for (int s = 0; s < max_slabs; ++s) {
+      std::vector<SfftJob> fj;
+      std::vector<GemmJob> gj;
+      std::vector<std::vector<int4>> qunits(kGemmQueues);
+      std::vector<double> qwork(kGemmQueues, 0.0);
+      for (int q : order) {
+        const JobPlan &J = P.jobs[q];
+        const ItemPlan &I = P.items[J.item];
+        const int64_t s0 = (int64_t)s * P.slab_w;
+        if (s0 >= I.n_r) continue;
+        const int w = (int)std::min<int64_t>(P.slab_w, I.n_r - s0);
+        // W~(G, r') -> W~(r, r' in slab), columns grouped by 128 bytes
+        SfftJob f{};
+        f.in = xr_base + J.o_xr;
+        f.i_slot = I.n_r;
+        f.i_col = 1;
+        f.tmp = tmp_base + J.o_tmp;
+        f.out = slab_base + J.o_slab;
+        f.o_col = 0;
+        f.o_shift = sh;
+        f.col0 = (int32_t)s0;
+        f.n_cols = w;
+        f.geo = J.item;
+        fj.push_back(f);
+        char *slot = psi_base + J.o_psi;
+        GemmJob g{};
+        g.psi_o = slot;
+        g.psi_u = slot + I.n_r_pad * I.k_o_pad * bpb_of(prec, 1);
+        g.ld_o = I.k_o_pad;
+        g.ld_u = I.k_u_pad;
+        g.k_o = J.k_o_eff;
+        g.k_u = J.k_u_eff;
+        g.n_r = (int32_t)I.n_r;
+        g.s0 = (int32_t)s0;
+        g.w = w;
+        g.cg_shift = sh;
+        g.slab = slab_base + J.o_slab;
+        g.states = sst_base + st_off[J.item];
+        g.n_states = items[J.item].n_states;
+        g.ld_states = (int32_t)I.n_r_pad;
+        g.part = reinterpret_cast<double *>(x_base + J.o_x);
+        const int gi = (int)gj.size();
+        gj.push_back(g);
+        const int nrt = (int)((I.n_r + P.bm - 1) / P.bm);
+        const int nct = (w + P.bn - 1) / P.bn;
+        const int gc = std::min(nct, gc_want);
+        const int gr = std::max(1, (group + gc - 1) / gc);
+        const double kk = (double)(J.k_o_eff + J.k_u_eff);
+        for (int cb = 0; cb < nct; cb += gc)
+          for (int rb = 0; rb < nrt; rb += gr) {
+            std::vector<int4> tiles;
+            for (int rt = rb; rt < std::min(nrt, rb + gr); ++rt)
+              for (int ct = cb; ct < std::min(nct, cb + gc); ++ct) {
+                const int r0 = rt * P.bm, c0 = (int)s0 + ct * P.bn;
+                if (r0 + P.bm <= c0) continue;          // lower triangle only
+                tiles.push_back(make_int4(gi, r0, c0, job_slots[q]++));
+              }
+            if (tiles.empty()) continue;
+            const int qq = (int)(std::min_element(qwork.begin(), qwork.end()) - qwork.begin());
+            qunits[qq].insert(qunits[qq].end(), tiles.begin(), tiles.end());
+            qwork[qq] += kk * (double)tiles.size();
+            mfma += 8.0 * P.bm * P.bn * kk * (prec == P_BF16X3 ? 3.0 : 1.0) * (double)tiles.size();
+          }
+      }
+      if (gj.empty()) continue;
+      {
+        SLaunch S;
+        S.phase = SP_FFT;
+        S.kind = 7;
+        S.sign = +1;
+        sfft_units(fj, geos, S.sfft);
+        S.sfft.jobs = reinterpret_cast<const SfftJob *>(blob.addv(fj));
+        S.sfft.n_jobs = (int)fj.size();
+        S.sfft.geos = reinterpret_cast<const Geo *>(off_geos);
+        S.sfft.in_f64 = dbl;
+        S.sfft.conj_in = 0;
+        L.push_back(S);
+      }
+      SLaunch G;
+      G.phase = SP_GEMM;
+      G.kind = 8;
+      G.gemm.jobs = reinterpret_cast<const GemmJob *>(blob.addv(gj));
+      std::vector<int4> units;
+      G.gemm.n_queues = kGemmQueues;
+      for (int q = 0; q < kGemmQueues; ++q) {
+        G.gemm.q_off[q] = (int32_t)units.size();
+        units.insert(units.end(), qunits[q].begin(), qunits[q].end());
+      }
+      G.gemm.q_off[kGemmQueues] = (int32_t)units.size();
+      G.gemm.units = reinterpret_cast<const int4 *>(blob.addv(units));
+      G.gemm.n_units = (int)units.size();
+      G.gemm.hermitian = 1;
+      G.gemm.counter = ctr + n_gemm * kGemmQueues;
+      ++n_gemm;
+      L.push_back(G);
+    }
+    // sums over the tiles of every job of the pass
+    {
+      std::vector<SigmaRed> red;
+      for (int q = jb; q < je; ++q) {
+        const JobPlan &J = P.jobs[q];
+        SigmaRed r{};
+        r.part = reinterpret_cast<const double *>(x_base + J.o_x);
+        r.n_slots = job_slots[q];
+        r.n_states = items[J.item].n_states;
+        r.sum = ssum + sum_off[J.item] + (int64_t)J.j * 2;
+        r.sum_stride = items[J.item].n_tau * 2;
+        red.push_back(r);
+      }
+      SLaunch R;
+      R.phase = SP_FINAL;
+      R.kind = 9;
+      R.red = reinterpret_cast<const SigmaRed *>(blob.addv(red));
+      R.n = (int)red.size();
+      R.max_states = max_states;
+      L.push_back(R);
+    }
+  }
+  {
+    std::vector<SigmaFin> fin;
+    for (int t = 0; t < n_items; ++t) {
+      SigmaFin f{};
+      f.sum = ssum + sum_off[t];
+      f.ct = reinterpret_cast<const double *>(off_ct[t]);
+      f.st = reinterpret_cast<const double *>(off_st[t]);
+      f.edge_o = reinterpret_cast<const double *>(off_eo[t]);
+      f.edge_u = reinterpret_cast<const double *>(off_eu[t]);
+      f.n_states = items[t].n_states;
+      f.n_tau = items[t].n_tau;
+      f.n_omega = items[t].n_omega;
+      f.out = items[t].sigma_out;
+      f.out_tau = items[t].sigma_tau_out;
+      fin.push_back(f);
+    }
+    SLaunch F;
+    F.phase = SP_FINAL;
+    F.kind = 10;
+    F.fin = reinterpret_cast<const SigmaFin *>(blob.addv(fin));
+    F.n = n_items;
+    F.max_states = max_states;
+    F.max_omega = max_omega;
+    L.push_back(F);
+  }
+  // device tables: allocate, patch the blob offsets, upload
+  bool moved = false;
+  HIPCHK(ctx->b_tables.ensure(blob.h.size() + 64, &moved));
+  const char *base = reinterpret_cast<const char *>(ctx->b_tables.p);
+  char *h = blob.h.data();
+  patch_geos(blob, base, off_geos, n_items);
+  for (auto &S : L) {
+    if (S.kind == 0) {
+      patch_stage(S.stage, h, base);
+    } else if (S.kind == 6) {
+      S.states = dev(base, S.states);
+    } else if (S.kind == 7) {
+      S.sfft.jobs = dev(base, S.sfft.jobs);
+      S.sfft.geos = dev(base, S.sfft.geos);
+    } else if (S.kind == 8) {
+      S.gemm.jobs = dev(base, S.gemm.jobs);
+      S.gemm.units = dev(base, S.gemm.units);
+    } else if (S.kind == 9) {
+      S.red = dev(base, S.red);
+    } else if (S.kind == 10) {
+      SigmaFin *f = reinterpret_cast<SigmaFin *>(h + reinterpret_cast<uintptr_t>(S.fin));
+      for (int t = 0; t < S.n; ++t) {
+        f[t].ct = dev(base, f[t].ct);
+        f[t].st = dev(base, f[t].st);
+        f[t].edge_o = dev(base, f[t].edge_o);
+        f[t].edge_u = dev(base, f[t].edge_u);
+      }
+      S.fin = dev(base, S.fin);
+    }
+  }
+  HIPCHK(ctx->h_tables.ensure(blob.h.size() + 64));
+  std::memcpy(ctx->h_tables.p, blob.h.data(), blob.h.size());
+  HIPCHK(hipMemcpyAsync(ctx->b_tables.p, ctx->h_tables.p, blob.h.size(), hipMemcpyHostToDevice,
+                        ctx->stream));
+  // launches, each phase bracketed by events when a report is wanted
+  hipStream_t sm = ctx->stream;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> evs;
+  size_t ev_i = 0;
+  auto ev = [&]() -> hipEvent_t {
+    if (ev_i >= ctx->ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ctx->ev_pool.push_back(e);
+    }
+    return ctx->ev_pool[ev_i++];
+  };
+  for (auto &S : L) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rep) {
+      e0 = ev();
+      e1 = ev();
+      if (!e0 || !e1) {
+        set_err(ctx, "hipEventCreate failed");
+        return GWCHI_EDEVICE;
+      }
+      HIPCHK(hipEventRecord(e0, sm));
+    }
+    switch (S.kind) {
+      case 0: HIPCHK(launch_stage(S.stage, prec, sm)); break;
+      case 5: HIPCHK(launch_fill_zero(S.fill_ptr, S.fill_bytes, sm)); break;
+      case 6:
+        HIPCHK(launch_sigma_states(S.phi_o, S.phi_u, S.states, S.n_states, S.n_occ, S.n_r,
+                                   S.n_r_pad, dbl, S.out, sm));
+        break;
+      case 7: HIPCHK(launch_sfft(S.sfft, dbl, S.sign, lds, sm)); break;
+      case 8: HIPCHK(launch_gemm_sigma(S.gemm, prec, 0, ctx->num_cu, sm)); break;
+      case 9: HIPCHK(launch_sigma_reduce(S.red, S.n, S.max_states, sm)); break;
+      case 10: HIPCHK(launch_sigma_final(S.fin, S.n, S.max_states, S.max_omega, sm)); break;
+    }
+    if (rep) {
+      HIPCHK(hipEventRecord(e1, sm));
+      evs.push_back({S.phase, {e0, e1}});
+    }
+  }
+  if (rep) {
+    HIPCHK(hipStreamSynchronize(sm));
+    gwchi_sigma_report r{};
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, evs.front().second.first, evs.back().second.second));
+    r.ms_total = ms;
+    double ph[SP_COUNT] = {0};
+    for (auto &e : evs) {
+      float m = 0.f;
+      HIPCHK(hipEventElapsedTime(&m, e.second.first, e.second.second));
+      ph[e.first] += m;
+    }
+    r.ms_stage = ph[SP_STAGE];
+    r.ms_fft = ph[SP_FFT];
+    r.ms_gemm = ph[SP_GEMM];
+    r.ms_final = ph[SP_FINAL];
+    r.n_gemm_launches = n_gemm;
+    r.slab_width = P.slab_w;
+    r.tau_batch = P.max_jobs_pass;
+    r.alg_flops = P.alg_flops;
+    r.mfma_flops = mfma;
+    *rep = r;
+  }
+  return GWCHI_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Analytic continuation (Sec. II.E.1).
 // ---------------------------------------------------------------------------
 
@@ -1760,7 +2319,8 @@ gwchi_status gwchi_destroy(gwchi_ctx *ctx) {
                     &ctx->b_tmp, &ctx->b_tables, &ctx->b_norm, &ctx->b_ctr, &ctx->b_wchi,
                     &ctx->b_wtau, &ctx->b_womega, &ctx->b_wa, &ctx->b_wdinv, &ctx->b_wrp,
                     &ctx->b_wcp, &ctx->b_wtab, &ctx->b_wflag, &ctx->b_pf, &ctx->b_pout,
-                    &ctx->b_pcoef, &ctx->b_ptab})
+                    &ctx->b_pcoef, &ctx->b_ptab, &ctx->b_sstates, &ctx->b_ssum, &ctx->b_sw,
+                    &ctx->b_sout, &ctx->b_stau})
     b->release();
   ctx->h_tables.release();
   ctx->h_wtab.release();
@@ -2044,6 +2604,121 @@ gwchi_status gwchi_w_build(gwchi_ctx *ctx, const gwchi_w_item *items, int32_t n_
       total.n_launches += r.n_launches;
     }
     if (report) *report = total;
+    return GWCHI_OK;
+  } catch (const std::bad_alloc &) {
+    set_err(ctx, "host allocation failed");
+    return GWCHI_ENOMEM;
+  } catch (...) {
+    set_err(ctx, "internal error");
+    return GWCHI_EDEVICE;
+  }
+}
+
+gwchi_status gwchi_sigma_validate(const gwchi_sigma_item *items, int32_t n_items,
+                                  int32_t check_orbitals) {
+  try {
+    return validate_sigma_items(nullptr, items, n_items, check_orbitals != 0);
+  } catch (...) {
+    g_tls_error = "internal error in validation";
+    return GWCHI_EINVAL;
+  }
+}
+
+gwchi_status gwchi_sigma_build_device(gwchi_ctx *ctx, const gwchi_sigma_item *items,
+                                      int32_t n_items, gwchi_precision prec, void *hip_stream,
+                                      gwchi_sigma_report *report) {
+  if (!ctx) {
+    g_tls_error = "ctx is NULL";
+    return GWCHI_EINVAL;
+  }
+  try {
+    if (prec != GWCHI_FP64 && prec != GWCHI_FP32 && prec != GWCHI_BF16X3) {
+      set_err(ctx, "unknown precision");
+      return GWCHI_EINVAL;
+    }
+    gwchi_status st = validate_sigma_items(ctx, items, n_items, false);
+    if (st != GWCHI_OK) return st;
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t us = reinterpret_cast<hipStream_t>(hip_stream);
+    HIPCHK(hipEventRecord(ctx->ev_in, us));
+    HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->ev_in, 0));
+    st = run_sigma(ctx, items, n_items, (int)prec, report);
+    if (st != GWCHI_OK) return st;
+    HIPCHK(hipEventRecord(ctx->ev_out, ctx->stream));
+    HIPCHK(hipStreamWaitEvent(us, ctx->ev_out, 0));
+    return GWCHI_OK;
+  } catch (const std::bad_alloc &) {
+    set_err(ctx, "host allocation failed");
+    return GWCHI_ENOMEM;
+  } catch (...) {
+    set_err(ctx, "internal error");
+    return GWCHI_EDEVICE;
+  }
+}
+
+gwchi_status gwchi_sigma_build(gwchi_ctx *ctx, const gwchi_sigma_item *items, int32_t n_items,
+                               gwchi_precision prec, gwchi_sigma_report *report) {
+  if (!ctx) {
+    g_tls_error = "ctx is NULL";
+    return GWCHI_EINVAL;
+  }
+  try {
+    if (prec != GWCHI_FP64 && prec != GWCHI_FP32 && prec != GWCHI_BF16X3) {
+      set_err(ctx, "unknown precision");
+      return GWCHI_EINVAL;
+    }
+    gwchi_status st = validate_sigma_items(ctx, items, n_items, true);
+    if (st != GWCHI_OK) return st;
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    // device copies: orbitals, W~, outputs, packed per item
+    int64_t phi_b = 0, w_b = 0, o_b = 0, ot_b = 0;
+    std::vector<int64_t> phi_off(n_items), w_off(n_items), o_off(n_items), ot_off(n_items);
+    for (int t = 0; t < n_items; ++t) {
+      const gwchi_sigma_item &it = items[t];
+      const int64_t n_r = (int64_t)it.n[0] * it.n[1] * it.n[2];
+      phi_off[t] = phi_b;
+      phi_b += round_up(n_r * 16 * (it.n_occ + it.n_unocc), 256);
+      w_off[t] = w_b;
+      w_b += round_up((int64_t)it.n_tau * it.n_g * it.n_g * 16, 256);
+      o_off[t] = o_b;
+      o_b += round_up((int64_t)it.n_states * it.n_omega * 16, 256);
+      ot_off[t] = ot_b;
+      ot_b += it.sigma_tau_out ? round_up((int64_t)it.n_states * it.n_tau * 16, 256) : 0;
+    }
+    HIPCHK(ctx->b_phi.ensure((size_t)phi_b, nullptr));
+    HIPCHK(ctx->b_sw.ensure((size_t)w_b, nullptr));
+    HIPCHK(ctx->b_sout.ensure((size_t)o_b, nullptr));
+    HIPCHK(ctx->b_stau.ensure((size_t)ot_b + 256, nullptr));
+    std::vector<gwchi_sigma_item> d(items, items + n_items);
+    for (int t = 0; t < n_items; ++t) {
+      const gwchi_sigma_item &it = items[t];
+      const int64_t n_r = (int64_t)it.n[0] * it.n[1] * it.n[2];
+      char *pb = reinterpret_cast<char *>(ctx->b_phi.p) + phi_off[t];
+      HIPCHK(hipMemcpy(pb, it.phi_occ, n_r * 16 * it.n_occ, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(pb + n_r * 16 * it.n_occ, it.phi_unocc, n_r * 16 * it.n_unocc,
+                       hipMemcpyHostToDevice));
+      char *wb = reinterpret_cast<char *>(ctx->b_sw.p) + w_off[t];
+      HIPCHK(hipMemcpy(wb, it.w_tau, (size_t)it.n_tau * it.n_g * it.n_g * 16, hipMemcpyHostToDevice));
+      d[t].phi_occ = reinterpret_cast<const double *>(pb);
+      d[t].phi_unocc = reinterpret_cast<const double *>(pb + n_r * 16 * it.n_occ);
+      d[t].w_tau = reinterpret_cast<const double *>(wb);
+      d[t].sigma_out = reinterpret_cast<double *>(reinterpret_cast<char *>(ctx->b_sout.p) + o_off[t]);
+      d[t].sigma_tau_out = it.sigma_tau_out
+                               ? reinterpret_cast<double *>(reinterpret_cast<char *>(ctx->b_stau.p) + ot_off[t])
+                               : nullptr;
+    }
+    st = run_sigma(ctx, d.data(), n_items, (int)prec, report);
+    if (st != GWCHI_OK) return st;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int t = 0; t < n_items; ++t) {
+      const gwchi_sigma_item &it = items[t];
+      HIPCHK(hipMemcpy(it.sigma_out, d[t].sigma_out, (size_t)it.n_states * it.n_omega * 16,
+                       hipMemcpyDeviceToHost));
+      if (it.sigma_tau_out)
+        HIPCHK(hipMemcpy(it.sigma_tau_out, d[t].sigma_tau_out, (size_t)it.n_states * it.n_tau * 16,
+                         hipMemcpyDeviceToHost));
+    }
     return GWCHI_OK;
   } catch (const std::bad_alloc &) {
     set_err(ctx, "host allocation failed");

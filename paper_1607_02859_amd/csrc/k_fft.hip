@@ -574,6 +574,180 @@ hipError_t launch_fft_n(const FftLaunch &L, int lds_bytes, int n, hipStream_t s)
   }
 }
 
+// ---------------------------------------------------------------------------
+// Sphere-to-grid transforms (the self-energy's W~(G, G') -> W~(r, r'), the
+// two spatial transforms of Eqs. (51)-(52)): the reverse of the pipeline
+// above.  Pencils first: the sphere points of pencil (k1, k2) along k0 are
+// transformed along axis 0; then per i0-plane the pencils are placed in their
+// (k1, k2) positions (zero elsewhere) and transformed along axes 1 and 2.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ cx<T> ld_in(const SfftLaunch &L, const SfftJob &J, int64_t e) {
+  cx<T> v;
+  if (L.in_f64) {
+    const cx<double> d = ld_g(reinterpret_cast<const cx<double> *>(J.in), e);
+    v = cx<T>{(T)d.x, (T)d.y};
+  } else {
+    v = ld_g(reinterpret_cast<const cx<T> *>(J.in), e);
+  }
+  if (L.conj_in) v.y = -v.y;
+  return v;
+}
+
+__device__ __forceinline__ int find_sjob(const SfftJob *jobs, int n, int u, bool pencils) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int u0 = pencils ? jobs[mid].unit0_pencils : jobs[mid].unit0_planes;
+    if (u0 <= u) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int N, int SIGN, typename T>
+__device__ __forceinline__ void spencil_n(const SfftLaunch &L, const SfftJob &J, const Geo &G,
+                                          int d, int c) {
+  // slots first, then every load (masked slots read element 0 and are zeroed)
+  int so[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) so[k] = ld_g(G.slot_of, (int64_t)d * N + k);
+  cx<T> v[N], o[N];
+  const int64_t col = (int64_t)(J.col0 + c) * J.i_col;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const cx<T> x = ld_in<T>(L, J, so[k] >= 0 ? (int64_t)so[k] * J.i_slot + col : col);
+    v[k] = so[k] >= 0 ? x : cx<T>{(T)0, (T)0};
+  }
+  reg_fft<N, SIGN, T, 1>(v, o);
+  cx<T> *tmp = reinterpret_cast<cx<T> *>(J.tmp);
+#pragma unroll
+  for (int i = 0; i < N; ++i) st_g(tmp, ((int64_t)i * G.n_disk + d) * J.n_cols + c, o[i]);
+}
+
+template <typename T, int SIGN>
+__global__ __launch_bounds__(256) void k_sfft_pencils(SfftLaunch L) {
+  for (int u = blockIdx.x; u < L.n_units_pencils; u += gridDim.x) {
+    const SfftJob J = L.jobs[find_sjob(L.jobs, L.n_jobs, u, true)];
+    const Geo G = L.geos[J.geo];
+    const int nch = (J.n_cols + 255) / 256;
+    const int lu = u - J.unit0_pencils;
+    const int d = lu / nch, ch = lu - d * nch;
+    const int c = ch * 256 + threadIdx.x;
+    if (c >= J.n_cols) continue;
+    switch (G.n0) {
+#define GW_SPEN(N)                              \
+  case N:                                       \
+    spencil_n<N, SIGN, T>(L, J, G, d, c);       \
+    break;
+      GW_FFT_SIZES(GW_SPEN)
+#undef GW_SPEN
+      default:
+        break;
+    }
+  }
+}
+
+// A block owns C adjacent columns x P i0-planes (the plane-block shape of the
+// forward transform), in LDS as [p][i1][i2][column] with padded columns.
+template <typename T, int SIGN>
+__global__ __launch_bounds__(256) void k_sfft_planes(SfftLaunch L) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  cx<T> *buf = reinterpret_cast<cx<T> *>(smem);
+  const int tid = threadIdx.x;
+  constexpr int EC = (int)sizeof(cx<T>);
+  for (int u = blockIdx.x; u < L.n_units_planes; u += gridDim.x) {
+    const SfftJob J = L.jobs[find_sjob(L.jobs, L.n_jobs, u, false)];
+    const Geo G = L.geos[J.geo];
+    const int n0 = G.n0, n1 = G.n1, n2 = G.n2;
+    const int C = G.cols, P = G.planes, D = G.n_disk;
+    const int plane = n1 * n2;
+    const int npg = (n0 + P - 1) / P;
+    const int lu = u - J.unit0_planes;
+    const int cg = lu / npg, pg = lu - cg * npg;
+    const int c0 = cg * C, p0 = pg * P;
+    const int np = min(P, n0 - p0);
+    int *s_i12 = reinterpret_cast<int *>(smem + fft_lds_bytes(n1, n2, C, P, EC));
+    for (int d = tid; d < D; d += 256) s_i12[d] = G.disk_i12[d];
+    for (int idx = tid; idx < np * plane * (C + 1); idx += 256) buf[idx] = cx<T>{(T)0, (T)0};
+    __syncthreads();
+    // place the pencils of these planes
+    const cx<T> *tmp = reinterpret_cast<const cx<T> *>(J.tmp);
+    for (int idx = tid; idx < np * D * C; idx += 256) {
+      const int cc = idx % C, rest = idx / C;
+      const int p = rest / D, d = rest - p * D;
+      const int c = c0 + cc;
+      if (c < J.n_cols) {
+        const int i12 = s_i12[d];
+        const int k1 = i12 / n2, k2 = i12 - k1 * n2;
+        buf[lds_idx(p, k1, k2, cc, n1, n2, C)] =
+            ld_g(tmp, ((int64_t)(p0 + p) * D + d) * J.n_cols + c);
+      }
+    }
+    __syncthreads();
+    // along axis 1: lines (p, k2, cc), stride one padded row
+    for (int ln = tid; ln < np * n2 * C; ln += 256) {
+      const int cc = ln % C, rest = ln / C;
+      const int p = rest / n2, k2 = rest - p * n2;
+      line_fft<SIGN, T>(buf + lds_idx(p, 0, k2, cc, n1, n2, C), n2 * (C + 1), n1);
+    }
+    __syncthreads();
+    // along axis 2: lines (p, i1, cc), stride C + 1
+    for (int ln = tid; ln < np * n1 * C; ln += 256) {
+      const int cc = ln % C, rest = ln / C;
+      const int p = rest / n1, i1 = rest - p * n1;
+      line_fft<SIGN, T>(buf + lds_idx(p, i1, 0, cc, n1, n2, C), C + 1, n2);
+    }
+    __syncthreads();
+    // write every grid point of the block
+    cx<T> *out = reinterpret_cast<cx<T> *>(J.out);
+    const int total = np * plane * C;
+    if (J.o_shift >= 0) {
+      // column-grouped: columns of a group are contiguous, lanes over them first
+      const int sh = J.o_shift;
+      for (int idx = tid; idx < total; idx += 256) {
+        const int cc = idx % C, rl = idx / C;
+        const int c = c0 + cc;
+        if (c < J.n_cols) {
+          const int p = rl / plane, q = rl - p * plane;
+          const int i1 = q / n2, i2 = q - i1 * n2;
+          const int64_t r = (int64_t)(p0 + p) * plane + q;
+          const int64_t e = (((int64_t)(c >> sh) * G.n_r + r) << sh) + (c & ((1 << sh) - 1));
+          st_g(out, e, buf[lds_idx(p, i1, i2, cc, n1, n2, C)]);
+        }
+      }
+    } else {
+      // one row of out per column: lanes over consecutive grid points first
+      const int span = np * plane;
+      for (int idx = tid; idx < total; idx += 256) {
+        const int cc = idx / span, rl = idx - cc * span;
+        const int c = c0 + cc;
+        if (c < J.n_cols) {
+          const int p = rl / plane, q = rl - p * plane;
+          const int i1 = q / n2, i2 = q - i1 * n2;
+          const int64_t r = (int64_t)(p0 + p) * plane + q;
+          st_g(out, (int64_t)c * J.o_col + r, buf[lds_idx(p, i1, i2, cc, n1, n2, C)]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int S>
+hipError_t launch_sfft_t(const SfftLaunch &L, int lds_bytes, hipStream_t s) {
+  const int g1 = L.n_units_pencils < 65536 ? L.n_units_pencils : 65536;
+  const int g2 = L.n_units_planes < 2048 ? L.n_units_planes : 2048;
+  if (g1 > 0) hipLaunchKernelGGL((k_sfft_pencils<T, S>), dim3(g1), dim3(256), 0, s, L);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_sfft_planes<T, S>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  if (e != hipSuccess) return e;
+  if (g2 > 0) hipLaunchKernelGGL((k_sfft_planes<T, S>), dim3(g2), dim3(256), lds_bytes, s, L);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 int fft_supported(int n) {
@@ -585,6 +759,13 @@ int fft_supported(int n) {
     default:
       return 0;
   }
+}
+
+hipError_t launch_sfft(const SfftLaunch &L, int dbl, int sign, int lds_bytes, hipStream_t s) {
+  if (dbl) return sign < 0 ? launch_sfft_t<double, -1>(L, lds_bytes, s)
+                           : launch_sfft_t<double, 1>(L, lds_bytes, s);
+  return sign < 0 ? launch_sfft_t<float, -1>(L, lds_bytes, s)
+                  : launch_sfft_t<float, 1>(L, lds_bytes, s);
 }
 
 hipError_t launch_fft(const FftLaunch &L, int dbl, int sign, int lds_bytes, int cubic_n,

@@ -50,9 +50,9 @@ struct MM<P_FP64, C> {
   static constexpr int NACC = 4;
   typedef d4v acc_t;
   // the FP64 16x16 result interleaves rows: value v of lane l is row l/16 + 4v
-  static __device__ __forceinline__ int acc_row(int l, int v) { return (l >> 4) + 4 * v; }
-  static __device__ __forceinline__ int acc_col(int l) { return l & 15; }
-  static __device__ __forceinline__ int frag_row(int l) { return l & 15; }
+  static constexpr int acc_row(int l, int v) { return (l >> 4) + 4 * v; }
+  static constexpr int acc_col(int l) { return l & 15; }
+  static constexpr int frag_row(int l) { return l & 15; }
 };
 
 template <bool C>
@@ -63,11 +63,11 @@ struct MM<P_FP32, C> {
   static constexpr int KR = C ? 4 : 8;
   static constexpr int NACC = 16;
   typedef f16v acc_t;
-  static __device__ __forceinline__ int acc_row(int l, int v) {
+  static constexpr int acc_row(int l, int v) {
     return 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
   }
-  static __device__ __forceinline__ int acc_col(int l) { return l & 31; }
-  static __device__ __forceinline__ int frag_row(int l) { return l & 31; }
+  static constexpr int acc_col(int l) { return l & 31; }
+  static constexpr int frag_row(int l) { return l & 31; }
 };
 
 template <bool C>
@@ -78,11 +78,11 @@ struct MM<P_BF16X3, C> {
   static constexpr int KR = 16;
   static constexpr int NACC = 16;
   typedef f16v acc_t;
-  static __device__ __forceinline__ int acc_row(int l, int v) {
+  static constexpr int acc_row(int l, int v) {
     return 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
   }
-  static __device__ __forceinline__ int acc_col(int l) { return l & 31; }
-  static __device__ __forceinline__ int frag_row(int l) { return l & 31; }
+  static constexpr int acc_col(int l) { return l & 31; }
+  static constexpr int frag_row(int l) { return l & 31; }
 };
 
 
@@ -138,7 +138,16 @@ struct Tile {
   static __device__ __forceinline__ int at(int r, int s) { return r * ROWB + ((s ^ swz(r)) << 4); }
 };
 
-template <int P, bool C, int WTM, int WTN, int KC, int WM, int OCC>
+template <typename R>
+__device__ __forceinline__ R wave_sum(R v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// SIG: the self-energy epilogue (products with W~ and the diagonal matrix
+// elements) instead of the polarizability's Hadamard product.
+template <int P, bool C, int WTM, int WTN, int KC, int WM, int OCC, bool SIG = false>
 struct Gemm {
   typedef MM<P, C> M;
   typedef Tile<P, C, WTM, WTN, KC, WM, OCC> T;
@@ -396,6 +405,113 @@ struct Gemm {
     return u;
   }
 
+  // Self-energy epilogue (complex orbitals), Sec. II.D: with acc_o and acc_u
+  // the edge-scaled Green's functions of the tile,
+  //   M(r, r') = acc(r, r') W~(r, r')      on r >= r' (diagonal halved), 0 above,
+  // and for every state n the tile's share of
+  //   Re sum_{r, r'} conj(psi_n(r)) M(r, r') psi_n(r'),
+  // so that, M being Hermitian, twice the sum over the lower tiles is the
+  // diagonal element <n| G o W~ |n>.  The states pass through LDS NSC at a
+  // time; each (state, occ|unocc) sum is reduced over the lanes, then over the
+  // waves in order, and written to the tile's slot of job.part.
+  static __device__ __forceinline__ void sigma_epilogue(const GemmJob &job, int r0, int c0,
+                                                        int slot, Acc &ao, Acc &au, char *lds) {
+    static_assert(C, "the self-energy epilogue is for complex orbitals");
+    typedef typename std::conditional<P == P_FP64, double, float>::type R;
+    typedef typename std::conditional<P == P_FP64, double2, float2>::type R2;
+    constexpr int NSC = 8;
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int n_r = job.n_r;
+    const int cend = job.s0 + job.w;
+    // W~ slab columns are grouped by 128 bytes (SH fixed per precision), so the
+    // rows of one MFMA block sit at constant offsets from one base per block
+    constexpr int SH = sizeof(R2) == 16 ? 3 : 4;
+    const R2 *wsl = reinterpret_cast<const R2 *>(job.slab);
+    // 1. products with W~ (read in the layout the chi epilogue writes)
+    sfor<0, WTM>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      sfor<0, WTN>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        const int col = c0 + (wc * WTN + j) * M::MB + M::acc_col(l);
+        const int cl = col - job.s0;
+        const int row0 = r0 + (wr * WTM + i) * M::MB + M::acc_row(l, 0);
+        const R2 *base = wsl + (((int64_t)(cl >> SH) * n_r + row0) << SH) + (cl & ((1 << SH) - 1));
+        sfor<0, M::NACC>([&](auto vv) {
+          constexpr int v = decltype(vv)::value;
+          constexpr int dr = M::acc_row(0, v) - M::acc_row(0, 0);   // same for every lane
+          const int row = row0 + dr;
+          const bool ok = col < cend && row < n_r && row >= col;
+          R2 x = ok ? base[dr << SH] : R2{(R)0, (R)0};
+          if (row == col) x = R2{(R)0.5 * x.x, (R)0.5 * x.y};
+          const R ore = ao.re[i][j][v], oim = ao.im[i][j][v];
+          ao.re[i][j][v] = ore * x.x - oim * x.y;
+          ao.im[i][j][v] = ore * x.y + oim * x.x;
+          const R ure = au.re[i][j][v], uim = au.im[i][j][v];
+          au.re[i][j][v] = ure * x.x - uim * x.y;
+          au.im[i][j][v] = ure * x.y + uim * x.x;
+        });
+      });
+    });
+    // 2. the states, NSC at a time: rows of the tile, then its columns
+    R2 *srow = reinterpret_cast<R2 *>(lds);                 // [BM][NSC]
+    R2 *scol = srow + T::BM * NSC;                          // [BN][NSC]
+    R *red = reinterpret_cast<R *>(scol + T::BN * NSC);     // [NW][NSC][2]
+    const R2 *psi = reinterpret_cast<const R2 *>(job.states);
+    for (int n0 = 0; n0 < job.n_states; n0 += NSC) {
+      __syncthreads();
+      for (int q = threadIdx.x; q < (T::BM + T::BN) * NSC; q += T::NT) {
+        const int k = q / (T::BM + T::BN), rr = q - k * (T::BM + T::BN);
+        const int g = rr < T::BM ? r0 + rr : c0 + (rr - T::BM);
+        const R2 v = n0 + k < job.n_states ? psi[(int64_t)(n0 + k) * job.ld_states + g]
+                                           : R2{(R)0, (R)0};
+        if (rr < T::BM) srow[rr * NSC + k] = v;
+        else scol[(rr - T::BM) * NSC + k] = v;
+      }
+      __syncthreads();
+      // one state at a time (a run-time loop keeps the register set small)
+#pragma unroll 1
+      for (int k = 0; k < NSC; ++k) {
+        R so = (R)0, su = (R)0;
+        sfor<0, WTN>([&](auto jj) {
+          constexpr int j = decltype(jj)::value;
+          R tor = 0, toi = 0, tur = 0, tui = 0;
+          sfor<0, WTM>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            sfor<0, M::NACC>([&](auto vv) {
+              constexpr int v = decltype(vv)::value;
+              const R2 p = srow[((wr * WTM + i) * M::MB + M::acc_row(l, v)) * NSC + k];
+              // conj(p) * M
+              tor += p.x * ao.re[i][j][v] + p.y * ao.im[i][j][v];
+              toi += p.x * ao.im[i][j][v] - p.y * ao.re[i][j][v];
+              tur += p.x * au.re[i][j][v] + p.y * au.im[i][j][v];
+              tui += p.x * au.im[i][j][v] - p.y * au.re[i][j][v];
+            });
+          });
+          const R2 q = scol[((wc * WTN + j) * M::MB + M::acc_col(l)) * NSC + k];
+          so += tor * q.x - toi * q.y;
+          su += tur * q.x - tui * q.y;
+        });
+        so = wave_sum(so);
+        su = wave_sum(su);
+        if (l == 0) {
+          red[(w * NSC + k) * 2 + 0] = so;
+          red[(w * NSC + k) * 2 + 1] = su;
+        }
+      }
+      __syncthreads();
+      if ((int)threadIdx.x < 2 * NSC) {
+        const int k = threadIdx.x >> 1, side = threadIdx.x & 1;
+        double a = 0.0;
+        for (int ww = 0; ww < T::NW; ++ww) a += (double)red[(ww * NSC + k) * 2 + side];
+        if (n0 + k < job.n_states)
+          job.part[((int64_t)slot * job.n_states + n0 + k) * 2 + side] = a;
+      }
+    }
+    // every wave is done with LDS before the next unit's loads refill it
+    __syncthreads();
+  }
+
   static __device__ __forceinline__ void run(const GemmLaunch &L) {
     // one LDS array per stage, so that the compiler sees which stage each
     // access touches and lets loads into other stages stay in flight
@@ -457,6 +573,10 @@ struct Gemm {
       zero(au);
       pipe(ao, job.psi_o, job.ld_o, job.k_o / KC);
       pipe(au, job.psi_u, job.ld_u, job.k_u / KC);
+      if constexpr (SIG) {
+        sigma_epilogue(job, r0, c0, unit.w, ao, au, st0);
+        continue;
+      }
       // epilogue: chi = -acc_o * conj(acc_u), column-major slab
       const int n_r = job.n_r;
       const int cend = job.s0 + job.w;
@@ -511,6 +631,11 @@ struct Gemm {
 template <int P, bool C, int WTM, int WTN, int KC, int OCC, int WM>
 __global__ __launch_bounds__(128 * WM, OCC) void k_gemm(GemmLaunch L) {
   Gemm<P, C, WTM, WTN, KC, WM, OCC>::run(L);
+}
+
+template <int P, int WTM, int WTN, int KC, int OCC, int WM>
+__global__ __launch_bounds__(128 * WM, OCC) void k_gemm_sigma(GemmLaunch L) {
+  Gemm<P, true, WTM, WTN, KC, WM, OCC, true>::run(L);
 }
 
 struct TileCfg {
@@ -646,6 +771,67 @@ int gemm_tile_per_cu(int prec, int cplx, int tile) {
   GW_TILES_BF16_R(GW_TRY)
 #undef GW_TRY
   return 0;
+}
+
+// Self-energy tiles, one per precision (complex orbitals): (wave tile M, wave
+// tile N, K chunk, minimum waves per SIMD, rows of waves).
+#define GW_SIGMA_TILES(X) \
+  X(P_FP64, 2, 2, 16, 2, 2) X(P_FP32, 1, 2, 32, 1, 4) X(P_BF16X3, 1, 2, 32, 1, 4)
+
+namespace {
+template <int P, int WTM, int WTN, int KC, int OCC, int WM>
+int sigma_per_cu() {
+  typedef Tile<P, true, WTM, WTN, KC, WM, OCC> T;
+  static int per_cu = -1;
+  if (per_cu < 0) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, k_gemm_sigma<P, WTM, WTN, KC, OCC, WM>, T::NT, 0) != hipSuccess || n < 1)
+      n = 1;
+    per_cu = n;
+  }
+  return per_cu;
+}
+}  // namespace
+
+int gemm_sigma_bm(int prec) {
+#define GW_SBM(P, A, B, K, O, W) if (prec == P) return W * A * (P == P_FP64 ? 16 : 32);
+  GW_SIGMA_TILES(GW_SBM)
+#undef GW_SBM
+  return 0;
+}
+int gemm_sigma_bn(int prec) {
+#define GW_SBN(P, A, B, K, O, W) if (prec == P) return 2 * B * (P == P_FP64 ? 16 : 32);
+  GW_SIGMA_TILES(GW_SBN)
+#undef GW_SBN
+  return 0;
+}
+int gemm_sigma_kc(int prec) {
+#define GW_SKC(P, A, B, K, O, W) if (prec == P) return K;
+  GW_SIGMA_TILES(GW_SKC)
+#undef GW_SKC
+  return 0;
+}
+int gemm_sigma_per_cu(int prec) {
+#define GW_SPC(P, A, B, K, O, W) if (prec == P) return sigma_per_cu<P, A, B, K, O, W>();
+  GW_SIGMA_TILES(GW_SPC)
+#undef GW_SPC
+  return 0;
+}
+
+hipError_t launch_gemm_sigma(const GemmLaunch &L, int prec, int grid, int num_cu, hipStream_t s) {
+  if (L.n_units <= 0) return hipSuccess;
+#define GW_SL(P, A, B, K, O, W)                                                         \
+  if (prec == P) {                                                                      \
+    typedef Tile<P, true, A, B, K, W, O> T;                                             \
+    int g = grid > 0 ? grid : sigma_per_cu<P, A, B, K, O, W>() * num_cu;                \
+    if (g > L.n_units) g = L.n_units;                                                   \
+    hipLaunchKernelGGL((k_gemm_sigma<P, A, B, K, O, W>), dim3(g), dim3(T::NT), 0, s, L); \
+    return hipGetLastError();                                                           \
+  }
+  GW_SIGMA_TILES(GW_SL)
+#undef GW_SL
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_gemm(const GemmLaunch &L, int prec, int cplx, int tile, int grid, int num_cu,

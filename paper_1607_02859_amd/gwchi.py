@@ -23,7 +23,8 @@ EXPORTS = ["gwchi_create", "gwchi_destroy", "gwchi_set_options", "gwchi_get_opti
            "gwchi_validate", "gwchi_chi_build", "gwchi_chi_build_device", "gwchi_autotune",
            "gwchi_autotune_times", "gwchi_last_error", "gwchi_version", "gwchi_w_build",
            "gwchi_w_build_device", "gwchi_w_validate", "gwchi_pade", "gwchi_pade_device",
-           "gwchi_pade_validate", "gwchi_chi_build_device_noalloc"]
+           "gwchi_pade_validate", "gwchi_chi_build_device_noalloc", "gwchi_sigma_validate",
+           "gwchi_sigma_build", "gwchi_sigma_build_device"]
 
 
 class GwchiItem(C.Structure):
@@ -113,6 +114,50 @@ class GwchiWReport(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class GwchiSigmaItem(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32 * 3),
+        ("is_complex", C.c_int32),
+        ("n_occ", C.c_int32),
+        ("n_unocc", C.c_int32),
+        ("phi_occ", C.c_void_p),
+        ("phi_unocc", C.c_void_p),
+        ("eps_occ", C.c_void_p),
+        ("eps_unocc", C.c_void_p),
+        ("mu", C.c_double),
+        ("n_tau", C.c_int32),
+        ("n_omega", C.c_int32),
+        ("tau", C.c_void_p),
+        ("ct", C.c_void_p),
+        ("st", C.c_void_p),
+        ("n_g", C.c_int32),
+        ("g_index", C.c_void_p),
+        ("w_tau", C.c_void_p),
+        ("n_states", C.c_int32),
+        ("states", C.c_void_p),
+        ("sigma_out", C.c_void_p),
+        ("sigma_tau_out", C.c_void_p),
+    ]
+
+
+class GwchiSigmaReport(C.Structure):
+    _fields_ = [
+        ("ms_total", C.c_double),
+        ("ms_stage", C.c_double),
+        ("ms_fft", C.c_double),
+        ("ms_gemm", C.c_double),
+        ("ms_final", C.c_double),
+        ("n_gemm_launches", C.c_int32),
+        ("slab_width", C.c_int32),
+        ("tau_batch", C.c_int32),
+        ("alg_flops", C.c_double),
+        ("mfma_flops", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class GwchiPadeItem(C.Structure):
     _fields_ = [
         ("n_points", C.c_int32),
@@ -159,6 +204,11 @@ def load(path: str = LIB_PATH):
     lib.gwchi_autotune_times.argtypes = [C.c_void_p, C.c_int, C.c_int32, P(C.c_double), C.c_int32,
                                          P(C.c_int32)]
     lib.gwchi_w_build.argtypes = [C.c_void_p, P(GwchiWItem), C.c_int32, P(GwchiWReport)]
+    lib.gwchi_sigma_validate.argtypes = [P(GwchiSigmaItem), C.c_int32, C.c_int32]
+    lib.gwchi_sigma_build.argtypes = [C.c_void_p, P(GwchiSigmaItem), C.c_int32, C.c_int,
+                                      P(GwchiSigmaReport)]
+    lib.gwchi_sigma_build_device.argtypes = [C.c_void_p, P(GwchiSigmaItem), C.c_int32, C.c_int,
+                                             C.c_void_p, P(GwchiSigmaReport)]
     lib.gwchi_w_validate.argtypes = [P(GwchiWItem), C.c_int32]
     lib.gwchi_pade_validate.argtypes = [P(GwchiPadeItem)]
     lib.gwchi_pade.argtypes = [C.c_void_p, P(GwchiPadeItem), P(C.c_double)]
@@ -172,7 +222,8 @@ def load(path: str = LIB_PATH):
               "gwchi_validate", "gwchi_chi_build", "gwchi_chi_build_device", "gwchi_autotune",
               "gwchi_autotune_times", "gwchi_w_build", "gwchi_w_build_device", "gwchi_w_validate",
               "gwchi_pade", "gwchi_pade_device", "gwchi_pade_validate",
-              "gwchi_chi_build_device_noalloc"):
+              "gwchi_chi_build_device_noalloc", "gwchi_sigma_validate", "gwchi_sigma_build",
+              "gwchi_sigma_build_device"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -256,6 +307,59 @@ def make_w_item(keep: _Keep, witem, chi=None, w_tau=None, w_omega=None) -> Gwchi
     it.w_tau_out = _ptr(w_tau)
     it.w_omega_out = _ptr(w_omega)
     return it
+
+
+def make_sigma_item(keep: _Keep, item, phi_occ=None, phi_unocc=None, w_tau=None, sigma_out=None,
+                    sigma_tau_out=None) -> GwchiSigmaItem:
+    """Fill a GwchiSigmaItem from a synth.SigmaItem.  Orbitals and W~ default to
+    host arrays of ``item``; pass device tensors (and device outputs) for the
+    device entry."""
+    it = GwchiSigmaItem()
+    it.n[0], it.n[1], it.n[2] = (int(v) for v in item.n)
+    it.is_complex = 1 if np.iscomplexobj(item.phi_occ) else 0
+    it.n_occ = item.phi_occ.shape[0]
+    it.n_unocc = item.phi_unocc.shape[0]
+    if phi_occ is None:
+        dt = np.complex128 if it.is_complex else np.float64
+        phi_occ = np.ascontiguousarray(item.phi_occ, dtype=dt)
+        phi_unocc = np.ascontiguousarray(item.phi_unocc, dtype=dt)
+        keep.refs += [phi_occ, phi_unocc]
+    if w_tau is None:
+        w_tau = np.ascontiguousarray(item.w_tau, dtype=np.complex128)
+        keep.refs.append(w_tau)
+    it.phi_occ = _ptr(phi_occ)
+    it.phi_unocc = _ptr(phi_unocc)
+    it.eps_occ = _ptr(keep.f64(item.eps_occ))
+    it.eps_unocc = _ptr(keep.f64(item.eps_unocc))
+    it.mu = float(item.mu)
+    it.n_tau = int(np.asarray(item.tau).shape[0])
+    it.n_omega = int(np.asarray(item.ct).shape[0])
+    it.tau = _ptr(keep.f64(item.tau))
+    it.ct = _ptr(keep.f64(item.ct))
+    it.st = _ptr(keep.f64(item.st))
+    g = keep.i32(item.g_index)
+    it.n_g = int(g.shape[0])
+    it.g_index = _ptr(g)
+    it.w_tau = _ptr(w_tau)
+    s = keep.i32(item.states)
+    it.n_states = int(s.shape[0])
+    it.states = _ptr(s)
+    it.sigma_out = _ptr(sigma_out)
+    it.sigma_tau_out = _ptr(sigma_tau_out)
+    return it
+
+
+def sigma_validate(items, check_orbitals=True) -> int:
+    """gwchi_sigma_validate on host arrays; returns the status code."""
+    lib = load()
+    keep = _Keep()
+    its = []
+    for it in items:
+        o = np.zeros(1, np.complex128)
+        keep.refs.append(o)
+        its.append(make_sigma_item(keep, it, sigma_out=o))
+    arr = (GwchiSigmaItem * len(its))(*its)
+    return int(lib.gwchi_sigma_validate(arr, len(its), 1 if check_orbitals else 0))
 
 
 def validate(items, check_orbitals=True) -> int:
@@ -459,6 +563,52 @@ class Context:
         rep = GwchiWReport()
         st = self.lib.gwchi_w_build_device(self.h, arr, len(witems), C.c_void_p(sh),
                                            C.byref(rep) if report else None)
+        if st != 0:
+            raise self._err(st)
+        return rep.as_dict() if report else None
+
+    def sigma_build(self, items: Sequence, prec="fp32", tau_out=False, report=False):
+        """Host-memory self-energy (gwchi_sigma_build): returns a list of
+        complex128 arrays Sigma_nn(i omega) (n_states, n_omega), with the
+        (n_states, n_tau, 2) tau-domain elements when ``tau_out`` and the
+        report dict when ``report``."""
+        keep = _Keep()
+        outs, taus, its = [], [], []
+        for it in items:
+            o = np.empty((len(it.states), np.asarray(it.ct).shape[0]), np.complex128)
+            t = np.empty((len(it.states), len(it.tau), 2), np.float64) if tau_out else None
+            outs.append(o)
+            taus.append(t)
+            its.append(make_sigma_item(keep, it, sigma_out=o, sigma_tau_out=t))
+        arr = (GwchiSigmaItem * len(its))(*its)
+        rep = GwchiSigmaReport()
+        st = self.lib.gwchi_sigma_build(self.h, arr, len(its), PRECISIONS[prec],
+                                        C.byref(rep) if report else None)
+        if st != 0:
+            raise self._err(st)
+        res = (outs, taus) if tau_out else outs
+        return (res, rep.as_dict()) if report else res
+
+    def sigma_build_device(self, items: Sequence, phis, w_taus, outs, tau_outs=None, prec="fp32",
+                           stream=None, report=False):
+        """Device-memory self-energy (gwchi_sigma_build_device): ``phis`` a list
+        of (phi_occ, phi_unocc) complex128 device tensors, ``w_taus`` complex128
+        device tensors (n_tau, n_g, n_g), ``outs`` complex128 device outputs
+        (n_states, n_omega), ``tau_outs`` optional float64 (n_states, n_tau, 2)."""
+        keep = _Keep()
+        if tau_outs is None:
+            tau_outs = [None] * len(items)
+        arr = (GwchiSigmaItem * len(items))(*[
+            make_sigma_item(keep, it, phi_occ=p[0], phi_unocc=p[1], w_tau=w, sigma_out=o,
+                            sigma_tau_out=t)
+            for it, p, w, o, t in zip(items, phis, w_taus, outs, tau_outs)])
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream()
+        sh = int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream or 0)
+        rep = GwchiSigmaReport()
+        st = self.lib.gwchi_sigma_build_device(self.h, arr, len(items), PRECISIONS[prec],
+                                               C.c_void_p(sh), C.byref(rep) if report else None)
         if st != 0:
             raise self._err(st)
         return rep.as_dict() if report else None

@@ -107,7 +107,9 @@ def test_struct_layout_matches_header(lib, tmp_path):
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gwchi.h"', 'int main(void){']
     mirrors = [("gwchi_item", gwchi.GwchiItem), ("gwchi_report", gwchi.GwchiReport),
                ("gwchi_options", gwchi.GwchiOptions), ("gwchi_w_item", gwchi.GwchiWItem),
-               ("gwchi_w_report", gwchi.GwchiWReport), ("gwchi_pade_item", gwchi.GwchiPadeItem)]
+               ("gwchi_w_report", gwchi.GwchiWReport), ("gwchi_pade_item", gwchi.GwchiPadeItem),
+               ("gwchi_sigma_item", gwchi.GwchiSigmaItem),
+               ("gwchi_sigma_report", gwchi.GwchiSigmaReport)]
     for cname, py in mirrors:
         lines.append(f'printf("%zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:
@@ -224,3 +226,57 @@ def test_validate_rejects_mixed_real_and_complex(lib):
     assert gwchi.validate([cplx, cplx]) == 0
     assert gwchi.validate([real, cplx]) == 1
     assert b"all real or all complex" in lib.gwchi_last_error(None)
+
+
+# ---- self-energy entry: host-only validation --------------------------------
+
+@pytest.fixture(scope="module")
+def sitem():
+    return synth.make_sigma_item(9, (6, 5, 4), 3, 9, 4, 4)
+
+
+def _s_mut(sitem, **kw):
+    d = dict(sitem.__dict__)
+    d.update(kw)
+    return synth.SigmaItem(**d)
+
+
+def test_sigma_valid_item_passes(lib, sitem):
+    assert gwchi.sigma_validate([sitem]) == 0
+
+
+@pytest.mark.parametrize("mut", ["state_high", "state_neg", "nan_st", "mu_in_band", "tau_zero",
+                                 "no_states", "too_many_states"])
+def test_sigma_validate_rejects(lib, sitem, mut):
+    if mut == "state_high":
+        w = _s_mut(sitem, states=np.array([0, 12], np.int32))
+    elif mut == "state_neg":
+        w = _s_mut(sitem, states=np.array([-1], np.int32))
+    elif mut == "nan_st":
+        st = sitem.st.copy()
+        st[0, 1] = np.nan
+        w = _s_mut(sitem, st=st)
+    elif mut == "mu_in_band":
+        w = _s_mut(sitem, mu=float(sitem.eps_unocc.min()) + 0.1)
+    elif mut == "tau_zero":
+        w = _s_mut(sitem, tau=np.concatenate([sitem.tau[:-1], [0.0]]))
+    elif mut == "no_states":
+        w = _s_mut(sitem, states=np.zeros(0, np.int32))
+    else:
+        w = _s_mut(sitem, states=np.zeros(1025, np.int32))
+    assert gwchi.sigma_validate([w]) == 1
+
+
+def test_sigma_validate_real_orbitals_unsupported(lib, sitem):
+    w = _s_mut(sitem, phi_occ=sitem.phi_occ.real.copy(), phi_unocc=sitem.phi_unocc.real.copy())
+    assert gwchi.sigma_validate([w]) == 4
+    assert b"real orbitals" in lib.gwchi_last_error(None)
+
+
+def test_sigma_validate_null(lib, sitem):
+    keep = gwchi._Keep()
+    it = gwchi.make_sigma_item(keep, sitem, sigma_out=None)
+    arr = (gwchi.GwchiSigmaItem * 1)(it)
+    assert lib.gwchi_sigma_validate(arr, 1, 1) == 1
+    assert b"NULL" in lib.gwchi_last_error(None)
+    assert lib.gwchi_sigma_validate(None, 0, 1) == 1

@@ -125,7 +125,7 @@ def test_planted_transposed_w_is_caught(small, monkeypatch):
     it = small
     orig = osg.w_real_space_rows
 
-    def planted(item, j, rows):
+    def planted(item, j, rows, w_rg=None):
         t = synth.SigmaItem(**{**item.__dict__, "w_tau": np.transpose(item.w_tau, (0, 2, 1)).copy()})
         return orig(t, j, rows)
 
