@@ -178,6 +178,77 @@ def bench_w(ctx, item, args):
     return out
 
 
+def bench_sigma(ctx, item, args):
+    """The self-energy step (Sec. II.D) on the workload's grid, bands and tau
+    grid: diagonal Sigma_nn(i omega) of the 8 states nearest the gap from a
+    seeded Hermitian W~(G, G', i tau) stand-in; inputs and outputs in HBM.  One
+    step is one call (staging, W~ to real space, the fused band GEMM with the
+    products and matrix elements, the sums and the cosine and sine transforms).
+    The dominant kernel is the band GEMM: its executed flops (lower-triangle
+    tiles, 8 BM BN K each) over its event-timed duration."""
+    import torch
+    from paper_1607_02859_amd import synth
+    dev = torch.device("cuda:0")
+    s = synth.make_sigma_item([2, 0], item.n, item.n_occ, item.n_unocc, item.n_tau, 8)
+    po = torch.from_numpy(s.phi_occ).to(dev)
+    pu = torch.from_numpy(s.phi_unocc).to(dev)
+    w = torch.from_numpy(s.w_tau).to(dev)
+    out = torch.empty((s.n_states, s.n_omega), dtype=torch.complex128, device=dev)
+    tau_out = torch.empty((s.n_states, s.n_tau, 2), dtype=torch.float64, device=dev)
+    paths = {}
+    for prec in args.precisions.split(","):
+        for _ in range(max(1, args.warmup)):
+            ctx.sigma_build_device([s], [(po, pu)], [w], [out], [tau_out], prec=prec, report=True)
+        reps = [ctx.sigma_build_device([s], [(po, pu)], [w], [out], [tau_out], prec=prec,
+                                       report=True) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        ms = sum(r["ms_total"] for r in reps) / len(reps)
+        gemm = sum(r["ms_gemm"] for r in reps) / len(reps)
+        issued = reps[0]["mfma_flops"] / (gemm * 1e-3) / 1e12
+        p = {"ms_per_step": ms, "ms_phases": {k: sum(r[k] for r in reps) / len(reps)
+                                               for k in ("ms_stage", "ms_fft", "ms_gemm", "ms_final")},
+             "tflops": reps[0]["alg_flops"] / (ms * 1e-3) / 1e12,
+             "gemm_tflops_issued": issued, "gemm_frac_of_peak": issued / PEAK_TFLOPS[prec],
+             "gemm_launches": reps[0]["n_gemm_launches"]}
+        if not args.no_check:
+            from oracle import sigma as osg
+            und, bar = osg.sigma_tau(s, 0)
+            got = tau_out.cpu().numpy()[:, 0, :]
+            p["err_vs_oracle_tau0"] = float(max(np.abs(got[:, 0] - und.real).max() / np.abs(und).max(),
+                                                np.abs(got[:, 1] - bar.real).max() / np.abs(bar).max()))
+        paths[prec] = p
+        log(f"[bench] sigma {prec}: {ms:.1f} ms/step (gemm {gemm:.1f}, fft {p['ms_phases']['ms_fft']:.1f}), "
+            f"gemm {issued:.1f} TFLOP/s issued ({100 * p['gemm_frac_of_peak']:.0f}% of peak), "
+            f"err {p.get('err_vs_oracle_tau0', float('nan')):.2e}")
+    head = "fp32" if "fp32" in paths else list(paths)[0]
+    H = paths[head]
+    out_d = {
+        "metric": "Sigma_nn(i omega) (self-energy, 8 states): TFLOP/s (8 N_r^2 K per tau, the two "
+                  "Green's functions)",
+        "value": H["tflops"], "unit": "TFLOP/s", "ms_per_step": H["ms_per_step"], "dtype": DTYPE[head],
+        "config": {"workload": WORKLOADS[args.config], "n_states": s.n_states,
+                   "data": "seeded Hermitian W~(G, G', i tau) stand-in of the workload's sphere"},
+        "paths": paths,
+        "roofline": {"bound": "mfma", "kernel": "k_gemm_sigma (band contractions, products with W~, "
+                                                "matrix elements)",
+                     "achieved": H["gemm_tflops_issued"], "peak": PEAK_TFLOPS[head], "unit": "TFLOP/s",
+                     "frac": H["gemm_frac_of_peak"], "traffic": None},
+    }
+    if not args.no_cpu:
+        from oracle import sigma as osg
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        cores = max([i.get("num_threads", 1) for i in info] or [1])
+        t0 = time.perf_counter()
+        osg.sigma_tau(s, 1)
+        dt = time.perf_counter() - t0
+        out_d["cpu_baseline"] = {"value": 8.0 * s.n_r ** 2 * (s.n_occ + s.n_unocc) / dt * 1e-12,
+                                 "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+                                 "cpu_model": cpu_model(),
+                                 "sample": f"1 of {s.n_tau} tau points (FP64 NumPy/SciPy), {dt:.1f} s"}
+    return out_d
+
+
 PADE_FUNCS, PADE_EVAL = 8192, 4096
 
 
@@ -323,6 +394,11 @@ def main():
     ap.add_argument("--pade", type=int, default=None,
                     help="also time the analytic continuation of many functions known at the "
                          "workload's imaginary frequencies (default: on for configuration 2)")
+    ap.add_argument("--sigma", type=int, default=None,
+                    help="also time the self-energy step on the workload (default: on for "
+                         "configuration 2)")
+    ap.add_argument("--sigma-only", action="store_true",
+                    help="time only the self-energy step (prints one JSON line with the sigma object)")
     ap.add_argument("--pade-only", action="store_true",
                     help="time only the continuation (prints one JSON line with the pade object)")
     ap.add_argument("--w-only", action="store_true",
@@ -355,10 +431,14 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    if args.w_only or args.pade_only:
+    if args.w_only or args.pade_only or args.sigma_only:
         ctx = gwchi.Context(0)
-        out = {"w_tilde": bench_w(ctx, item, args)} if args.w_only else {
-            "pade": bench_pade(ctx, item, args)}
+        if args.w_only:
+            out = {"w_tilde": bench_w(ctx, item, args)}
+        elif args.sigma_only:
+            out = {"sigma": bench_sigma(ctx, item, args)}
+        else:
+            out = {"pade": bench_pade(ctx, item, args)}
         ctx.close()
         print(json.dumps(out), flush=True)
         return
@@ -499,6 +579,10 @@ def main():
         args.pade = 1 if args.config == 2 else 0
     if args.pade:
         res["pade"] = bench_pade(ctx, item, args)
+    if args.sigma is None:
+        args.sigma = 1 if args.config == 2 else 0
+    if args.sigma:
+        res["sigma"] = bench_sigma(ctx, item, args)
     ctx.close()
     del phis, outs
     torch.cuda.empty_cache()

@@ -141,3 +141,48 @@ def test_workload_24cubed_sampled_taus(ctx):
         say(f"[sigma24] prec={prec} ms={rep['ms_total']:.1f} (gemm {rep['ms_gemm']:.1f}, "
             f"fft {rep['ms_fft']:.1f}) err(sampled taus)={worst:.3e}")
         assert np.all(np.isfinite(outs[0])) and worst <= TOL[prec]
+
+
+def test_chain_chi_w_sigma_pade(ctx):
+    """The whole chain on the GPU, each step fed by the previous one's device
+    output -- chi(i omega) (polarizability build), W~(i tau) (screened
+    interaction), Sigma_nn(i omega) (self-energy), then the continuation to
+    real frequencies -- against the oracle chain run on the same seeded
+    inputs (each oracle step fed by the previous oracle step), FP64."""
+    import torch
+    from oracle import chi as oc, pade as op, w as ow
+    dev = torch.device("cuda:0")
+    n_tau = 8
+    it = synth.make_item(211, (8, 8, 8), 8, 40, True, n_tau, x_min=1.0)
+    s_v = synth.coulomb_sqrt(it.n, it.g_index)
+    st, _ = synth.st_fit(it.tau, it.omega, 1.0, 75.0)
+    states = np.array([6, 7, 8, 9], np.int32)
+    # oracle chain
+    chi_ref = oc.chi_omega(it)
+    w_ref = ow.w_tilde_tau(chi_ref, s_v, it.ct)
+    sitem = synth.SigmaItem(n=it.n, phi_occ=it.phi_occ, phi_unocc=it.phi_unocc,
+                            eps_occ=it.eps_occ, eps_unocc=it.eps_unocc, mu=it.mu, tau=it.tau,
+                            omega=it.omega, ct=it.ct, st=st, g_index=it.g_index, w_tau=w_ref,
+                            states=states)
+    sig_ref = osg.sigma_omega(sitem)
+    z = 1j * it.omega
+    wr = np.linspace(-5.0, 5.0, 41) + 0.1j
+    pade_ref = op.continue_to(z, sig_ref, wr)
+    # GPU chain, device buffers passed along
+    po = torch.from_numpy(it.phi_occ).to(dev)
+    pu = torch.from_numpy(it.phi_unocc).to(dev)
+    chi = torch.empty((it.n_omega, it.n_g, it.n_g), dtype=torch.complex128, device=dev)
+    ctx.build_device([it], [(po, pu)], [chi], "fp64")
+    witem = synth.WItem(chi=None, sqrt_v=s_v, ct=it.ct, omega=it.omega)
+    w_tau = torch.empty((n_tau, it.n_g, it.n_g), dtype=torch.complex128, device=dev)
+    ctx.w_build_device([witem], [chi], [w_tau])
+    sig = torch.empty((len(states), it.n_omega), dtype=torch.complex128, device=dev)
+    ctx.sigma_build_device([sitem], [(po, pu)], [w_tau], [sig], prec="fp64")
+    out = torch.empty((len(states), len(wr)), dtype=torch.complex128, device=dev)
+    ctx.pade_device(z, sig, wr, out)
+    torch.cuda.synchronize()
+    e_sig = osg.rel_l2(sig.cpu().numpy(), sig_ref)
+    got = out.cpu().numpy()
+    e_pade = float(np.abs(got - pade_ref).max() / np.abs(pade_ref).max())
+    say(f"[chain] sigma err={e_sig:.3e} continuation err={e_pade:.3e}")
+    assert e_sig <= 1e-10 and e_pade <= 1e-8
