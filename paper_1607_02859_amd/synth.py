@@ -13,9 +13,10 @@ Kresse (arXiv:1607.02859):
   Fermi level, which sits at zero (Sec. II.A.1, the text after Eqs. (1)-(2));
 * a response cutoff sphere of plane waves (Sec. II.C step (i), the cutoff
   sphere after Eqs. (43)-(44));
-* a small nonuniform time/frequency grid (Sec. II.A.2) with cosine
-  coefficients gamma_kj obtained by minimising the error function of
-  Eq. (5) over a range of transition energies (Sec. II.A.3).
+* a small nonuniform time/frequency grid (Sec. II.A.2) with cosine and sine
+  coefficients obtained by minimising the maximum of the error functions of
+  Eqs. (5) and (8) over a range of transition energies (Sec. II.A.3), from
+  the ``minimax`` module of this package.
 
 The physical orbitals of the paper are not available; the stand-ins here are
 seeded Gaussian columns orthonormalised by QR.  They fix only shapes, value
@@ -29,6 +30,8 @@ import math
 from typing import List, Optional, Sequence
 
 import numpy as np
+
+from . import minimax
 
 __all__ = [
     "Item",
@@ -132,98 +135,27 @@ def g_sphere(n: Sequence[int], frac2: float = 5.0 / 36.0) -> np.ndarray:
 # Time / frequency grid and cosine-transform coefficients
 # ----------------------------------------------------------------------------
 
-def _fit_ct(tau, omega, x, ridge):
-    """Least-squares cosine coefficients c_kj = gamma_kj cos(omega_k tau_j).
-
-    For each omega_k, minimise the relative residual of the error function
-    eta^c (Eq. (5)): 2x/(x^2+omega_k^2) - sum_j c_kj exp(-x tau_j), sampled
-    on the transition energies x, plus a small ridge term on column-scaled
-    coefficients to keep the transform well conditioned.
-    """
-    E = np.exp(-np.outer(x, tau))
-    C = np.empty((len(omega), len(tau)))
-    err = 0.0
-    amp = 0.0
-    for k, w in enumerate(omega):
-        f = 2.0 * x / (x * x + w * w)
-        A = E / f[:, None]
-        s = np.sqrt((A * A).sum(0))
-        As = A / s
-        if ridge > 0.0:
-            M = np.vstack([As, ridge * np.eye(len(tau))])
-            rhs = np.concatenate([np.ones(len(x)), np.zeros(len(tau))])
-        else:
-            M, rhs = As, np.ones(len(x))
-        c = np.linalg.lstsq(M, rhs, rcond=None)[0] / s
-        C[k] = c
-        err = max(err, float(np.abs(A @ c - 1.0).max()))
-        amp = max(amp, float((np.abs(A) @ np.abs(c)).max()))
-    return C, err, amp
-
-
-def _family(n_tau, x_min, x_max, a, b, p):
-    t = np.linspace(0.0, 1.0, n_tau) ** p
-    lo, hi = math.log(a / x_max), math.log(b / x_min)
-    tau = np.exp(lo + t * (hi - lo))
-    omega = np.geomspace(x_min / 2.0, x_max, n_tau)
-    return tau, omega
-
-
-@functools.lru_cache(maxsize=64)
-def _ct_grid_cached(n_tau, x_min, x_max, ridge):
-    x = np.geomspace(x_min, x_max, 600)
-    best = None
-    for a in (0.05, 0.1, 0.2, 0.3, 0.5):
-        for b in (1.0, 2.0, 3.0, 5.0, 8.0):
-            for p in (0.7, 0.85, 1.0, 1.2):
-                tau, omega = _family(n_tau, x_min, x_max, a, b, p)
-                _, err, amp = _fit_ct(tau, omega, x, 0.0)
-                score = math.log(err) + 0.5 * math.log(amp)
-                if best is None or score < best[0]:
-                    best = (score, tau, omega)
-    _, tau, omega = best
-    xf = np.geomspace(x_min, x_max, 1500)
-    ct, err, _ = _fit_ct(tau, omega, xf, ridge)
-    return tau, omega, ct, err
-
-
-def ct_grid(n_tau: int, x_min: float, x_max: float, ridge: float = 1e-6):
+def ct_grid(n_tau: int, x_min: float, x_max: float):
     """Nonuniform tau/omega grids and cosine coefficients for transition
-    energies x in [x_min, x_max] (eV).
-
-    The minimax grids the paper uses (Sec. II.A.2) come from a method that is
-    not restated in the paper, so a stand-in is used: omega_k log-spaced in
-    [x_min/2, x_max]; tau_j from a three-parameter log-spaced family picked to
-    minimise log(fit error) + 0.5 log(amplification); coefficients from the
-    least-squares minimisation of Eq. (5).  Returns (tau, omega, ct, fit_err)
-    with ct of shape (n_omega, n_tau).
-    """
-    tau, omega, ct, err = _ct_grid_cached(int(n_tau), float(x_min), float(x_max), float(ridge))
-    return tau.copy(), omega.copy(), ct.copy(), err
+    energies x in [x_min, x_max] (eV): the grid of ``minimax.minimax_grid``
+    (omega_k log-spaced in [x_min/2, x_max], tau_j from a three-parameter
+    log-spaced family) with the minimax coefficients of Eq. (5) under an
+    amplification bound.  Returns (tau, omega, ct, max relative fit error)
+    with ct of shape (n_omega, n_tau)."""
+    g = minimax.minimax_grid(int(n_tau), float(x_min), float(x_max))
+    return g.tau, g.omega, g.ct, g.err_cos
 
 
-def st_fit(tau: np.ndarray, omega: np.ndarray, x_min: float, x_max: float, ridge: float = 1e-6):
+def st_fit(tau: np.ndarray, omega: np.ndarray, x_min: float, x_max: float):
     """Sine-transform coefficients st[k][j] = lambda_kj sin(omega_k tau_j) on a
-    given tau/omega grid: for each omega_k, the least-squares minimisation of the
-    relative residual of Eq. (8), 2 omega_k/(x^2 + omega_k^2) - sum_j st_kj exp(-x tau_j),
-    on 1500 log-spaced x in [x_min, x_max], with the same small ridge on
-    column-scaled coefficients as the cosine fit.  Returns (st, fit_err)."""
-    tau = np.asarray(tau, dtype=np.float64)
-    x = np.geomspace(x_min, x_max, 1500)
-    E = np.exp(-np.outer(x, tau))
-    S = np.empty((len(omega), len(tau)))
-    err = 0.0
-    for k, w in enumerate(omega):
-        f = 2.0 * w / (x * x + w * w)
-        A = E / f[:, None]
-        sc = np.sqrt((A * A).sum(0))
-        As = A / sc
-        M = np.vstack([As, ridge * np.eye(len(tau))]) if ridge > 0.0 else As
-        rhs = np.concatenate([np.ones(len(x)), np.zeros(len(tau))]) if ridge > 0.0 else np.ones(len(x))
-        c = np.linalg.lstsq(M, rhs, rcond=None)[0] / sc
-        S[k] = c
-        err = max(err, float(np.abs(A @ c - 1.0).max()))
-    return S, err
+    given tau/omega grid: the minimax coefficients of Eq. (8) under the same
+    amplification bound as the cosine ones.  Returns (st, max relative fit
+    error).  On the grids of ``ct_grid`` this equals ``minimax_grid(...).st``."""
+    g = minimax.minimax_grid(len(tau), float(x_min), float(x_max))
+    if np.array_equal(g.tau, np.asarray(tau)) and np.array_equal(g.omega, np.asarray(omega)):
+        return g.st, g.err_sin
+    return minimax.fit_transform(np.asarray(tau, float), np.asarray(omega, float), "sin",
+                                 float(x_min), float(x_max))
 
 
 def gauss_legendre_st(omega: np.ndarray, t_max: float, panel: float = 0.1, nodes: int = 8):
@@ -512,7 +444,7 @@ def make_sigma_item(seed, n, n_occ, n_unocc, n_tau, n_states, *, gap=1.0, x_min=
     """One seeded self-energy item with complex orbitals.
 
     Orbitals, eigenvalues, grid and cosine coefficients are those of
-    ``make_item``; the sine coefficients come from ``st_fit`` on the same grid.
+    ``make_item``; the sine coefficients are the grid's minimax ones (Eq. (8)).
     The screened interaction is a Hermitian, negative semidefinite stand-in
     that decays in tau like the correlated interaction:
         W~(i tau_j) = -strength sum_m exp(-x_m tau_j) b_m b_m^H,
@@ -521,7 +453,7 @@ def make_sigma_item(seed, n, n_occ, n_unocc, n_tau, n_states, *, gap=1.0, x_min=
     n_states bands nearest the gap, half below and half above it."""
     it = make_item(seed, n, n_occ, n_unocc, True, n_tau, gap=gap, x_min=x_min, x_max=x_max,
                    n_g=n_g)
-    st, _ = st_fit(it.tau, it.omega, x_min, x_max)
+    st = minimax.minimax_grid(n_tau, x_min, x_max).st
     rng = np.random.default_rng([seed, 77])
     g = it.g_index.shape[0]
     rank = max(1, g // 4) if rank is None else int(rank)
