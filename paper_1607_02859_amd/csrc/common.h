@@ -187,6 +187,9 @@ struct SfftLaunch {
   int32_t n_units_pencils, n_units_planes;
   int32_t in_f64;           // input complex FP64 (else the working precision)
   int32_t conj_in;          // read the complex conjugate of each input element
+  int32_t lower_only;       // only rows r >= col0 + c of column c are wanted: plane blocks
+                            // whose rows all lie above their first column are skipped
+                            // (those rows of out are left unwritten)
 };
 
 // ---------------------------------------------------------------------------

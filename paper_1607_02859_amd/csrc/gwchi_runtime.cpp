@@ -1992,6 +1992,7 @@ gwchi_status run_sigma(gwchi_ctx *ctx, const gwchi_sigma_item *items, int n_item
         S.sfft.geos = reinterpret_cast<const Geo *>(off_geos);
         S.sfft.in_f64 = dbl;
         S.sfft.conj_in = 0;
+        S.sfft.lower_only = 1;          // the GEMM reads rows r >= r' only
         L.push_back(S);
       }
       SLaunch G;

@@ -621,8 +621,15 @@ __device__ __forceinline__ void spencil_n(const SfftLaunch &L, const SfftJob &J,
   }
   reg_fft<N, SIGN, T, 1>(v, o);
   cx<T> *tmp = reinterpret_cast<cx<T> *>(J.tmp);
+  // planes the plane pass skips (lower_only: every row of the plane block
+  // above the block's first column) are not written
+  const int64_t plane = (int64_t)G.n1 * G.n2;
+  const int64_t zlim = L.lower_only ? (int64_t)J.col0 + (c / G.cols) * G.cols : -1;
 #pragma unroll
-  for (int i = 0; i < N; ++i) st_g(tmp, ((int64_t)i * G.n_disk + d) * J.n_cols + c, o[i]);
+  for (int i = 0; i < N; ++i) {
+    const int hi = min(N, (i / G.planes + 1) * G.planes);
+    if (hi * plane > zlim) st_g(tmp, ((int64_t)i * G.n_disk + d) * J.n_cols + c, o[i]);
+  }
 }
 
 template <typename T, int SIGN>
@@ -667,6 +674,8 @@ __global__ __launch_bounds__(256) void k_sfft_planes(SfftLaunch L) {
     const int cg = lu / npg, pg = lu - cg * npg;
     const int c0 = cg * C, p0 = pg * P;
     const int np = min(P, n0 - p0);
+    // a block whose rows all lie above its first column is not wanted (lower_only)
+    if (L.lower_only && (int64_t)(p0 + np) * plane <= (int64_t)J.col0 + c0) continue;
     int *s_i12 = reinterpret_cast<int *>(smem + fft_lds_bytes(n1, n2, C, P, EC));
     for (int d = tid; d < D; d += 256) s_i12[d] = G.disk_i12[d];
     for (int idx = tid; idx < np * plane * (C + 1); idx += 256) buf[idx] = cx<T>{(T)0, (T)0};
