@@ -872,8 +872,13 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, const Bases &D, Bu
             const int q = (int)(std::min_element(qwork.begin(), qwork.end()) - qwork.begin());
             qunits[q].insert(qunits[q].end(), tiles.begin(), tiles.end());
             qwork[q] += kk * (double)tiles.size();
-            P.mfma_flops += (I.cplx ? 8.0 : 2.0) * P.bm * P.bn * kk *
-                            (P.prec == P_BF16X3 ? 3.0 : 1.0) * (double)tiles.size();
+            // complex FP64 / FP32 take three real products per band in the
+            // unoccupied pass, four in the occupied one
+            const double kmf = I.cplx ? (P.prec == P_BF16X3 ? 8.0 * kk
+                                                             : 8.0 * J.k_o_eff + 6.0 * J.k_u_eff)
+                                      : 2.0 * kk;
+            P.mfma_flops += kmf * P.bm * P.bn * (P.prec == P_BF16X3 ? 3.0 : 1.0) *
+                            (double)tiles.size();
           }
         }
         FftJob f{};

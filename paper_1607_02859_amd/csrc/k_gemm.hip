@@ -158,6 +158,19 @@ struct Gemm {
     acc_t im[WTM][WTN];
   };
 
+  // The unoccupied-band pass (the long one) of the FP64 and FP32 complex
+  // polarizability forms the sum of a * conj(b) with three real products
+  // instead of four (the self-energy kernel, short of registers for its
+  // epilogue, keeps four):
+  //   S1 += a.re b.re,  S2 += a.im b.im,  S3 += (a.re + a.im)(b.re - b.im),
+  //   re = S1 + S2,     im = S3 - S1 + S2.
+  // S1 and S2 sit in Acc.re and Acc.im, S3 in an Acc3; the pass ends by
+  // combining them, so that two accumulator sets are live in the other pass.
+  static constexpr bool G3 = C && P != P_BF16X3 && !SIG;
+  struct Acc3 {
+    acc_t x[WTM][WTN];
+  };
+
   static __device__ __forceinline__ void zero(Acc &a) {
     sfor<0, WTM>([&](auto ii) {
       sfor<0, WTN>([&](auto jj) {
@@ -208,6 +221,89 @@ struct Gemm {
   // sharing a SIMD the one holding its operands keeps the matrix core busy
   // while the others issue their LDS reads (measured: +3 % on split-BF16,
   // neutral on FP32, none for FP64).
+  static __device__ __forceinline__ void compute3(Acc &acc, Acc3 &x, const char *buf, int wr,
+                                                  int wc) {
+    if constexpr (P != P_FP64) __builtin_amdgcn_s_setprio(1);
+    const int l = threadIdx.x & 63;
+    const int ra = wr * WTM * M::MB + M::frag_row(l);
+    const int rb = T::BM + wc * WTN * M::MB + M::frag_row(l);
+#pragma unroll 4
+    for (int kb = 0; kb < KC; kb += M::KR) {
+      if constexpr (P == P_FP64) {
+        const int s = kb + (l >> 4);           // one band per slot
+        double2 a[WTM], b[WTN];
+        double as[WTM], bd[WTN];
+#pragma unroll
+        for (int i = 0; i < WTM; ++i) {
+          a[i] = ld<double2>(buf, ra + i * 16, s);
+          as[i] = a[i].x + a[i].y;
+        }
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) {
+          b[j] = ld<double2>(buf, rb + j * 16, s);
+          bd[j] = b[j].x - b[j].y;
+        }
+#pragma unroll
+        for (int i = 0; i < WTM; ++i)
+#pragma unroll
+          for (int j = 0; j < WTN; ++j) {
+            acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, acc.re[i][j], 0, 0, 0);
+            acc.im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].y, acc.im[i][j], 0, 0, 0);
+            x.x[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[i], bd[j], x.x[i][j], 0, 0, 0);
+          }
+      } else {
+        const int s = (kb >> 1) + (l >> 5);    // two bands (re, im, re, im) per slot
+        float4 a[WTM], b[WTN];
+        float as[WTM][2], bd[WTN][2];
+#pragma unroll
+        for (int i = 0; i < WTM; ++i) {
+          a[i] = ld<float4>(buf, ra + i * 32, s);
+          as[i][0] = a[i].x + a[i].y;
+          as[i][1] = a[i].z + a[i].w;
+        }
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) {
+          b[j] = ld<float4>(buf, rb + j * 32, s);
+          bd[j][0] = b[j].x - b[j].y;
+          bd[j][1] = b[j].z - b[j].w;
+        }
+#pragma unroll
+        for (int i = 0; i < WTM; ++i)
+#pragma unroll
+          for (int j = 0; j < WTN; ++j) {
+            f16v &s1 = acc.re[i][j];
+            f16v &s2 = acc.im[i][j];
+            f16v &s3 = x.x[i][j];
+            s1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].x, b[j].x, s1, 0, 0, 0);
+            s2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].y, b[j].y, s2, 0, 0, 0);
+            s3 = __builtin_amdgcn_mfma_f32_32x32x2f32(as[i][0], bd[j][0], s3, 0, 0, 0);
+            s1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].z, b[j].z, s1, 0, 0, 0);
+            s2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].w, b[j].w, s2, 0, 0, 0);
+            s3 = __builtin_amdgcn_mfma_f32_32x32x2f32(as[i][1], bd[j][1], s3, 0, 0, 0);
+          }
+      }
+    }
+    if constexpr (P != P_FP64) __builtin_amdgcn_s_setprio(0);
+  }
+
+  static __device__ __forceinline__ void zero3(Acc3 &x) {
+    sfor<0, WTM>([&](auto ii) {
+      sfor<0, WTN>([&](auto jj) { x.x[decltype(ii)::value][decltype(jj)::value] = acc_t{}; });
+    });
+  }
+  // re = S1 + S2, im = S3 - S1 + S2: the end of a three-product pass
+  static __device__ __forceinline__ void combine3(Acc &acc, const Acc3 &x) {
+    sfor<0, WTM>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      sfor<0, WTN>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        const acc_t s1 = acc.re[i][j], s2 = acc.im[i][j];
+        acc.re[i][j] = s1 + s2;
+        acc.im[i][j] = x.x[i][j] - s1 + s2;
+      });
+    });
+  }
+
   static __device__ __forceinline__ void compute(Acc &acc, const char *buf, int wr, int wc) {
     if constexpr (P != P_FP64) __builtin_amdgcn_s_setprio(1);
     compute_body(acc, buf, wr, wc);
@@ -541,7 +637,8 @@ struct Gemm {
         dma_lane(t, r0, c0, grow[t], sb[t]);
       });
       // one pipelined pass over the n chunks of an operand into acc
-      auto pipe = [&](Acc &acc, const void *psi, int ld, int n) {
+      // three: the three-product form (Acc3 x holds S3), else x is unused
+      auto pipe = [&](auto three, Acc &acc, Acc3 &x, const void *psi, int ld, int n) {
         constexpr int CB = KC * M::BPB;      // bytes per chunk in a row
         const char *base = reinterpret_cast<const char *>(psi);
         const uint32_t pitch = (uint32_t)ld * M::BPB;
@@ -561,7 +658,8 @@ struct Gemm {
               if (c + ST - 1 < n)
                 issue(base + (size_t)(c + ST - 1) * CB, pitch, grow, sb,
                       stage(std::integral_constant<int, (s + ST - 1) % ST>{}));
-              compute(acc, stage(ss), wr, wc);
+              if constexpr (decltype(three)::value) compute3(acc, x, stage(ss), wr, wc);
+              else compute(acc, stage(ss), wr, wc);
             }
           });
         }
@@ -569,10 +667,26 @@ struct Gemm {
         __syncthreads();
       };
       Acc ao, au;
-      zero(ao);
-      zero(au);
-      pipe(ao, job.psi_o, job.ld_o, job.k_o / KC);
-      pipe(au, job.psi_u, job.ld_u, job.k_u / KC);
+      if constexpr (G3) {
+        // the unoccupied pass first: its third accumulator set is free while
+        // the occupied accumulators are not yet live
+        zero(au);
+        {
+          Acc3 x;
+          zero3(x);
+          pipe(std::true_type{}, au, x, job.psi_u, job.ld_u, job.k_u / KC);
+          combine3(au, x);
+        }
+        zero(ao);
+        Acc3 unused;
+        pipe(std::false_type{}, ao, unused, job.psi_o, job.ld_o, job.k_o / KC);
+      } else {
+        Acc3 unused;
+        zero(ao);
+        zero(au);
+        pipe(std::false_type{}, ao, unused, job.psi_o, job.ld_o, job.k_o / KC);
+        pipe(std::false_type{}, au, unused, job.psi_u, job.ld_u, job.k_u / KC);
+      }
       if constexpr (SIG) {
         sigma_epilogue(job, r0, c0, unit.w, ao, au, st0);
         continue;
