@@ -196,15 +196,36 @@ struct Gemm {
   // the loads of one chunk: base points at the chunk's first band of row 0,
   // pitchB is the operand's row pitch in bytes (row offsets in 64 bits: an
   // operand can exceed 4 GB)
+  //
+  // The DMA instruction is written out rather than taken from the compiler's
+  // builtin: the compiler cannot tell which stage a builtin DMA writes, so it
+  // waits for every DMA in flight before the next LDS read, the prefetch of a
+  // later chunk included, and the ring degenerates to load-then-compute.  The
+  // ring's own waits (wait_then_barrier) are what order the stages: a stage is
+  // read only after the vmcnt wait and barrier that cover its loads, and is
+  // refilled only after the barrier that follows its last reads.  M0 holds the
+  // wave's LDS destination (16 bytes per lane from there); it must be written
+  // one wait state before the load.
+  // (M0 is reserved to the compiler, which sets it before each of its own
+  // uses; no other code in these kernels reads it.)
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+  static __device__ __forceinline__ void dma16(const char *g, uint32_t lds) {
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+                 :
+                 : "v"(g), "s"(lds)
+                 : "memory", "m0");
+  }
+#pragma clang diagnostic pop
   static __device__ __forceinline__ void issue(const char *base, uint32_t pitchB,
                                                const uint32_t (&grow)[T::LPW],
                                                const uint32_t (&sb)[T::LPW], char *buf) {
     const int w = threadIdx.x >> 6;
+    const uint32_t lds0 = __builtin_amdgcn_readfirstlane(
+        (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char *)(buf + w * 1024));
     sfor<0, T::LPW>([&](auto tt) {
       constexpr int t = decltype(tt)::value;
-      __builtin_amdgcn_global_load_lds(
-          (const __attribute__((address_space(1))) void *)(base + ((uint64_t)grow[t] * pitchB + sb[t])),
-          (__attribute__((address_space(3))) void *)(buf + (w + t * T::NW) * 1024), 16, 0, 0);
+      dma16(base + ((uint64_t)grow[t] * pitchB + sb[t]), lds0 + t * T::NW * 1024);
     });
   }
 
