@@ -43,7 +43,17 @@ struct Geo {
   const int32_t *disk_i12; // [n_disk] k1*n2 + k2
   const int32_t *slot_of;  // [n_disk][n0] output slot of (pencil d, k0), or -1
   const int32_t *disk_of;  // [n1*n2] pencil d of (k1, k2), or -1
+  // real input only (packed transforms): the disk is closed under negation
+  const int32_t *disk_pair;  // [n_disk] pencil of (-k1, -k2)
+  const int32_t *disk_canon; // [n_canon] pencils d with d <= disk_pair[d]
+  int32_t n_canon;
 };
+
+// Packed real transforms: the plane-FFT block's C lines carry 2C real columns
+// (column-grouped in groups of 2C); lines of a job with n real columns.
+__host__ __device__ constexpr int packed_lines(int n_cols, int cols) {
+  return (n_cols + 2 * cols - 1) / (2 * cols) * cols;
+}
 
 // ---------------------------------------------------------------------------
 // Staging: FP64 weights and scaled operands in the working layout.
@@ -138,6 +148,9 @@ struct FftLaunch {
   int32_t in_real;          // input is real
   int32_t lower_only;       // column c holds only rows r >= col0 + c; others read as zero
   int32_t grouped;          // every job's input is column-grouped (s_col == 0)
+  int32_t packed;           // real, column-grouped input in groups of 2 * cols: two
+                            // real columns per complex transform (pencil units are
+                            // (mirror pair, 256 lines))
 };
 
 // ---------------------------------------------------------------------------

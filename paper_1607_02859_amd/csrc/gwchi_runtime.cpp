@@ -305,6 +305,11 @@ struct ItemPlan {
   std::vector<double> eps_o, eps_u;
   std::vector<int32_t> disk_i12, slot_of, disk_of;
   int n_disk = 0, planes = 1, cols = 16, fft_lds = 0;
+  // real orbitals: the first-index transform packs two real columns into one
+  // complex line (slab groups of 2 * cols columns); mirror pencils and the
+  // canonical pencil of each mirror pair
+  int pack = 0;
+  std::vector<int32_t> disk_pair, disk_canon;
   std::vector<double> coef;    // [n_omega][n_tau]
   std::vector<double> tau;
   const double *phi_o = nullptr, *phi_u = nullptr;
@@ -440,6 +445,19 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
       auto ins = dmap.emplace(i12, (int)dmap.size());
       dk[g] = {ins.first->second, k0};
     }
+    // real orbitals: the disk is closed under negation (pencils the sphere
+    // does not touch are added without output slots), so that every pencil
+    // of a packed transform finds its mirror
+    I.pack = !I.cplx && sigma_states == 0;
+    if (I.pack) {
+      std::vector<int> have;
+      for (auto &kv : dmap) have.push_back(kv.first);
+      for (int i12 : have) {
+        const int k1 = i12 / I.n2, k2 = i12 - k1 * I.n2;
+        const int m = ((I.n1 - k1) % I.n1) * I.n2 + (I.n2 - k2) % I.n2;
+        dmap.emplace(m, (int)dmap.size());
+      }
+    }
     I.n_disk = (int)dmap.size();
     I.disk_i12.resize(I.n_disk);
     for (auto &kv : dmap) I.disk_i12[kv.second] = kv.first;
@@ -447,6 +465,16 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
     for (int g = 0; g < I.n_g; ++g) I.slot_of[(size_t)dk[g].first * I.n0 + dk[g].second] = g;
     I.disk_of.assign((size_t)I.n1 * I.n2, -1);
     for (int d = 0; d < I.n_disk; ++d) I.disk_of[I.disk_i12[d]] = d;
+    I.disk_pair.clear();
+    I.disk_canon.clear();
+    if (I.pack) {
+      I.disk_pair.resize(I.n_disk);
+      for (int d = 0; d < I.n_disk; ++d) {
+        const int k1 = I.disk_i12[d] / I.n2, k2 = I.disk_i12[d] - k1 * I.n2;
+        I.disk_pair[d] = I.disk_of[((I.n1 - k1) % I.n1) * I.n2 + (I.n2 - k2) % I.n2];
+        if (d <= I.disk_pair[d]) I.disk_canon.push_back(d);
+      }
+    }
     // plane-FFT block shape (same formula as the kernels)
     if (I.n0 == I.n1 && I.n1 == I.n2 && fft_specialised(I.n0)) {
       I.cols = fftc_cols(I.n0, ec);
@@ -507,7 +535,7 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
       const int64_t wmax = std::min<int64_t>(W, I.n_r);
       b[0] = round_up(I.n_r_pad * (I.k_o_pad + I.k_u_pad) * bpb, 256);
       b[1] = sigma_states > 0 ? round_up(round_up(wmax, 128 / ec) * I.n_r * ec, 256)
-                              : round_up(round_up(wmax, I.cols) * I.n_r * es, 256);
+                              : round_up(round_up(wmax, I.cols * (I.pack ? 2 : 1)) * I.n_r * es, 256);
       b[2] = round_up((int64_t)I.n_g * I.n_r * ec, 256);
       b[3] = round_up((int64_t)I.n0 * I.n_disk * std::max<int64_t>(wmax, I.n_g) * ec, 256);
       b[4] = (int64_t)I.n_g * I.n_g * ec;
@@ -622,13 +650,22 @@ void emit_fft(Built &B, const Plan &P, std::vector<FftJob> &jobs, int phase, int
   }
   for (auto &kv : groups) {
     std::vector<FftJob> &fj = kv.second;
+    // real column-grouped input of packing items: two columns per transform
+    bool packed = in_real != 0;
+    for (auto &f : fj) packed = packed && f.s_col == 0 && P.items[f.geo].pack;
     int up = 0, un = 0, lds = 0;
     for (auto &f : fj) {
       const ItemPlan &I = P.items[f.geo];
       f.unit0_planes = up;
       f.unit0_pencils = un;
-      up += ((f.n_cols + I.cols - 1) / I.cols) * ((I.n0 + I.planes - 1) / I.planes);
-      un += I.n_disk * ((f.n_cols + 255) / 256);
+      if (packed) {
+        const int n_pc = packed_lines(f.n_cols, I.cols);
+        up += (n_pc / I.cols) * ((I.n0 + I.planes - 1) / I.planes);
+        un += (int)I.disk_canon.size() * ((n_pc + 255) / 256);
+      } else {
+        up += ((f.n_cols + I.cols - 1) / I.cols) * ((I.n0 + I.planes - 1) / I.planes);
+        un += I.n_disk * ((f.n_cols + 255) / 256);
+      }
       lds = std::max(lds, I.fft_lds);
     }
     const int n0 = std::get<0>(kv.first), n1 = std::get<1>(kv.first), n2 = std::get<2>(kv.first);
@@ -641,6 +678,7 @@ void emit_fft(Built &B, const Plan &P, std::vector<FftJob> &jobs, int phase, int
     F.fft.n_units_planes = up;
     F.fft.n_units_pencils = un;
     F.fft.in_real = in_real;
+    F.fft.packed = packed ? 1 : 0;
     F.fft.lower_only = lower_only;
     // the jobs of a launch are all column-grouped or all contiguous along r
     // with unit stride (the two layouts the cubic kernels read; contiguous
@@ -744,12 +782,17 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, const Bases &D, Bu
   key << "|";
   // geometry tables
   std::vector<size_t> off_i12(n_items), off_sdk(n_items), off_dof(n_items), off_perm_o(n_items),
-      off_perm_u(n_items), off_eps_o(n_items), off_eps_u(n_items), off_coef(n_items);
+      off_perm_u(n_items), off_eps_o(n_items), off_eps_u(n_items), off_coef(n_items),
+      off_pair(n_items, 0), off_canon(n_items, 0);
   for (int t = 0; t < n_items; ++t) {
     const ItemPlan &I = P.items[t];
     off_i12[t] = B.blob.addv(I.disk_i12);
     off_sdk[t] = B.blob.addv(I.slot_of);
     off_dof[t] = B.blob.addv(I.disk_of);
+    if (I.pack) {
+      off_pair[t] = B.blob.addv(I.disk_pair);
+      off_canon[t] = B.blob.addv(I.disk_canon);
+    }
     off_perm_o[t] = B.blob.addv(I.perm_o);
     off_perm_u[t] = B.blob.addv(I.perm_u);
     off_eps_o[t] = B.blob.addv(I.eps_o);
@@ -775,6 +818,9 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, const Bases &D, Bu
     g.disk_i12 = reinterpret_cast<const int32_t *>(off_i12[t]);   // offset, patched
     g.slot_of = reinterpret_cast<const int32_t *>(off_sdk[t]);
     g.disk_of = reinterpret_cast<const int32_t *>(off_dof[t]);
+    g.disk_pair = reinterpret_cast<const int32_t *>(off_pair[t]);
+    g.disk_canon = reinterpret_cast<const int32_t *>(off_canon[t]);
+    g.n_canon = (int32_t)I.disk_canon.size();
     geos[t] = g;
   }
   const size_t off_geos = B.blob.addv(geos);
@@ -850,7 +896,7 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, const Bases &D, Bu
         g.s0 = (int32_t)s0;
         g.w = w;
         g.cg_shift = 0;
-        while ((1 << (g.cg_shift + 1)) <= I.cols) ++g.cg_shift;
+        while ((1 << (g.cg_shift + 1)) <= I.cols * (I.pack ? 2 : 1)) ++g.cg_shift;
         g.slab = slab_base + J.o_slab;
         const int gi = (int)gj.size();
         gj.push_back(g);
@@ -1088,6 +1134,10 @@ void patch_geos(Blob &blob, const char *base, size_t off_geos, int n_items) {
     g[i].disk_i12 = dev(base, g[i].disk_i12);
     g[i].slot_of = dev(base, g[i].slot_of);
     g[i].disk_of = dev(base, g[i].disk_of);
+    if (g[i].n_canon > 0) {
+      g[i].disk_pair = dev(base, g[i].disk_pair);
+      g[i].disk_canon = dev(base, g[i].disk_canon);
+    }
   }
 }
 

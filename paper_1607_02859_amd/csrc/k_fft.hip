@@ -273,17 +273,23 @@ __global__ __launch_bounds__(256) void k_fft_planes(FftLaunch L) {
     const int cg = lu / npg, pg = lu - cg * npg;
     const int c0 = cg * C, p0 = pg * P;
     const int np = min(P, n0 - p0);
+    // packed real input: line cc of the block holds the real columns
+    // ca = 2 c0 + cc (real part) and ca + C (imaginary part); tmp rows hold
+    // n_pc packed lines
+    const int c0r = L.packed ? 2 * c0 : c0;        // first real column of the block
+    const int n_pc = L.packed ? packed_lines(J.n_cols, C) : J.n_cols;
     // lower-triangle storage: a block whose planes all lie above the first
     // stored row of its first column is zero; it is skipped and the pencil
     // pass reads those planes as zero (same test there)
-    if (L.lower_only && (int64_t)(p0 + np) * plane <= (int64_t)J.col0 + c0) continue;
+    if (L.lower_only && (int64_t)(p0 + np) * plane <= (int64_t)J.col0 + c0r) continue;
     // the sphere's pencil table, kept in LDS for the gather
     int *s_i12 = reinterpret_cast<int *>(smem + fft_lds_bytes(n1, n2, C, P, EC));
     for (int d = tid; d < D; d += 256) s_i12[d] = G.disk_i12[d];
     // load np planes of C columns
     const int total = np * plane * C;
-    // element idx of the block -> (global offset or -1, LDS index)
-    auto locate = [&](int idx, int64_t &e, int &li) {
+    // element idx of the block -> (global offset or -1, LDS index); packed:
+    // e2 is the offset of the imaginary part's column
+    auto locate = [&](int idx, int64_t &e, int64_t &e2, int &li) {
       int cc, rl;
       if (J.s_col == 0) {       // column-grouped input: one contiguous run
         cc = idx % C;
@@ -296,26 +302,36 @@ __global__ __launch_bounds__(256) void k_fft_planes(FftLaunch L) {
       const int c = c0 + cc;
       const int64_t r = (int64_t)p0 * plane + rl;
       e = -1;
-      if (idx < total && c < J.n_cols && !(L.lower_only && r < J.col0 + c))
+      e2 = -1;
+      if (L.packed) {               // column-grouped, groups of 2C real columns
+        const int ca = 2 * c0 + cc, cb = ca + C;
+        const int64_t b = ((int64_t)cg * (n0 * plane) + r) * (2 * C) + cc;
+        if (idx < total && ca < J.n_cols && !(L.lower_only && r < J.col0 + ca)) e = b;
+        if (idx < total && cb < J.n_cols && !(L.lower_only && r < J.col0 + cb)) e2 = b + C;
+      } else if (idx < total && c < J.n_cols && !(L.lower_only && r < J.col0 + c)) {
         e = J.s_col == 0 ? (int64_t)cg * (n0 * plane) * C + r * C + cc
                          : r * J.s_r + (int64_t)c * J.s_col;
+      }
       const int p = rl / plane, q = rl - p * plane;
       const int i1 = q / n2, i2 = q - i1 * n2;
       li = lds_idx(p, i1, i2, cc, n1, n2, C);
     };
-    auto fetch = [&](int64_t e) -> cx<T> {
+    auto fetch = [&](int64_t e, int64_t e2) -> cx<T> {
       cx<T> v = {(T)0, (T)0};
-      if (e >= 0) {
+      if (L.packed) {
+        if (e >= 0) v.x = reinterpret_cast<const T *>(J.in)[e];
+        if (e2 >= 0) v.y = reinterpret_cast<const T *>(J.in)[e2];
+      } else if (e >= 0) {
         if (L.in_real) v.x = reinterpret_cast<const T *>(J.in)[e];
         else v = reinterpret_cast<const cx<T> *>(J.in)[e];
       }
       return v;
     };
     for (int idx = tid; idx < total; idx += 256) {
-      int64_t e;
+      int64_t e, e2;
       int li;
-      locate(idx, e, li);
-      buf[li] = fetch(e);
+      locate(idx, e, e2, li);
+      buf[li] = fetch(e, e2);
     }
     __syncthreads();
     // along i2: lines (p, i1, cc), stride C
@@ -338,10 +354,10 @@ __global__ __launch_bounds__(256) void k_fft_planes(FftLaunch L) {
       const int cc = idx % C, rest = idx / C;
       const int p = rest / D, d = rest - p * D;
       const int c = c0 + cc;
-      if (c < J.n_cols) {
+      if ((L.packed ? 2 * c0 + cc : c) < J.n_cols) {
         const int i12 = s_i12[d];
         const int i1 = i12 / n2, i2 = i12 - i1 * n2;
-        tmp[((int64_t)(p0 + p) * D + d) * J.n_cols + c] = buf[lds_idx(p, i1, i2, cc, n1, n2, C)];
+        tmp[((int64_t)(p0 + p) * D + d) * n_pc + c] = buf[lds_idx(p, i1, i2, cc, n1, n2, C)];
       }
     }
     __syncthreads();
@@ -384,12 +400,17 @@ void k_fft_planes_c(FftLaunch L) {
     const int lu = u - J.unit0_planes;
     const int cg = lu / npg, pg = lu - cg * npg;
     const int c0 = cg * C, p0 = pg * P;
+    // packed real input (column-grouped only): line cc holds the real columns
+    // 2 c0 + cc (real part) and 2 c0 + cc + C (imaginary part)
+    const bool packed = GROUPED && L.packed;
+    const int c0r = packed ? 2 * c0 : c0;          // first real column of the block
+    const int n_pc = packed ? packed_lines(J.n_cols, C) : J.n_cols;
     // lower-triangle storage: a block whose planes all lie above the first
     // stored row of its first column is zero; it is skipped and the pencil
     // pass reads those planes as zero (same test there)
-    if (L.lower_only && (int64_t)(p0 + P) * plane <= (int64_t)J.col0 + c0) continue;
+    if (L.lower_only && (int64_t)(p0 + P) * plane <= (int64_t)J.col0 + c0r) continue;
     const int c = c0 + cc;
-    const bool col_ok = c < J.n_cols;
+    const bool col_ok = (packed ? c0r + cc : c) < J.n_cols;
     const int64_t zlim = L.lower_only ? (int64_t)J.col0 + c : -1;
     // LDS element (grid point rl of the block, column k)
     auto li = [&](int rl, int k) { return rl * C + k; };
@@ -408,11 +429,28 @@ void k_fft_planes_c(FftLaunch L) {
       // is a run of NC rows of one group, read straight into registers;
       // rows above the diagonal of lower-triangle storage read as zero
       const int64_t r0 = (int64_t)p0 * plane + rl0;
-      const int64_t e0 = col_ok ? ((int64_t)cg * G.n_r + r0) * C + cc : 0;
+      if (packed) {
+        // groups of 2C real columns; both columns of the line lie in one
+        // group, which the slab holds whole
+        const int ca = c0r + cc, cb = ca + C;
+        const bool okb = cb < J.n_cols;
+        const int64_t za = L.lower_only ? (int64_t)J.col0 + ca : -1;
+        const int64_t zb = L.lower_only ? (int64_t)J.col0 + cb : -1;
+        const int64_t e0 = col_ok ? ((int64_t)cg * G.n_r + r0) * (2 * C) + cc : 0;
+        const T *in = reinterpret_cast<const T *>(J.in);
 #pragma unroll
-      for (int i = 0; i < NC; ++i) {
-        const cx<T> x = load(e0 + i * C);
-        v[i] = (col_ok && r0 + i >= zlim) ? x : cx<T>{(T)0, (T)0};
+        for (int i = 0; i < NC; ++i) {
+          const T xa = ld_g(in, e0 + i * (2 * C));
+          const T xb = ld_g(in, e0 + i * (2 * C) + C);
+          v[i] = cx<T>{(col_ok && r0 + i >= za) ? xa : (T)0, (okb && r0 + i >= zb) ? xb : (T)0};
+        }
+      } else {
+        const int64_t e0 = col_ok ? ((int64_t)cg * G.n_r + r0) * C + cc : 0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+          const cx<T> x = load(e0 + i * C);
+          v[i] = (col_ok && r0 + i >= zlim) ? x : cx<T>{(T)0, (T)0};
+        }
       }
     } else {
       // each column contiguous in r with unit stride (element (r, c) at
@@ -469,10 +507,10 @@ void k_fft_planes_c(FftLaunch L) {
       for (int i = 0; i < NC; ++i) v[i] = buf[li((p * NC + i) * NC + a, cc)];
       reg_fft<NC, SIGN, T, 1>(v, o);
       if (col_ok) {
-        cx<T> *tmp = reinterpret_cast<cx<T> *>(J.tmp) + (int64_t)(p0 + p) * D * J.n_cols + c;
+        cx<T> *tmp = reinterpret_cast<cx<T> *>(J.tmp) + (int64_t)(p0 + p) * D * n_pc + c;
 #pragma unroll
         for (int k = 0; k < NC; ++k)
-          if (dk[k] >= 0) st_g(tmp, (int64_t)dk[k] * J.n_cols, o[k]);
+          if (dk[k] >= 0) st_g(tmp, (int64_t)dk[k] * n_pc, o[k]);
       }
     }
     __syncthreads();
@@ -506,11 +544,97 @@ __device__ __forceinline__ void pencil_n(const FftJob &J, const Geo &G, int d, i
     if (so[k] >= 0) st_g(out, (int64_t)so[k] * J.o_slot, o[k]);
 }
 
+// Packed real input: line pc holds z = x_a + i x_b for the real columns ca
+// and cb = ca + C, so that with Z its transform
+//   X_a(G) = (Z(G) + conj Z(-G)) / 2,   X_b(G) = (Z(G) - conj Z(-G)) / (2 i).
+// The thread owns pencil d = (k1, k2) and its mirror m = (-k1, -k2) (the disk
+// is closed under negation), transforms both along i0 and writes the sphere
+// points of both pencils for both columns; -G of (k0, d) is (-k0, m).
+template <int N, int SIGN, typename T>
+__device__ __forceinline__ void pencil_pk_n(const FftJob &J, const Geo &G, int d, int pc,
+                                            int n_pc, int lower_only) {
+  const cx<T> *tmp = reinterpret_cast<const cx<T> *>(J.tmp);
+  const int C = G.cols;
+  const int m = G.disk_pair[d];
+  const int64_t plane = (int64_t)G.n1 * G.n2;
+  const int ca = (pc / C) * (2 * C) + pc % C, cb = ca + C;
+  // planes whose plane-FFT block was skipped as all-zero (first real column
+  // of the block, as there)
+  const int64_t zlim = lower_only ? (int64_t)J.col0 + (pc / C) * (2 * C) : -1;
+  int sd[N], sm[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    sd[k] = ld_g(G.slot_of, (int64_t)d * N + k);
+    sm[k] = ld_g(G.slot_of, (int64_t)m * N + k);
+  }
+  auto pencil = [&](int dd, cx<T> (&z)[N]) {
+    cx<T> v[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const int hi = min(N, (i / G.planes + 1) * G.planes);
+      const bool ok = hi * plane > zlim;
+      const cx<T> x = ld_g(tmp, ok ? ((int64_t)i * G.n_disk + dd) * n_pc + pc : 0);
+      v[i] = ok ? x : cx<T>{(T)0, (T)0};
+    }
+    reg_fft<N, SIGN, T, 1>(v, z);
+  };
+  cx<T> zd[N], zm[N];
+  pencil(d, zd);
+  if (m != d) {
+    pencil(m, zm);
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) zm[k] = zd[k];
+  }
+  cx<T> *out = reinterpret_cast<cx<T> *>(J.out);
+  const bool oka = ca < J.n_cols, okb = cb < J.n_cols;
+  const int64_t oa = (int64_t)(J.col0 + ca) * J.o_col, ob = (int64_t)(J.col0 + cb) * J.o_col;
+  auto emit = [&](const cx<T> (&z)[N], const cx<T> (&w)[N], const int (&so)[N]) {
+    sfor<0, N>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      if (so[k] >= 0) {
+        const cx<T> g = z[k], q = w[(N - k) % N];      // Z(G), Z(-G)
+        const cx<T> xa = {(T)0.5 * (g.x + q.x), (T)0.5 * (g.y - q.y)};
+        const cx<T> xb = {(T)0.5 * (g.y + q.y), (T)0.5 * (q.x - g.x)};
+        if (oka) st_g(out, (int64_t)so[k] * J.o_slot + oa, xa);
+        if (okb) st_g(out, (int64_t)so[k] * J.o_slot + ob, xb);
+      }
+    });
+  };
+  emit(zd, zm, sd);
+  if (m != d) emit(zm, zd, sm);
+}
+
 template <typename T, int SIGN, int NC>
 __global__ __launch_bounds__(256) void k_fft_pencils(FftLaunch L) {
   for (int u = blockIdx.x; u < L.n_units_pencils; u += gridDim.x) {
     const FftJob J = L.jobs[find_job(L.jobs, L.n_jobs, u, true)];
     const Geo G = L.geos[J.geo];
+    if (L.packed) {
+      // units: (mirror pair q, 256 packed lines)
+      const int n_pc = packed_lines(J.n_cols, G.cols);
+      const int nch = (n_pc + 255) / 256;
+      const int lu = u - J.unit0_pencils;
+      const int q = lu / nch, ch = lu - q * nch;
+      const int pc = ch * 256 + threadIdx.x;
+      if (pc >= n_pc || (pc / G.cols) * (2 * G.cols) + pc % G.cols >= J.n_cols) continue;
+      const int d = G.disk_canon[q];
+      if constexpr (NC > 0) {
+        pencil_pk_n<NC, SIGN, T>(J, G, d, pc, n_pc, L.lower_only);
+      } else {
+        switch (G.n0) {
+#define GW_PEN(N)                                               \
+  case N:                                                       \
+    pencil_pk_n<N, SIGN, T>(J, G, d, pc, n_pc, L.lower_only);   \
+    break;
+          GW_FFT_SIZES(GW_PEN)
+#undef GW_PEN
+          default:
+            break;
+        }
+      }
+      continue;
+    }
     const int nch = (J.n_cols + 255) / 256;
     const int lu = u - J.unit0_pencils;
     const int d = lu / nch, ch = lu - d * nch;
