@@ -47,6 +47,11 @@ struct Geo {
   const int32_t *disk_pair;  // [n_disk] pencil of (-k1, -k2)
   const int32_t *disk_canon; // [n_canon] pencils d with d <= disk_pair[d]
   int32_t n_canon;
+  // half rows (see FftJob::half_rows)
+  const int32_t *slot_half;  // [n_disk][n0] compact row of (pencil d, k0), or -1
+  const int32_t *hrow;       // [n_half] sphere index of compact row h
+  const int32_t *gneg;       // [n_g] sphere index of -G
+  int32_t n_half;
 };
 
 // Packed real transforms: the plane-FFT block's C lines carry 2C real columns
@@ -137,6 +142,12 @@ struct FftJob {
   int32_t geo;
   int32_t unit0_planes;     // first plane-FFT block of this job in the launch
   int32_t unit0_pencils;    // first pencil block of this job in the launch
+  // real orbitals with a sphere closed under G -> -G: only the rows G of one
+  // half (Geo::hrow) are transformed over the second index.  First index:
+  // output row = slot_half (compact row, -1 = not kept).  Second index:
+  // column c is row hrow[c]; each result chi(G, G') is also written
+  // conjugated at (-G, -G'), which is exact for a real chi(r, r').
+  int32_t half_rows;
 };
 
 struct FftLaunch {

@@ -15,6 +15,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <unordered_map>
 #include <memory>
 #include <mutex>
 #include <numeric>
@@ -310,6 +311,11 @@ struct ItemPlan {
   // canonical pencil of each mirror pair
   int pack = 0;
   std::vector<int32_t> disk_pair, disk_canon;
+  // real orbitals, sphere closed under G -> -G: the second-index transform
+  // runs over the rows of one half only (hrow), the first index keeps only
+  // those rows (slot_half); gneg[g] is the sphere index of -G
+  int half = 0;
+  std::vector<int32_t> slot_half, hrow, gneg;
   std::vector<double> coef;    // [n_omega][n_tau]
   std::vector<double> tau;
   const double *phi_o = nullptr, *phi_u = nullptr;
@@ -467,6 +473,39 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
     for (int d = 0; d < I.n_disk; ++d) I.disk_of[I.disk_i12[d]] = d;
     I.disk_pair.clear();
     I.disk_canon.clear();
+    I.half = 0;
+    I.slot_half.clear();
+    I.hrow.clear();
+    I.gneg.clear();
+    if (I.pack) {
+      // -G of every sphere point, if the sphere holds it
+      std::unordered_map<int, int> gi;
+      for (int g = 0; g < I.n_g; ++g) gi.emplace(it.g_index[g], g);
+      I.gneg.assign(I.n_g, -1);
+      bool closed = true;
+      for (int g = 0; g < I.n_g && closed; ++g) {
+        const int f = it.g_index[g];
+        const int k0 = f / (I.n1 * I.n2), k1 = (f / I.n2) % I.n1, k2 = f % I.n2;
+        const int fm = (((I.n0 - k0) % I.n0) * I.n1 + (I.n1 - k1) % I.n1) * I.n2 + (I.n2 - k2) % I.n2;
+        auto q = gi.find(fm);
+        if (q == gi.end()) closed = false;
+        else I.gneg[g] = q->second;
+      }
+      if (closed) {
+        I.half = 1;
+        std::vector<int32_t> hidx(I.n_g, -1);
+        for (int g = 0; g < I.n_g; ++g)
+          if (g <= I.gneg[g]) {
+            hidx[g] = (int32_t)I.hrow.size();
+            I.hrow.push_back(g);
+          }
+        I.slot_half.assign(I.slot_of.size(), -1);
+        for (size_t e = 0; e < I.slot_of.size(); ++e)
+          if (I.slot_of[e] >= 0) I.slot_half[e] = hidx[I.slot_of[e]];
+      } else {
+        I.gneg.clear();
+      }
+    }
     if (I.pack) {
       I.disk_pair.resize(I.n_disk);
       for (int d = 0; d < I.n_disk; ++d) {
@@ -783,7 +822,8 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, const Bases &D, Bu
   // geometry tables
   std::vector<size_t> off_i12(n_items), off_sdk(n_items), off_dof(n_items), off_perm_o(n_items),
       off_perm_u(n_items), off_eps_o(n_items), off_eps_u(n_items), off_coef(n_items),
-      off_pair(n_items, 0), off_canon(n_items, 0);
+      off_pair(n_items, 0), off_canon(n_items, 0), off_shalf(n_items, 0), off_hrow(n_items, 0),
+      off_gneg(n_items, 0);
   for (int t = 0; t < n_items; ++t) {
     const ItemPlan &I = P.items[t];
     off_i12[t] = B.blob.addv(I.disk_i12);
@@ -792,6 +832,11 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, const Bases &D, Bu
     if (I.pack) {
       off_pair[t] = B.blob.addv(I.disk_pair);
       off_canon[t] = B.blob.addv(I.disk_canon);
+    }
+    if (I.half) {
+      off_shalf[t] = B.blob.addv(I.slot_half);
+      off_hrow[t] = B.blob.addv(I.hrow);
+      off_gneg[t] = B.blob.addv(I.gneg);
     }
     off_perm_o[t] = B.blob.addv(I.perm_o);
     off_perm_u[t] = B.blob.addv(I.perm_u);
@@ -821,6 +866,10 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, const Bases &D, Bu
     g.disk_pair = reinterpret_cast<const int32_t *>(off_pair[t]);
     g.disk_canon = reinterpret_cast<const int32_t *>(off_canon[t]);
     g.n_canon = (int32_t)I.disk_canon.size();
+    g.slot_half = reinterpret_cast<const int32_t *>(off_shalf[t]);
+    g.hrow = reinterpret_cast<const int32_t *>(off_hrow[t]);
+    g.gneg = reinterpret_cast<const int32_t *>(off_gneg[t]);
+    g.n_half = I.half ? (int32_t)I.hrow.size() : 0;
     geos[t] = g;
   }
   const size_t off_geos = B.blob.addv(geos);
@@ -938,6 +987,7 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, const Bases &D, Bu
         f.col0 = (int32_t)s0;
         f.n_cols = w;
         f.geo = J.item;
+        f.half_rows = I.half;
         fj.push_back(f);
       }
       if (gj.empty()) continue;
@@ -981,7 +1031,8 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, const Bases &D, Bu
         f.o_slot = I.n_g;
         f.o_col = 1;
         f.col0 = 0;
-        f.n_cols = I.n_g;
+        f.n_cols = I.half ? (int32_t)I.hrow.size() : I.n_g;
+        f.half_rows = I.half;
         f.geo = J.item;
         fj.push_back(f);
       }
@@ -1137,6 +1188,11 @@ void patch_geos(Blob &blob, const char *base, size_t off_geos, int n_items) {
     if (g[i].n_canon > 0) {
       g[i].disk_pair = dev(base, g[i].disk_pair);
       g[i].disk_canon = dev(base, g[i].disk_canon);
+    }
+    if (g[i].n_half > 0) {
+      g[i].slot_half = dev(base, g[i].slot_half);
+      g[i].hrow = dev(base, g[i].hrow);
+      g[i].gneg = dev(base, g[i].gneg);
     }
   }
 }

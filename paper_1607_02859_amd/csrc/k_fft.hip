@@ -538,6 +538,23 @@ __device__ __forceinline__ void pencil_n(const FftJob &J, const Geo &G, int d, i
     v[i] = ok ? x : cx<T>{(T)0, (T)0};
   }
   reg_fft<N, SIGN, T, 1>(v, o);
+  if (J.half_rows) {
+    // column c is row g = hrow[c] of the kept half; chi(-G, -G') is the
+    // conjugate of chi(G, G') (not written again for a row with -G = G)
+    const int g = ld_g(G.hrow, (int64_t)c);
+    const int gm = ld_g(G.gneg, (int64_t)g);
+    cx<T> *out = reinterpret_cast<cx<T> *>(J.out);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      if (so[k] >= 0) {
+        st_g(out, (int64_t)so[k] * J.o_slot + (int64_t)g * J.o_col, o[k]);
+        if (gm != g)
+          st_g(out, (int64_t)ld_g(G.gneg, (int64_t)so[k]) * J.o_slot + (int64_t)gm * J.o_col,
+               cx<T>{o[k].x, -o[k].y});
+      }
+    }
+    return;
+  }
   cx<T> *out = reinterpret_cast<cx<T> *>(J.out) + (int64_t)(J.col0 + c) * J.o_col;
 #pragma unroll
   for (int k = 0; k < N; ++k)
@@ -561,11 +578,13 @@ __device__ __forceinline__ void pencil_pk_n(const FftJob &J, const Geo &G, int d
   // planes whose plane-FFT block was skipped as all-zero (first real column
   // of the block, as there)
   const int64_t zlim = lower_only ? (int64_t)J.col0 + (pc / C) * (2 * C) : -1;
+  // output rows: sphere slots, or compact rows of the kept half
+  const int32_t *tab = J.half_rows ? G.slot_half : G.slot_of;
   int sd[N], sm[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    sd[k] = ld_g(G.slot_of, (int64_t)d * N + k);
-    sm[k] = ld_g(G.slot_of, (int64_t)m * N + k);
+    sd[k] = ld_g(tab, (int64_t)d * N + k);
+    sm[k] = ld_g(tab, (int64_t)m * N + k);
   }
   auto pencil = [&](int dd, cx<T> (&z)[N]) {
     cx<T> v[N];

@@ -282,6 +282,42 @@ DEGENERATE = {
 _DEG = {}
 
 
+# Real orbitals: the first-index transform packs two real columns into one
+# complex line, and when the plane-wave list is closed under G -> -G only one
+# half of the rows is transformed over the second index, the other half
+# following by conjugation.  A shuffled closed list makes the -G map
+# non-trivial; a list with one point of a +-G pair dropped takes the path that
+# transforms every row.
+def _real_sphere(kind):
+    it = synth.make_item(114, (12, 12, 12), 6, 40, False, 3, x_min=1.0)
+    g = np.asarray(it.g_index)
+    if kind == "shuffled":
+        g = np.random.default_rng(5).permutation(g)
+    else:
+        g = np.concatenate([g[:7], g[8:]])     # drops m = (-1, -1, 0), keeps (1, 1, 0)
+    it.g_index = np.ascontiguousarray(g, dtype=np.int32)
+    return it
+
+
+_REAL = {}
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("herm", [0, 1])
+@pytest.mark.parametrize("kind", ["shuffled", "open"])
+def test_real_sphere_symmetry(ctx, kind, herm, prec):
+    if kind not in _REAL:
+        it = _real_sphere(kind)
+        _REAL[kind] = (it, oc.chi_omega(it))
+    it, ref = _REAL[kind]
+    say(f"[real sphere] kind={kind} herm={herm} prec={prec} n_g={len(it.g_index)}")
+    ctx.set_options(use_graph=1, hermitian=herm, skip_zero_bands=0, slab_width=0, tile_id=0)
+    out = ctx.build([it], prec)[0]
+    err = oc.rel_frobenius(out, ref)
+    say(f"   err={err:.3e}")
+    assert np.all(np.isfinite(out)) and err <= TOL[prec]
+
+
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("herm", [0, 1])
 @pytest.mark.parametrize("name", list(DEGENERATE))
