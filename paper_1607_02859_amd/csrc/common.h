@@ -148,6 +148,9 @@ struct FftJob {
   // column c is row hrow[c]; each result chi(G, G') is also written
   // conjugated at (-G, -G'), which is exact for a real chi(r, r').
   int32_t half_rows;
+  // single-launch transform (FftLaunch::fused): output rows column-grouped in
+  // groups of 2^o_gshift
+  int32_t o_gshift;
 };
 
 struct FftLaunch {
@@ -162,7 +165,25 @@ struct FftLaunch {
   int32_t packed;           // real, column-grouped input in groups of 2 * cols: two
                             // real columns per complex transform (pencil units are
                             // (mirror pair, 256 lines))
+  int32_t fused;            // single-launch first-index transform (complex FP32,
+                            // cubic fft_fusable grids): units are columns, input
+                            // column-major (column groups one column wide)
 };
+
+// Single-launch transform: sizes, i0-planes per LDS batch (one thread per
+// line, 256 threads) and LDS bytes (FP32 points).  Every disk pencil is owned
+// by one thread, so n_disk <= 256.
+constexpr bool fft_fusable(int n) { return n == 12 || n == 16 || n == 18 || n == 20 || n == 24; }
+// (at most 9 16-byte loads per thread and batch, for registers)
+__host__ __device__ constexpr int fused_pb(int n) {
+  return 256 / n < n ? (256 / n < 4608 / (n * n) ? 256 / n : 4608 / (n * n))
+                     : (n < 4608 / (n * n) ? n : 4608 / (n * n));
+}
+// LDS: the linear stage of one batch (whole KB) and the padded work area
+__host__ __device__ constexpr int fused_stage_bytes(int n) {
+  return (fused_pb(n) * n * n * 8 + 1023) / 1024 * 1024;
+}
+constexpr int fused_lds_bytes(int n) { return fused_stage_bytes(n) + 8 * fused_pb(n) * n * (n + 1); }
 
 // ---------------------------------------------------------------------------
 // Cosine transform (FP64 accumulation) and norms.

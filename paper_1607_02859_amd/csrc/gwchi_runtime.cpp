@@ -316,6 +316,9 @@ struct ItemPlan {
   // those rows (slot_half); gneg[g] is the sphere index of -G
   int half = 0;
   std::vector<int32_t> slot_half, hrow, gneg;
+  // single-launch first-index transform (FP32 slab, small cubic grid, every
+  // disk pencil owned by one of 256 threads); sgroup: slab column-group width
+  int fused = 0, sgroup = 16;
   std::vector<double> coef;    // [n_omega][n_tau]
   std::vector<double> tau;
   const double *phi_o = nullptr, *phi_u = nullptr;
@@ -524,6 +527,12 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
       I.planes = fft_planes(I.n0, I.n1, I.n2, ec);
       I.fft_lds = fft_lds_bytes(I.n1, I.n2, I.cols, I.planes, ec) + 4 * I.n_disk;
     }
+    // (complex orbitals only: for packed real columns the two-launch path
+    // measures faster, its plane blocks skipping the zero triangle plane by
+    // plane and its pencil pass spread over more threads)
+    I.fused = prec != P_FP64 && sigma_states == 0 && !I.pack && I.n0 == I.n1 && I.n1 == I.n2 &&
+              fft_fusable(I.n0) && I.n_disk <= 256;
+    I.sgroup = I.fused ? 1 : I.cols * (I.pack ? 2 : 1);
     I.phi_o = it.phi_occ;
     I.phi_u = it.phi_unocc;
     I.out = it.chi_out;
@@ -574,8 +583,8 @@ gwchi_status build_plan(gwchi_ctx *ctx, const gwchi_item *items, int n_items, in
       const int64_t wmax = std::min<int64_t>(W, I.n_r);
       b[0] = round_up(I.n_r_pad * (I.k_o_pad + I.k_u_pad) * bpb, 256);
       b[1] = sigma_states > 0 ? round_up(round_up(wmax, 128 / ec) * I.n_r * ec, 256)
-                              : round_up(round_up(wmax, I.cols * (I.pack ? 2 : 1)) * I.n_r * es, 256);
-      b[2] = round_up((int64_t)I.n_g * I.n_r * ec, 256);
+                              : round_up(round_up(wmax, I.sgroup) * I.n_r * es, 256);
+      b[2] = round_up(round_up(I.n_g, I.cols) * I.n_r * ec, 256);
       b[3] = round_up((int64_t)I.n0 * I.n_disk * std::max<int64_t>(wmax, I.n_g) * ec, 256);
       b[4] = (int64_t)I.n_g * I.n_g * ec;
       if (sigma_states > 0) {
@@ -682,13 +691,15 @@ struct Built {
 // cubic grids run the kernels specialised for their size.
 void emit_fft(Built &B, const Plan &P, std::vector<FftJob> &jobs, int phase, int sign,
               int in_real, int lower_only, size_t off_geos) {
-  std::map<std::tuple<int, int, int>, std::vector<FftJob>> groups;
+  // key: grid and, for the first index, whether the items take the single launch
+  std::map<std::tuple<int, int, int, int>, std::vector<FftJob>> groups;
   for (auto &f : jobs) {
     const ItemPlan &I = P.items[f.geo];
-    groups[std::make_tuple(I.n0, I.n1, I.n2)].push_back(f);
+    groups[std::make_tuple(I.n0, I.n1, I.n2, phase == PH_FFT_R ? I.fused : 0)].push_back(f);
   }
   for (auto &kv : groups) {
     std::vector<FftJob> &fj = kv.second;
+    const int fused = std::get<3>(kv.first);
     // real column-grouped input of packing items: two columns per transform
     bool packed = in_real != 0;
     for (auto &f : fj) packed = packed && f.s_col == 0 && P.items[f.geo].pack;
@@ -697,6 +708,11 @@ void emit_fft(Built &B, const Plan &P, std::vector<FftJob> &jobs, int phase, int
       const ItemPlan &I = P.items[f.geo];
       f.unit0_planes = up;
       f.unit0_pencils = un;
+      if (fused) {
+        up += f.n_cols;                                    // one unit per column
+        lds = std::max(lds, fused_lds_bytes(I.n0));
+        continue;
+      }
       if (packed) {
         const int n_pc = packed_lines(f.n_cols, I.cols);
         up += (n_pc / I.cols) * ((I.n0 + I.planes - 1) / I.planes);
@@ -718,6 +734,7 @@ void emit_fft(Built &B, const Plan &P, std::vector<FftJob> &jobs, int phase, int
     F.fft.n_units_pencils = un;
     F.fft.in_real = in_real;
     F.fft.packed = packed ? 1 : 0;
+    F.fft.fused = fused;
     F.fft.lower_only = lower_only;
     // the jobs of a launch are all column-grouped or all contiguous along r
     // with unit stride (the two layouts the cubic kernels read; contiguous
@@ -945,7 +962,7 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, const Bases &D, Bu
         g.s0 = (int32_t)s0;
         g.w = w;
         g.cg_shift = 0;
-        while ((1 << (g.cg_shift + 1)) <= I.cols * (I.pack ? 2 : 1)) ++g.cg_shift;
+        while ((1 << (g.cg_shift + 1)) <= I.sgroup) ++g.cg_shift;
         g.slab = slab_base + J.o_slab;
         const int gi = (int)gj.size();
         gj.push_back(g);
@@ -988,6 +1005,9 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, const Bases &D, Bu
         f.n_cols = w;
         f.geo = J.item;
         f.half_rows = I.half;
+        // single launch: rows of chi(G, r') column-grouped for the second index
+        f.o_gshift = 0;
+        while ((1 << (f.o_gshift + 1)) <= I.cols) ++f.o_gshift;
         fj.push_back(f);
       }
       if (gj.empty()) continue;
@@ -1025,7 +1045,7 @@ void build_launches(gwchi_ctx *ctx, Plan &P, bool want_norms, const Bases &D, Bu
         FftJob f{};
         f.in = xr_base + J.o_xr;
         f.s_r = 1;
-        f.s_col = I.n_r;
+        f.s_col = I.fused ? 0 : I.n_r;     // the single launch writes column groups
         f.tmp = tmp_base + J.o_tmp;
         f.out = x_base + J.o_x;
         f.o_slot = I.n_g;

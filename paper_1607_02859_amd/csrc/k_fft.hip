@@ -676,6 +676,185 @@ __global__ __launch_bounds__(256) void k_fft_pencils(FftLaunch L) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Single-launch first-index transform for small cubic grids (complex FP32
+// input): one workgroup per column, whose n^3 points are contiguous in the
+// slab (column groups one column wide).  The i0-planes pass through LDS in batches of
+// PB: a batch arrives by direct global-to-LDS loads into a linear stage while
+// the previous batch is being transformed (the last batch of a line prefetches
+// the first stored batch of the workgroup's next column), is copied into a
+// work area with rows padded to n + 1 points and masked to the stored lower
+// triangle, and is transformed along i2 and i1 there; thread d then takes the
+// values of disk pencil d = (k1, k2) into registers.  After the last batch
+// each thread holds the n0 values of its pencil and transforms them along i0.
+// The pencil scratch of the two-launch path never reaches memory.
+// Output rows are column-grouped, out[((s / X) * n_r + c) * X + s % X] with
+// X = 2^o_gshift, the layout the second-index transform reads.
+// ---------------------------------------------------------------------------
+// global -> LDS, 16 bytes per lane at lds + 16 * lane (lds wave-uniform); the
+// instruction is written out so that the compiler adds no wait of its own for
+// it (the barrier waits below order the stage).  M0 is written one wait state
+// before the load; no other code in these kernels reads M0.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void fft_dma16(const char *g, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+               :
+               : "v"(g), "s"(lds)
+               : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
+// every load of this wave has landed (vmcnt 0), then the workgroup barrier
+__device__ __forceinline__ void fft_wait_loads_barrier() {
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int NC, int SIGN>
+__global__ __launch_bounds__(256, 2) void k_fft_fused(FftLaunch L) {
+  typedef float T;
+  extern __shared__ __attribute__((aligned(1024))) char smem[];
+  constexpr int plane = NC * NC, RP = NC + 1, PP = NC * RP;
+  constexpr int PB = fused_pb(NC), NB = (NC + PB - 1) / PB;
+  constexpr int SB = fused_stage_bytes(NC);
+  static_assert(NC % 2 == 0 && PB * NC <= 256, "two points per 16 bytes, one thread per line");
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const f4 *stage = reinterpret_cast<const f4 *>(smem);
+  cx<T> *work = reinterpret_cast<cx<T> *>(smem + SB);
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const uint32_t lds_stage = __builtin_amdgcn_readfirstlane(
+      (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char *)smem);
+  // a unit: its job, column, first stored row and first batch holding a
+  // stored row (rows above the diagonal of lower-triangle storage read as zero)
+  struct Unit {
+    int job, line, b0;
+    int64_t za;
+  };
+  auto unit = [&](int uu) -> Unit {
+    Unit x;
+    x.job = find_job(L.jobs, L.n_jobs, uu, false);
+    const FftJob &J = L.jobs[x.job];
+    x.line = uu - J.unit0_planes;
+    x.za = L.lower_only ? (int64_t)J.col0 + x.line : 0;
+    x.b0 = 0;
+    while (x.b0 < NB - 1 && (int64_t)(x.b0 * PB + PB) * plane <= x.za) ++x.b0;
+    return x;
+  };
+  // the loads of batch b of a column into the stage: 1 KB per wave
+  // instruction; lanes past the batch read its first bytes again (their
+  // stage bytes are never used)
+  auto issue = [&](const Unit &x, int b) {
+    const FftJob &J = L.jobs[x.job];
+    const char *g = reinterpret_cast<const char *>(reinterpret_cast<const cx<T> *>(J.in) +
+                                                    ((int64_t)x.line * L.geos[J.geo].n_r +
+                                                     (int64_t)b * PB * plane));
+    const int np = NC - b * PB < PB ? NC - b * PB : PB;
+    const int bytes = np * plane * (int)sizeof(cx<T>);
+    for (int c = wv; c < SB / 1024; c += 4) {
+      const int o = c * 1024 + lane * 16;
+      fft_dma16(g + (o < bytes ? o : 0), __builtin_amdgcn_readfirstlane(lds_stage + c * 1024));
+    }
+  };
+  int u = blockIdx.x;
+  Unit cur;
+  if (u < L.n_units_planes) {
+    cur = unit(u);
+    issue(cur, cur.b0);
+  }
+  for (; u < L.n_units_planes; u += gridDim.x) {
+    const FftJob J = L.jobs[cur.job];
+    const Geo G = L.geos[J.geo];
+    const int un = u + (int)gridDim.x;
+    const bool has_next = un < L.n_units_planes;
+    const Unit nxt = has_next ? unit(un) : cur;
+    // thread t owns disk pencil t = (k1, k2)
+    const bool own = tid < G.n_disk;
+    const int i12 = ld_g(G.disk_i12, (int64_t)(own ? tid : 0));
+    const int k1 = i12 / NC, k2 = i12 - k1 * NC;
+    cx<T> zp[NC];
+    sfor<0, NB>([&](auto bb) {
+      constexpr int b = decltype(bb)::value;
+      constexpr int p0 = b * PB;
+      constexpr int np = NC - p0 < PB ? NC - p0 : PB;
+      constexpr int npt = np * plane;
+      if (b < cur.b0) {                                // all above the diagonal
+        sfor<0, np>([&](auto pp) { zp[p0 + decltype(pp)::value] = cx<T>{(T)0, (T)0}; });
+        return;
+      }
+      fft_wait_loads_barrier();                        // batch b is in the stage
+      // stage -> work: padded rows, masked
+      for (int e2 = tid; e2 < npt / 2; e2 += 256) {
+        const int pt = 2 * e2;
+        const int p = pt / plane, rem = pt - p * plane;
+        const int i1 = rem / NC, i2 = rem - i1 * NC;
+        const int64_t r = (int64_t)p0 * plane + pt;
+        const f4 v = stage[e2];
+        cx<T> *dst = work + p * PP + i1 * RP + i2;
+        dst[0] = r >= cur.za ? cx<T>{v.x, v.y} : cx<T>{(T)0, (T)0};
+        dst[1] = r + 1 >= cur.za ? cx<T>{v.z, v.w} : cx<T>{(T)0, (T)0};
+      }
+      __syncthreads();                                 // the stage is free again
+      if (b + 1 < NB) issue(cur, b + 1);
+      else if (has_next) issue(nxt, nxt.b0);
+      if (tid < np * NC) {                             // along i2: line (p, i1)
+        const int p = tid / NC, i1 = tid - p * NC;
+        line_n<NC, SIGN, T>(work + p * PP + i1 * RP, 1);
+      }
+      __syncthreads();
+      if (tid < np * NC) {                             // along i1: line (p, k2)
+        const int p = tid / NC, kk2 = tid - p * NC;
+        line_n<NC, SIGN, T>(work + p * PP + kk2, RP);
+      }
+      __syncthreads();
+      if (own)
+        sfor<0, np>([&](auto pp) {
+          constexpr int p = decltype(pp)::value;
+          zp[p0 + p] = work[p * PP + k1 * RP + k2];
+        });
+      __syncthreads();                                 // work is free again
+    });
+    // along i0
+    cx<T> o[NC];
+    reg_fft<NC, SIGN, T, 1>(zp, o);
+    cx<T> *out = reinterpret_cast<cx<T> *>(J.out);
+    const int gs = J.o_gshift;
+    auto at = [&](int sl, int64_t col) -> int64_t {
+      return ((((int64_t)(sl >> gs)) * G.n_r + col) << gs) + (sl & ((1 << gs) - 1));
+    };
+    if (own) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        const int sl = ld_g(G.slot_of, (int64_t)tid * NC + k);
+        if (sl >= 0) st_g(out, at(sl, (int64_t)J.col0 + cur.line), o[k]);
+      }
+    }
+    cur = nxt;
+  }
+}
+
+template <int SIGN>
+hipError_t launch_fused_t(const FftLaunch &L, int lds_bytes, int n, hipStream_t s) {
+  const void *k;
+  switch (n) {
+    case 12: k = (const void *)k_fft_fused<12, SIGN>; break;
+    case 16: k = (const void *)k_fft_fused<16, SIGN>; break;
+    case 18: k = (const void *)k_fft_fused<18, SIGN>; break;
+    case 20: k = (const void *)k_fft_fused<20, SIGN>; break;
+    case 24: k = (const void *)k_fft_fused<24, SIGN>; break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  if (e != hipSuccess) return e;
+  const int g = L.n_units_planes < 2048 ? L.n_units_planes : 2048;
+  if (g <= 0) return hipSuccess;
+  FftLaunch a = L;
+  void *args[] = {&a};
+  return hipLaunchKernel(k, dim3(g), dim3(256), args, lds_bytes, s);
+}
+
 template <typename T, int S, int NC>
 hipError_t launch_fft_t(const FftLaunch &L, int lds_bytes, hipStream_t s) {
   // plane blocks: a grid of a few resident rounds that strides over the units
@@ -923,6 +1102,10 @@ hipError_t launch_sfft(const SfftLaunch &L, int dbl, int sign, int lds_bytes, hi
 hipError_t launch_fft(const FftLaunch &L, int dbl, int sign, int lds_bytes, int cubic_n,
                       hipStream_t s) {
   if (cubic_n < 0) return hipErrorInvalidValue;   // layouts the planner never mixes
+  if (L.fused) {
+    if (dbl || sign > 0 || L.packed || !fft_fusable(cubic_n)) return hipErrorInvalidValue;
+    return launch_fused_t<-1>(L, lds_bytes, cubic_n, s);
+  }
   const int n = fft_specialised(cubic_n) ? cubic_n : 0;
   if (dbl) return sign < 0 ? launch_fft_n<double, -1>(L, lds_bytes, n, s)
                            : launch_fft_n<double, 1>(L, lds_bytes, n, s);
