@@ -50,7 +50,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_gemm_gamma_complex_24cubed_hbm_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "chi_build_gamma_complex_24cubed_hbm_traffic.md")
 W_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_w_update_sphere24_hbm_traffic.md")
 
 
@@ -69,11 +69,28 @@ def gemm_traffic(kernel_prefix: str, profile: str = TRAFFIC_PROFILE, source: str
     src = os.path.join(ROOT, "paper_1607_02859_amd", "csrc", source)
     if not m or hashlib.sha256(open(src, "rb").read()).hexdigest() != m.group(1):
         return None
+    ird = iwr = None
     for line in txt.splitlines():
-        if line.startswith("| `" + kernel_prefix):
-            cols = [c.strip() for c in line.strip("|").split("|")]
-            return (float(cols[4]) + float(cols[5])) * 1e9
+        cols = [c.strip() for c in line.strip().strip("|").split("|")]
+        if line.startswith("| kernel"):
+            ird = next(i for i, c in enumerate(cols) if "read GB" in c)
+            iwr = next(i for i, c in enumerate(cols) if "write GB" in c)
+        elif ird is not None and line.startswith("| `" + kernel_prefix):
+            return (float(cols[ird]) + float(cols[iwr])) * 1e9
     return None
+
+
+def gemm_kernel_name(prec: str, cplx: bool, tile_id: int) -> str:
+    """Kernel name prefix of GEMM tile tile_id (1-based menu entry, as in the
+    report) of a precision's tile menu in k_gemm.hip."""
+    import re
+    fam = {"fp64": "FP64", "fp32": "FP32", "bf16x3": "BF16"}[prec] + ("_C" if cplx else "_R")
+    src = open(os.path.join(ROOT, "paper_1607_02859_amd", "csrc", "k_gemm.hip")).read()
+    body = re.search(r"#define GW_TILES_" + fam + r"\(X\)(.*?)\n\n", src, re.S).group(1)
+    tiles = re.findall(r"X\(P_\w+, (true|false), (\d+), (\d+), (\d+), (\d+), (\d+)\)", body)
+    c, a, b, k, o, w = tiles[tile_id - 1]
+    p = {"fp64": 0, "fp32": 1, "bf16x3": 2}[prec]
+    return f"void k_gemm<{p}, {c}, {a}, {b}, {k}, {o}, {w}>"
 
 
 def cpu_model() -> str:
@@ -562,8 +579,9 @@ def main():
         "peak": PEAK_TFLOPS[head],
         "unit": "TFLOP/s",
         "frac": achieved / PEAK_TFLOPS[head],
-        "traffic": gemm_traffic("void k_gemm<1, true,") if (head == "fp32" and args.config == 2)
-        else None,
+        "traffic": gemm_traffic(gemm_kernel_name(head, True, H["tile_id"]))
+        if (head == "fp32" and args.config == 2) else None,
+        "tile": gemm_kernel_name(head, item.is_complex, H["tile_id"]),
         "traffic_source": os.path.relpath(TRAFFIC_PROFILE, ROOT),
         "per_launch_flops": per_launch,
         "avg_launch_ms": H["gemm_ms_per_launch"],
