@@ -119,16 +119,17 @@ __global__ __launch_bounds__(256) void k_ct(CtLaunch L, int k0) {
 // Hermitian completion: chi(i w_k) is Hermitian and out(b, a) = conj(out(a, b))^T
 // holds exactly (the same sums with conjugated terms), so one block computes a
 // 32x32 tile on or below the block diagonal and writes it and its mirror.
-// 512 threads: thread (tx, ty) owns (a0 + ty + 16 i, b0 + tx), i = 0, 1, for
-// CH frequencies.  The input tiles of the next PD taus are in flight in
-// registers while the current ones are used from LDS.
+// 1024 threads, thread (tx, ty) owning element (a0 + ty, b0 + tx) for CH
+// frequencies: one element per thread keeps the accumulators to 4 CH
+// registers, so that four waves share each SIMD.  The input tiles of the next
+// PD taus are in flight in registers while the current ones are used from LDS.
 template <typename T, int CH>
-__global__ __launch_bounds__(512) void k_ct_herm(CtLaunch L, int k0) {
+__global__ __launch_bounds__(1024, 4) void k_ct_herm(CtLaunch L, int k0) {
   constexpr int PD = 2;
   __shared__ double2 t1[32][33];     // t1[gp][g] = x_j[b0 + gp][a0 + g] = X[g][g']
   __shared__ double2 t2[32][33];     // t2[g][gp] = x_j[a0 + g][b0 + gp] = X[g'][g]
   const int tid = threadIdx.x;
-  const int tx = tid & 31, ty = tid >> 5;    // ty in [0, 16)
+  const int tx = tid & 31, ty = tid >> 5;    // ty in [0, 32)
   typedef typename std::conditional<sizeof(T) == 8, double2, float2>::type V;
   for (int t = blockIdx.x; t < L.n_tiles; t += gridDim.x) {
     const CtItem it = L.items[find_tile(L.items, L.n_items, t)];
@@ -143,32 +144,26 @@ __global__ __launch_bounds__(512) void k_ct_herm(CtLaunch L, int k0) {
     const int a0 = ta * 32, b0 = tb * 32;
     const int64_t mat = (int64_t)ng * ng;
     const V *x = reinterpret_cast<const V *>(it.x);
-    double2 acc[2][CH];
+    const int g = a0 + ty, gp = b0 + tx;
+    const bool in = g < ng && gp < ng;
+    double2 acc[CH];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int g = a0 + ty + 16 * i, gp = b0 + tx;
-      const bool in = g < ng && gp < ng;
-#pragma unroll
-      for (int k = 0; k < CH; ++k)
-        acc[i][k] = (it.accumulate && in && k0 + k < it.n_omega)
-                        ? reinterpret_cast<const double2 *>(it.out)[(int64_t)(k0 + k) * mat +
-                                                                    (int64_t)g * ng + gp]
-                        : make_double2(0.0, 0.0);
-    }
-    // element q of a 32x32 tile: row q >> 5, column q & 31.  The two input
-    // tiles of tau j + PD are fetched into register slot j % PD while tau j
-    // is used from LDS, so that PD taus of loads are in flight.
-    V r1[PD][2], r2[PD][2];
-    auto fetch = [&](int j, V (&q1)[2], V (&q2)[2]) {
+    for (int k = 0; k < CH; ++k)
+      acc[k] = (it.accumulate && in && k0 + k < it.n_omega)
+                   ? reinterpret_cast<const double2 *>(it.out)[(int64_t)(k0 + k) * mat +
+                                                               (int64_t)g * ng + gp]
+                   : make_double2(0.0, 0.0);
+    // element (row ty, column tx) of each 32x32 input tile; the two tiles of
+    // tau j + PD are fetched into register slot j % PD while tau j is used
+    // from LDS, so that PD taus of loads are in flight
+    V r1[PD], r2[PD];
+    const int g1 = a0 + tx, gp1 = b0 + ty;           // t1: x_j[gp][g]
+    const int g2 = a0 + ty, gp2 = b0 + tx;           // t2: x_j[g][gp]
+    const bool ok1 = g1 < ng && gp1 < ng, ok2 = g2 < ng && gp2 < ng;
+    auto fetch = [&](int j, V &q1, V &q2) {
       const int64_t base = (int64_t)j * mat;
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int e = tid + 512 * q, row = e >> 5, col = e & 31;
-        const int g1 = a0 + col, gp1 = b0 + row;     // t1: x_j[gp][g]
-        q1[q] = (g1 < ng && gp1 < ng) ? x[base + (int64_t)gp1 * ng + g1] : V{0, 0};
-        const int g2 = a0 + row, gp2 = b0 + col;     // t2: x_j[g][gp]
-        q2[q] = (g2 < ng && gp2 < ng) ? x[base + (int64_t)g2 * ng + gp2] : V{0, 0};
-      }
+      q1 = ok1 ? x[base + (int64_t)gp1 * ng + g1] : V{0, 0};
+      q2 = ok2 ? x[base + (int64_t)g2 * ng + gp2] : V{0, 0};
     };
     const int nt = it.n_tau_x;
     sfor<0, PD>([&](auto ss) {
@@ -180,26 +175,18 @@ __global__ __launch_bounds__(512) void k_ct_herm(CtLaunch L, int k0) {
         constexpr int sl = decltype(ss)::value;
         const int j = jb + sl;
         if (j < nt) {
-#pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            const int e = tid + 512 * q, row = e >> 5, col = e & 31;
-            t1[row][col] = make_double2((double)r1[sl][q].x, (double)r1[sl][q].y);
-            t2[row][col] = make_double2((double)r2[sl][q].x, (double)r2[sl][q].y);
-          }
+          t1[ty][tx] = make_double2((double)r1[sl].x, (double)r1[sl].y);
+          t2[ty][tx] = make_double2((double)r2[sl].x, (double)r2[sl].y);
           __syncthreads();
           if (j + PD < nt) fetch(j + PD, r1[sl], r2[sl]);
+          const double2 u = t1[tx][ty], w = t2[ty][tx];
+          const double xr = u.x + w.x, xi = u.y - w.y;
 #pragma unroll
-          for (int i = 0; i < 2; ++i) {
-            const int gl = ty + 16 * i;
-            const double2 u = t1[tx][gl], w = t2[gl][tx];
-            const double xr = u.x + w.x, xi = u.y - w.y;
-#pragma unroll
-            for (int k = 0; k < CH; ++k) {
-              if (k0 + k < it.n_omega) {
-                const double c = it.coef[(int64_t)(k0 + k) * it.n_tau + it.j0 + j];
-                acc[i][k].x += c * xr;
-                acc[i][k].y += c * xi;
-              }
+          for (int k = 0; k < CH; ++k) {
+            if (k0 + k < it.n_omega) {
+              const double c = it.coef[(int64_t)(k0 + k) * it.n_tau + it.j0 + j];
+              acc[k].x += c * xr;
+              acc[k].y += c * xi;
             }
           }
           __syncthreads();
@@ -207,31 +194,21 @@ __global__ __launch_bounds__(512) void k_ct_herm(CtLaunch L, int k0) {
       });
     }
     double2 *out = reinterpret_cast<double2 *>(it.out);
+    if (in) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int g = a0 + ty + 16 * i, gp = b0 + tx;
-      if (g < ng && gp < ng) {
-#pragma unroll
-        for (int k = 0; k < CH; ++k)
-          if (k0 + k < it.n_omega) out[(int64_t)(k0 + k) * mat + (int64_t)g * ng + gp] = acc[i][k];
-      }
+      for (int k = 0; k < CH; ++k)
+        if (k0 + k < it.n_omega) out[(int64_t)(k0 + k) * mat + (int64_t)g * ng + gp] = acc[k];
     }
     if (ta != tb) {
       // mirror tile out[k][b0 + .][a0 + .] = conj(acc)^T, transposed through LDS
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         if (k0 + k >= it.n_omega) break;
-#pragma unroll
-        for (int i = 0; i < 2; ++i) t1[ty + 16 * i][tx] = acc[i][k];   // [g_l][gp_l]
+        t1[ty][tx] = acc[k];                         // [g_l][gp_l]
         __syncthreads();
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const int gpl = ty + 16 * i;
-          const int g = a0 + tx, gp = b0 + gpl;
-          const double2 v = t1[tx][gpl];
-          if (g < ng && gp < ng)
-            out[(int64_t)(k0 + k) * mat + (int64_t)gp * ng + g] = make_double2(v.x, -v.y);
-        }
+        const double2 v = t1[tx][ty];                // element (a0 + tx, b0 + ty)
+        if (a0 + tx < ng && b0 + ty < ng)
+          out[(int64_t)(k0 + k) * mat + (int64_t)(b0 + ty) * ng + a0 + tx] = make_double2(v.x, -v.y);
         __syncthreads();
       }
     }
@@ -294,11 +271,11 @@ hipError_t launch_ct_herm(const CtLaunch &L, int max_omega, hipStream_t s) {
   int k0 = 0;
   while (k0 < max_omega) {
     const int left = max_omega - k0;
-    if (left <= 4) hipLaunchKernelGGL((k_ct_herm<T, 4>), dim3(grid), dim3(512), 0, s, L, k0);
-    else if (left <= 8) hipLaunchKernelGGL((k_ct_herm<T, 8>), dim3(grid), dim3(512), 0, s, L, k0);
-    else if (left <= 12) hipLaunchKernelGGL((k_ct_herm<T, 12>), dim3(grid), dim3(512), 0, s, L, k0);
-    else if (left <= 16) hipLaunchKernelGGL((k_ct_herm<T, 16>), dim3(grid), dim3(512), 0, s, L, k0);
-    else hipLaunchKernelGGL((k_ct_herm<T, 20>), dim3(grid), dim3(512), 0, s, L, k0);
+    if (left <= 4) hipLaunchKernelGGL((k_ct_herm<T, 4>), dim3(grid), dim3(1024), 0, s, L, k0);
+    else if (left <= 8) hipLaunchKernelGGL((k_ct_herm<T, 8>), dim3(grid), dim3(1024), 0, s, L, k0);
+    else if (left <= 12) hipLaunchKernelGGL((k_ct_herm<T, 12>), dim3(grid), dim3(1024), 0, s, L, k0);
+    else if (left <= 16) hipLaunchKernelGGL((k_ct_herm<T, 16>), dim3(grid), dim3(1024), 0, s, L, k0);
+    else hipLaunchKernelGGL((k_ct_herm<T, 20>), dim3(grid), dim3(1024), 0, s, L, k0);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k0 += left <= 4 ? 4 : left <= 8 ? 8 : left <= 12 ? 12 : left <= 16 ? 16 : 20;
