@@ -724,6 +724,35 @@ struct Gemm {
           const int cl = col - job.s0;
           const int sh = job.cg_shift;
           const int64_t cb = ((int64_t)(cl >> sh) * n_r << sh) + (cl & ((1 << sh) - 1));
+          if constexpr (P != P_FP64 && C) {
+            if (sh == 0) {
+              // one-column groups: a lane's values v and v + 1 are adjacent rows of
+              // one column, so they go out as one 16-byte store when both are kept
+              auto val = [&](int v, int row) {
+                const float ore = ao.re[i][j][v], ure = au.re[i][j][v];
+                const float oim = ao.im[i][j][v], uim = au.im[i][j][v];
+                float2 x = make_float2(-(ore * ure + oim * uim), -(oim * ure - ore * uim));
+                if (herm && row == col) x = make_float2(0.5f * x.x, 0.0f);
+                return x;
+              };
+              sfor<0, M::NACC / 2>([&](auto vv) {
+                constexpr int v = 2 * decltype(vv)::value;
+                const int row = r0 + (wr * WTM + i) * M::MB + M::acc_row(l, v);
+                static_assert(M::acc_row(0, v + 1) == M::acc_row(0, v) + 1, "adjacent rows");
+                const bool ok0 = col < cend && row < n_r && !(herm && row < col);
+                const bool ok1 = col < cend && row + 1 < n_r && !(herm && row + 1 < col);
+                const float2 x0 = val(v, row), x1 = val(v + 1, row + 1);
+                float2 *dst = reinterpret_cast<float2 *>(job.slab) + cb + row;
+                if (ok0 && ok1) {
+                  *reinterpret_cast<float4 *>(dst) = make_float4(x0.x, x0.y, x1.x, x1.y);
+                } else {
+                  if (ok0) dst[0] = x0;
+                  if (ok1) dst[1] = x1;
+                }
+              });
+              return;
+            }
+          }
           sfor<0, M::NACC>([&](auto vv) {
             constexpr int v = decltype(vv)::value;
             const int row = r0 + (wr * WTM + i) * M::MB + M::acc_row(l, v);
