@@ -272,7 +272,8 @@ const char *gemm_tile_name(int prec, int cplx, int tile);
 hipError_t launch_fft(const FftLaunch &L, int dbl, int sign, int lds_bytes, int cubic_n,
                       hipStream_t s);
 // sphere-to-grid transform; lds_bytes as fft_lds_bytes + 4 * n_disk for the block shape
-hipError_t launch_sfft(const SfftLaunch &L, int dbl, int sign, int lds_bytes, hipStream_t s);
+hipError_t launch_sfft(const SfftLaunch &L, int dbl, int sign, int lds_bytes, int cubic,
+                       hipStream_t s);
 // self-energy: fused band contractions, products with W~ and the diagonal
 // matrix elements (one tile shape per precision, complex orbitals)
 hipError_t launch_gemm_sigma(const GemmLaunch &L, int prec, int grid, int num_cu, hipStream_t s);

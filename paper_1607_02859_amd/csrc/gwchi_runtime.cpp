@@ -1863,15 +1863,22 @@ struct SLaunch {
   const SigmaRed *red = nullptr;
   const SigmaFin *fin = nullptr;
   int n = 0, max_states = 0, max_omega = 0;
+  int cubic = 0;                  // sphere-to-grid: shared cubic grid edge, or 0
   void *fill_ptr = nullptr;
   int64_t fill_bytes = 0;
 };
 
 // Unit counts of a sphere-to-grid launch: job prefix offsets and totals.
-void sfft_units(std::vector<SfftJob> &jobs, const std::vector<Geo> &geos, SfftLaunch &L) {
+// units of a sphere-to-grid launch; returns the grid edge the jobs share when
+// every grid is cubic and the same (the plane kernel then runs with
+// compile-time line lengths), else 0
+int sfft_units(std::vector<SfftJob> &jobs, const std::vector<Geo> &geos, SfftLaunch &L) {
   int up = 0, un = 0;
+  int cubic = -1;
   for (auto &j : jobs) {
     const Geo &g = geos[j.geo];
+    const int n = (g.n0 == g.n1 && g.n1 == g.n2) ? g.n0 : 0;
+    cubic = cubic < 0 ? n : (cubic == n ? n : 0);
     j.unit0_pencils = un;
     j.unit0_planes = up;
     un += g.n_disk * ((j.n_cols + 255) / 256);
@@ -1879,6 +1886,7 @@ void sfft_units(std::vector<SfftJob> &jobs, const std::vector<Geo> &geos, SfftLa
   }
   L.n_units_pencils = un;
   L.n_units_planes = up;
+  return cubic < 0 ? 0 : cubic;
 }
 
 gwchi_status run_sigma(gwchi_ctx *ctx, const gwchi_sigma_item *items, int n_items, int prec,
@@ -2034,7 +2042,7 @@ gwchi_status run_sigma(gwchi_ctx *ctx, const gwchi_sigma_item *items, int n_item
       S.phase = SP_FFT;
       S.kind = 7;
       S.sign = -1;
-      sfft_units(fj, geos, S.sfft);
+      S.cubic = sfft_units(fj, geos, S.sfft);
       S.sfft.jobs = reinterpret_cast<const SfftJob *>(blob.addv(fj));
       S.sfft.n_jobs = (int)fj.size();
       S.sfft.geos = reinterpret_cast<const Geo *>(off_geos);
@@ -2117,7 +2125,7 @@ gwchi_status run_sigma(gwchi_ctx *ctx, const gwchi_sigma_item *items, int n_item
         S.phase = SP_FFT;
         S.kind = 7;
         S.sign = +1;
-        sfft_units(fj, geos, S.sfft);
+        S.cubic = sfft_units(fj, geos, S.sfft);
         S.sfft.jobs = reinterpret_cast<const SfftJob *>(blob.addv(fj));
         S.sfft.n_jobs = (int)fj.size();
         S.sfft.geos = reinterpret_cast<const Geo *>(off_geos);
@@ -2255,7 +2263,7 @@ gwchi_status run_sigma(gwchi_ctx *ctx, const gwchi_sigma_item *items, int n_item
         HIPCHK(launch_sigma_states(S.phi_o, S.phi_u, S.states, S.n_states, S.n_occ, S.n_r,
                                    S.n_r_pad, dbl, S.out, sm));
         break;
-      case 7: HIPCHK(launch_sfft(S.sfft, dbl, S.sign, lds, sm)); break;
+      case 7: HIPCHK(launch_sfft(S.sfft, dbl, S.sign, lds, S.cubic, sm)); break;
       case 8: HIPCHK(launch_gemm_sigma(S.gemm, prec, 0, ctx->num_cu, sm)); break;
       case 9: HIPCHK(launch_sigma_reduce(S.red, S.n, S.max_states, sm)); break;
       case 10: HIPCHK(launch_sigma_final(S.fin, S.n, S.max_states, S.max_omega, sm)); break;

@@ -979,7 +979,8 @@ __global__ __launch_bounds__(256) void k_sfft_pencils(SfftLaunch L) {
 
 // A block owns C adjacent columns x P i0-planes (the plane-block shape of the
 // forward transform), in LDS as [p][i1][i2][column] with padded columns.
-template <typename T, int SIGN>
+// NC > 0: cubic NC^3 grid, line transforms inlined at compile-time length
+template <typename T, int SIGN, int NC>
 __global__ __launch_bounds__(256) void k_sfft_planes(SfftLaunch L) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   cx<T> *buf = reinterpret_cast<cx<T> *>(smem);
@@ -1020,14 +1021,16 @@ __global__ __launch_bounds__(256) void k_sfft_planes(SfftLaunch L) {
     for (int ln = tid; ln < np * n2 * C; ln += 256) {
       const int cc = ln % C, rest = ln / C;
       const int p = rest / n2, k2 = rest - p * n2;
-      line_fft<SIGN, T>(buf + lds_idx(p, 0, k2, cc, n1, n2, C), n2 * (C + 1), n1);
+      if constexpr (NC > 0) line_n<NC, SIGN, T>(buf + lds_idx(p, 0, k2, cc, n1, n2, C), n2 * (C + 1));
+      else line_fft<SIGN, T>(buf + lds_idx(p, 0, k2, cc, n1, n2, C), n2 * (C + 1), n1);
     }
     __syncthreads();
     // along axis 2: lines (p, i1, cc), stride C + 1
     for (int ln = tid; ln < np * n1 * C; ln += 256) {
       const int cc = ln % C, rest = ln / C;
       const int p = rest / n1, i1 = rest - p * n1;
-      line_fft<SIGN, T>(buf + lds_idx(p, i1, 0, cc, n1, n2, C), C + 1, n2);
+      if constexpr (NC > 0) line_n<NC, SIGN, T>(buf + lds_idx(p, i1, 0, cc, n1, n2, C), C + 1);
+      else line_fft<SIGN, T>(buf + lds_idx(p, i1, 0, cc, n1, n2, C), C + 1, n2);
     }
     __syncthreads();
     // write every grid point of the block
@@ -1065,18 +1068,35 @@ __global__ __launch_bounds__(256) void k_sfft_planes(SfftLaunch L) {
   }
 }
 
+template <typename T, int S, int NC>
+hipError_t launch_sfft_planes(const SfftLaunch &L, int lds_bytes, int g2, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void *)k_sfft_planes<T, S, NC>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_sfft_planes<T, S, NC>), dim3(g2), dim3(256), lds_bytes, s, L);
+  return hipGetLastError();
+}
+
+// cubic: the grid edge shared by every job's geometry (0 if they differ or a
+// grid is not cubic)
 template <typename T, int S>
-hipError_t launch_sfft_t(const SfftLaunch &L, int lds_bytes, hipStream_t s) {
+hipError_t launch_sfft_t(const SfftLaunch &L, int lds_bytes, int cubic, hipStream_t s) {
   const int g1 = L.n_units_pencils < 65536 ? L.n_units_pencils : 65536;
   const int g2 = L.n_units_planes < 2048 ? L.n_units_planes : 2048;
   if (g1 > 0) hipLaunchKernelGGL((k_sfft_pencils<T, S>), dim3(g1), dim3(256), 0, s, L);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void *)k_sfft_planes<T, S>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-  if (e != hipSuccess) return e;
-  if (g2 > 0) hipLaunchKernelGGL((k_sfft_planes<T, S>), dim3(g2), dim3(256), lds_bytes, s, L);
-  return hipGetLastError();
+  if (g2 <= 0) return hipSuccess;
+  switch (cubic) {
+    case 12: return launch_sfft_planes<T, S, 12>(L, lds_bytes, g2, s);
+    case 16: return launch_sfft_planes<T, S, 16>(L, lds_bytes, g2, s);
+    case 18: return launch_sfft_planes<T, S, 18>(L, lds_bytes, g2, s);
+    case 20: return launch_sfft_planes<T, S, 20>(L, lds_bytes, g2, s);
+    case 24: return launch_sfft_planes<T, S, 24>(L, lds_bytes, g2, s);
+    case 28: return launch_sfft_planes<T, S, 28>(L, lds_bytes, g2, s);
+    case 32: return launch_sfft_planes<T, S, 32>(L, lds_bytes, g2, s);
+    default: return launch_sfft_planes<T, S, 0>(L, lds_bytes, g2, s);
+  }
 }
 
 }  // namespace
@@ -1092,11 +1112,13 @@ int fft_supported(int n) {
   }
 }
 
-hipError_t launch_sfft(const SfftLaunch &L, int dbl, int sign, int lds_bytes, hipStream_t s) {
-  if (dbl) return sign < 0 ? launch_sfft_t<double, -1>(L, lds_bytes, s)
-                           : launch_sfft_t<double, 1>(L, lds_bytes, s);
-  return sign < 0 ? launch_sfft_t<float, -1>(L, lds_bytes, s)
-                  : launch_sfft_t<float, 1>(L, lds_bytes, s);
+hipError_t launch_sfft(const SfftLaunch &L, int dbl, int sign, int lds_bytes, int cubic,
+                       hipStream_t s) {
+  if (!fft_specialised(cubic)) cubic = 0;
+  if (dbl) return sign < 0 ? launch_sfft_t<double, -1>(L, lds_bytes, cubic, s)
+                           : launch_sfft_t<double, 1>(L, lds_bytes, cubic, s);
+  return sign < 0 ? launch_sfft_t<float, -1>(L, lds_bytes, cubic, s)
+                  : launch_sfft_t<float, 1>(L, lds_bytes, cubic, s);
 }
 
 hipError_t launch_fft(const FftLaunch &L, int dbl, int sign, int lds_bytes, int cubic_n,
