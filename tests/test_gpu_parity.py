@@ -42,6 +42,12 @@ CASES = {
     "real18": lambda: synth.make_item(108, (18, 18, 18), 6, 30, False, 3, x_min=1.0),
     "cplx20": lambda: synth.make_item(109, (20, 20, 20), 6, 30, True, 3, x_min=1.0),
     "cfg1": lambda: synth.make_config(1)[0],
+    # complex cubic grids of the single-launch first-index FFT (one batch of
+    # planes at 12^3, two batches with a partial one at 18^3), and a slab
+    # narrower than the grid so that several slabs and the lower-triangle
+    # batches at their diagonals are exercised
+    "cplx12": lambda: synth.make_item(115, (12, 12, 12), 5, 27, True, 3, x_min=1.0),
+    "cplx18": lambda: synth.make_item(116, (18, 18, 18), 6, 30, True, 3, x_min=1.0),
 }
 
 _ORACLE = {}
@@ -191,15 +197,17 @@ def test_config2_full_size_sampled_rows(ctx):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("name", ["cplx16", "real18", "cplx20"])
-def test_cubic_hermitian_default(ctx, name, prec):
+@pytest.mark.parametrize("name", ["cplx12", "cplx16", "real18", "cplx18", "cplx20"])
+@pytest.mark.parametrize("slab", [0, 1024])
+def test_cubic_hermitian_default(ctx, name, prec, slab):
     """The default options (Hermitian completion, persistent launch, graph) on
-    the cubic grids with specialised FFT kernels."""
+    the cubic grids with specialised FFT kernels, with the planner's slab
+    width and with 1024-column slabs."""
     it, ref = case(name)
-    ctx.set_options(use_graph=1, hermitian=1, skip_zero_bands=0, slab_width=0, tile_id=0)
+    ctx.set_options(use_graph=1, hermitian=1, skip_zero_bands=0, slab_width=slab, tile_id=0)
     out = ctx.build([it], prec)[0]
     err = oc.rel_frobenius(out, ref)
-    say(f"[cubic-herm] case={name} prec={prec} err={err:.3e}")
+    say(f"[cubic-herm] case={name} prec={prec} slab={slab} err={err:.3e}")
     assert err <= TOL[prec]
 
 
