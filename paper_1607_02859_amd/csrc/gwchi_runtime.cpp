@@ -2116,7 +2116,9 @@ gwchi_status run_sigma(gwchi_ctx *ctx, const gwchi_sigma_item *items, int n_item
             const int qq = (int)(std::min_element(qwork.begin(), qwork.end()) - qwork.begin());
             qunits[qq].insert(qunits[qq].end(), tiles.begin(), tiles.end());
             qwork[qq] += kk * (double)tiles.size();
-            mfma += 8.0 * P.bm * P.bn * kk * (prec == P_BF16X3 ? 3.0 : 1.0) * (double)tiles.size();
+            // FP64: three real products per band in the unoccupied pass
+            mfma += (prec == P_FP64 ? 8.0 * J.k_o_eff + 6.0 * J.k_u_eff : 8.0 * kk) * P.bm * P.bn *
+                    (prec == P_BF16X3 ? 3.0 : 1.0) * (double)tiles.size();
           }
       }
       if (gj.empty()) continue;

@@ -159,14 +159,14 @@ struct Gemm {
   };
 
   // The unoccupied-band pass (the long one) of the FP64 and FP32 complex
-  // polarizability forms the sum of a * conj(b) with three real products
-  // instead of four (the self-energy kernel, short of registers for its
-  // epilogue, keeps four):
+  // polarizability and of the FP64 self-energy forms the sum of a * conj(b)
+  // with three real products instead of four (the FP32 self-energy kernel,
+  // short of registers for its epilogue, measured no faster with three):
   //   S1 += a.re b.re,  S2 += a.im b.im,  S3 += (a.re + a.im)(b.re - b.im),
   //   re = S1 + S2,     im = S3 - S1 + S2.
   // S1 and S2 sit in Acc.re and Acc.im, S3 in an Acc3; the pass ends by
   // combining them, so that two accumulator sets are live in the other pass.
-  static constexpr bool G3 = C && P != P_BF16X3 && !SIG;
+  static constexpr bool G3 = C && (P == P_FP64 || (P == P_FP32 && !SIG));
   struct Acc3 {
     acc_t x[WTM][WTN];
   };
