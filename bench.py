@@ -327,23 +327,21 @@ def bench_pade(ctx, item, args):
     return out
 
 
-def bench_batched(args):
-    """The 32-system batch (configuration 5: real orbitals, 16^3-28^3 grids,
-    16/256 .. 96/1536 bands, gaps 0.1-10 eV, 20 taus, one persistent launch per
-    slab over every (system, tau) job) on every path: tiles autotuned on the
-    six 24^3 systems, one warm-up, then two builds timed with per-launch events
-    (GEMM time) and by the wall clock; error against the oracle on sampled rows
-    of one system of every grid size."""
+def bench_config(args, cfg, sample, tune=None, timed=2, kappa=True):
+    """One more workload configuration on every path, in one persistent launch
+    per slab over all its (item, tau) jobs: GEMM tiles autotuned on the items
+    tune(items) selects (else the menu's default), one warm-up, then `timed`
+    builds timed with per-launch events (GEMM time) and by the wall clock;
+    error against the oracle on the sampled rows [(item, rows)]."""
     import torch
     from paper_1607_02859_amd import gwchi, synth
     dev = torch.device("cuda:0")
-    items = synth.make_config(5)
+    items = synth.make_config(cfg)
     phis = [(torch.from_numpy(it.phi_occ).to(dev), torch.from_numpy(it.phi_unocc).to(dev))
             for it in items]
     outs = [torch.empty((it.n_omega, it.n_g, it.n_g), dtype=torch.complex128, device=dev)
             for it in items]
     alg = sum(synth.algorithmic_flops(it) for it in items)
-    sample = [(0, [0, 5]), (9, [2, 100]), (16, [3, 1700]), (20, [1, 1000]), (31, [7, 4000])]
     refs = None
     if not args.no_check:
         from oracle import chi as oc
@@ -351,27 +349,30 @@ def bench_batched(args):
     ctx = gwchi.Context(0)
     ctx.set_options(use_graph=1, timing=1, hermitian=1, kappa=0)
     stream = torch.cuda.current_stream()
-    out = {"config": {"workload": WORKLOADS[5], "items": len(items)}, "paths": {}}
+    out = {"config": {"workload": WORKLOADS[cfg], "items": len(items)}, "paths": {}}
     for prec in args.precisions.split(","):
-        ctx.autotune([it for it in items if it.n[0] == 24], prec)
+        if tune is not None:
+            ctx.autotune(tune(items), prec)
         ctx.build_device(items, phis, outs, prec, stream=stream, report=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         reps = [ctx.build_device(items, phis, outs, prec, stream=stream, report=True)
-                for _ in range(2)]
+                for _ in range(timed)]
         torch.cuda.synchronize()
-        wall = (time.perf_counter() - t0) / 2
-        gemm_ms = sum(r["ms_gemm"] for r in reps) / 2
+        wall = (time.perf_counter() - t0) / timed
+        gemm_ms = sum(r["ms_gemm"] for r in reps) / timed
         issued = reps[-1]["mfma_flops"] / (gemm_ms * 1e-3) / 1e12
-        p = {"ms_per_step": 1e3 * wall, "tflops": alg / wall / 1e12, "gemm_ms": gemm_ms,
+        p = {"ms_per_step": 1e3 * wall, "ms_per_tau": 1e3 * wall / max(it.n_tau for it in items),
+             "tflops": alg / wall / 1e12, "gemm_ms": gemm_ms,
              "mfma_tflops_issued": issued, "mfma_frac_of_peak": issued / PEAK_TFLOPS[prec],
-             "phase_ms": {k: sum(r[k] for r in reps) / 2
+             "phase_ms": {k: sum(r[k] for r in reps) / timed
                           for k in ("ms_stage", "ms_gemm", "ms_fft_r", "ms_fft_rp", "ms_ct")},
              "tile_id": reps[-1]["tile_id"]}
-        ctx.set_options(kappa=1)
-        p["kappa_F"] = ctx.build_device(items, phis, outs, prec, stream=stream,
-                                        report=True)["kappa_F_max"]
-        ctx.set_options(kappa=0)
+        if kappa:
+            ctx.set_options(kappa=1)
+            p["kappa_F"] = ctx.build_device(items, phis, outs, prec, stream=stream,
+                                            report=True)["kappa_F_max"]
+            ctx.set_options(kappa=0)
         if refs is not None:
             from oracle import chi as oc
             errs = [oc.rel_frobenius(outs[t].cpu().numpy()[:, rows, :], refs[t])
@@ -379,14 +380,27 @@ def bench_batched(args):
             p["err_vs_oracle_sampled_rows"] = max(errs)
             p["within_tol"] = bool(max(errs) <= TOL[prec])
         out["paths"][prec] = p
-        log(f"[bench] batched {prec}: {p['ms_per_step']:.0f} ms/step, {p['tflops']:.1f} TFLOP/s, "
+        log(f"[bench] config {cfg} {prec}: {p['ms_per_step']:.0f} ms/step, {p['tflops']:.1f} TFLOP/s, "
             f"gemm {issued:.1f} TFLOP/s issued ({100 * p['mfma_frac_of_peak']:.0f}% of peak), "
-            f"kappa_F {p['kappa_F']:.2f}, err {p.get('err_vs_oracle_sampled_rows', float('nan')):.2e}")
+            + (f"kappa_F {p['kappa_F']:.2f}, " if "kappa_F" in p else "")
+            + f"err {p.get('err_vs_oracle_sampled_rows', float('nan')):.2e}")
     ctx.close()
+    del phis, outs
+    torch.cuda.empty_cache()
     if "fp64" in out["paths"]:
         for prec, p in out["paths"].items():
             p["speedup_vs_fp64"] = out["paths"]["fp64"]["ms_per_step"] / p["ms_per_step"]
     return out
+
+
+def bench_batched(args):
+    """The 32-system batch (configuration 5: real orbitals, 16^3-28^3 grids,
+    16/256 .. 96/1536 bands, gaps 0.1-10 eV, 20 taus) on every path: tiles
+    autotuned on the six 24^3 systems, two timed builds; sampled rows of one
+    system of every grid size."""
+    return bench_config(args, 5, [(0, [0, 5]), (9, [2, 100]), (16, [3, 1700]), (20, [1, 1000]),
+                                  (31, [7, 4000])],
+                        tune=lambda items: [it for it in items if it.n[0] == 24])
 
 
 def main():
@@ -426,6 +440,10 @@ def main():
     ap.add_argument("--batched", type=int, default=None,
                     help="also time the 32-system batch (configuration 5) on every path, one "
                          "warm-up and two timed builds (default: on for configuration 2)")
+    ap.add_argument("--more-configs", type=int, default=None,
+                    help="also time the 8-k-point batch (configuration 3) and the 32^3 grid "
+                         "(configuration 4) on every path, tiles autotuned on the first item, "
+                         "one warm-up and one timed build (default: on for configuration 2)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -608,6 +626,14 @@ def main():
         args.batched = 1 if args.config == 2 else 0
     if args.batched:
         res["batched"] = bench_batched(args)
+    if args.more_configs is None:
+        args.more_configs = 1 if args.config == 2 else 0
+    if args.more_configs:
+        first = lambda items: items[:1]
+        res["config3"] = bench_config(args, 3, [(0, [0, 700]), (5, [3, 2968])], tune=first,
+                                      timed=1, kappa=False)
+        res["config4"] = bench_config(args, 4, [(0, [1, 7122])], tune=first, timed=1,
+                                      kappa=False)
     print(json.dumps(res), flush=True)
 
 
