@@ -121,13 +121,17 @@ __global__ __launch_bounds__(256) void k_ct(CtLaunch L, int k0) {
 // 32x32 tile on or below the block diagonal and writes it and its mirror.
 // 1024 threads, thread (tx, ty) owning element (a0 + ty, b0 + tx) for CH
 // frequencies: one element per thread keeps the accumulators to 4 CH
-// registers, so that four waves share each SIMD.  The input tiles of the next
-// PD taus are in flight in registers while the current ones are used from LDS.
+// registers, so that four waves share each SIMD.  Per tau the thread needs
+// X[g][g'] = x_j[g'][g] (the transposed tile, through LDS) and X[g'][g] =
+// x_j[g][g'] (its own element, straight from its load).  The transposed tile
+// alternates between two LDS buffers, so that one barrier per tau orders its
+// writes and reads, and the input tiles of the next PD taus are in flight in
+// registers while the current one is used.  The mirror tile is transposed
+// through the same two buffers, one barrier per frequency.
 template <typename T, int CH>
 __global__ __launch_bounds__(1024, 4) void k_ct_herm(CtLaunch L, int k0) {
-  constexpr int PD = 2;
-  __shared__ double2 t1[32][33];     // t1[gp][g] = x_j[b0 + gp][a0 + g] = X[g][g']
-  __shared__ double2 t2[32][33];     // t2[g][gp] = x_j[a0 + g][b0 + gp] = X[g'][g]
+  constexpr int PD = sizeof(T) == 8 || CH > 16 ? 2 : 4;   // within 128 registers
+  __shared__ double2 tt[2][32][33];  // tt[.][gp][g] = x_j[b0 + gp][a0 + g] = X[g][g']
   const int tid = threadIdx.x;
   const int tx = tid & 31, ty = tid >> 5;    // ty in [0, 32)
   typedef typename std::conditional<sizeof(T) == 8, double2, float2>::type V;
@@ -155,10 +159,9 @@ __global__ __launch_bounds__(1024, 4) void k_ct_herm(CtLaunch L, int k0) {
                    : make_double2(0.0, 0.0);
     // element (row ty, column tx) of each 32x32 input tile; the two tiles of
     // tau j + PD are fetched into register slot j % PD while tau j is used
-    // from LDS, so that PD taus of loads are in flight
     V r1[PD], r2[PD];
-    const int g1 = a0 + tx, gp1 = b0 + ty;           // t1: x_j[gp][g]
-    const int g2 = a0 + ty, gp2 = b0 + tx;           // t2: x_j[g][gp]
+    const int g1 = a0 + tx, gp1 = b0 + ty;           // transposed tile: x_j[gp][g]
+    const int g2 = a0 + ty, gp2 = b0 + tx;           // own element: x_j[g][gp]
     const bool ok1 = g1 < ng && gp1 < ng, ok2 = g2 < ng && gp2 < ng;
     auto fetch = [&](int j, V &q1, V &q2) {
       const int64_t base = (int64_t)j * mat;
@@ -175,12 +178,14 @@ __global__ __launch_bounds__(1024, 4) void k_ct_herm(CtLaunch L, int k0) {
         constexpr int sl = decltype(ss)::value;
         const int j = jb + sl;
         if (j < nt) {
-          t1[ty][tx] = make_double2((double)r1[sl].x, (double)r1[sl].y);
-          t2[ty][tx] = make_double2((double)r2[sl].x, (double)r2[sl].y);
+          // buffer j % 2 was last read at tau j - 2, before the barrier of tau j - 1
+          double2(*tb2)[33] = tt[j & 1];
+          tb2[ty][tx] = make_double2((double)r1[sl].x, (double)r1[sl].y);
+          const double wr = (double)r2[sl].x, wi = (double)r2[sl].y;
           __syncthreads();
           if (j + PD < nt) fetch(j + PD, r1[sl], r2[sl]);
-          const double2 u = t1[tx][ty], w = t2[ty][tx];
-          const double xr = u.x + w.x, xi = u.y - w.y;
+          const double2 u = tb2[tx][ty];
+          const double xr = u.x + wr, xi = u.y - wi;
 #pragma unroll
           for (int k = 0; k < CH; ++k) {
             if (k0 + k < it.n_omega) {
@@ -189,7 +194,6 @@ __global__ __launch_bounds__(1024, 4) void k_ct_herm(CtLaunch L, int k0) {
               acc[k].y += c * xi;
             }
           }
-          __syncthreads();
         }
       });
     }
@@ -199,18 +203,23 @@ __global__ __launch_bounds__(1024, 4) void k_ct_herm(CtLaunch L, int k0) {
       for (int k = 0; k < CH; ++k)
         if (k0 + k < it.n_omega) out[(int64_t)(k0 + k) * mat + (int64_t)g * ng + gp] = acc[k];
     }
+    // every read of the tau buffers is done before the mirror reuses them
+    __syncthreads();
     if (ta != tb) {
-      // mirror tile out[k][b0 + .][a0 + .] = conj(acc)^T, transposed through LDS
+      // mirror tile out[k][b0 + .][a0 + .] = conj(acc)^T, transposed through
+      // LDS; frequency k uses buffer k % 2, last read at frequency k - 2,
+      // before the barrier of frequency k - 1
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         if (k0 + k >= it.n_omega) break;
-        t1[ty][tx] = acc[k];                         // [g_l][gp_l]
+        tt[k & 1][ty][tx] = acc[k];                  // [g_l][gp_l]
         __syncthreads();
-        const double2 v = t1[tx][ty];                // element (a0 + tx, b0 + ty)
+        const double2 v = tt[k & 1][tx][ty];         // element (a0 + tx, b0 + ty)
         if (a0 + tx < ng && b0 + ty < ng)
           out[(int64_t)(k0 + k) * mat + (int64_t)(b0 + ty) * ng + a0 + tx] = make_double2(v.x, -v.y);
-        __syncthreads();
       }
+      // the next tile's first tau writes buffer 0
+      __syncthreads();
     }
   }
 }
