@@ -979,33 +979,87 @@ __global__ __launch_bounds__(256) void k_sfft_pencils(SfftLaunch L) {
 
 // A block owns C adjacent columns x P i0-planes (the plane-block shape of the
 // forward transform), in LDS as [p][i1][i2][column] with padded columns.
-// NC > 0: cubic NC^3 grid, line transforms inlined at compile-time length
+// NC > 0: cubic NC^3 grid, line transforms inlined at compile-time length.
+// The blocks are persistent over the units; the pencil values of a block's
+// next unit (the first PF of each thread's share) are loaded into registers
+// while the current unit's transforms and stores run.
 template <typename T, int SIGN, int NC>
 __global__ __launch_bounds__(256) void k_sfft_planes(SfftLaunch L) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   cx<T> *buf = reinterpret_cast<cx<T> *>(smem);
   const int tid = threadIdx.x;
   constexpr int EC = (int)sizeof(cx<T>);
-  for (int u = blockIdx.x; u < L.n_units_planes; u += gridDim.x) {
-    const SfftJob J = L.jobs[find_sjob(L.jobs, L.n_jobs, u, false)];
-    const Geo G = L.geos[J.geo];
-    const int n0 = G.n0, n1 = G.n1, n2 = G.n2;
-    const int C = G.cols, P = G.planes, D = G.n_disk;
-    const int plane = n1 * n2;
-    const int npg = (n0 + P - 1) / P;
+  constexpr int PF = sizeof(T) == 8 ? 2 : 12;
+  // unit u: job index, first column and plane, planes; false for a block
+  // whose rows all lie above its first column (not wanted with lower_only)
+  auto locate = [&](int u, int &ji, int &c0, int &p0, int &np) -> bool {
+    ji = find_sjob(L.jobs, L.n_jobs, u, false);
+    const SfftJob &J = L.jobs[ji];
+    const Geo &G = L.geos[J.geo];
+    const int plane = G.n1 * G.n2;
+    const int npg = (G.n0 + G.planes - 1) / G.planes;
     const int lu = u - J.unit0_planes;
     const int cg = lu / npg, pg = lu - cg * npg;
-    const int c0 = cg * C, p0 = pg * P;
-    const int np = min(P, n0 - p0);
-    // a block whose rows all lie above its first column is not wanted (lower_only)
-    if (L.lower_only && (int64_t)(p0 + np) * plane <= (int64_t)J.col0 + c0) continue;
+    c0 = cg * G.cols;
+    p0 = pg * G.planes;
+    np = min(G.planes, G.n0 - p0);
+    return !(L.lower_only && (int64_t)(p0 + np) * plane <= (int64_t)J.col0 + c0);
+  };
+  auto next_wanted = [&](int u) {
+    int ji, c0, p0, np;
+    while (u < L.n_units_planes && !locate(u, ji, c0, p0, np)) u += gridDim.x;
+    return u;
+  };
+  // the first PF pencil values of this thread in unit u (entry idx = tid + 256 t:
+  // column c0 + idx % C, plane p0 + idx / C / D, disk pencil idx / C % D)
+  cx<T> pre[PF];
+  auto prefetch = [&](int u) {
+    if (u >= L.n_units_planes) return;
+    int ji, c0, p0, np;
+    locate(u, ji, c0, p0, np);
+    const SfftJob &J = L.jobs[ji];
+    const Geo &G = L.geos[J.geo];
+    const int C = G.cols, D = G.n_disk;
+    const cx<T> *tmp = reinterpret_cast<const cx<T> *>(J.tmp);
+    const int n_cols = J.n_cols;
+#pragma unroll
+    for (int t = 0; t < PF; ++t) {
+      const int idx = tid + 256 * t;
+      const int cc = idx % C, rest = idx / C;
+      const int p = rest / D, d = rest - p * D;
+      const int c = c0 + cc;
+      if (idx < np * D * C && c < n_cols)
+        pre[t] = ld_g(tmp, ((int64_t)(p0 + p) * D + d) * n_cols + c);
+    }
+  };
+  int u = next_wanted((int)blockIdx.x);
+  prefetch(u);
+  while (u < L.n_units_planes) {
+    int ji, c0, p0, np;
+    locate(u, ji, c0, p0, np);
+    const SfftJob J = L.jobs[ji];
+    const Geo G = L.geos[J.geo];
+    const int n1 = G.n1, n2 = G.n2;
+    const int C = G.cols, P = G.planes, D = G.n_disk;
+    const int plane = n1 * n2;
     int *s_i12 = reinterpret_cast<int *>(smem + fft_lds_bytes(n1, n2, C, P, EC));
     for (int d = tid; d < D; d += 256) s_i12[d] = G.disk_i12[d];
     for (int idx = tid; idx < np * plane * (C + 1); idx += 256) buf[idx] = cx<T>{(T)0, (T)0};
     __syncthreads();
-    // place the pencils of these planes
+    // place the pencils of these planes: the prefetched ones, then any beyond
     const cx<T> *tmp = reinterpret_cast<const cx<T> *>(J.tmp);
-    for (int idx = tid; idx < np * D * C; idx += 256) {
+#pragma unroll
+    for (int t = 0; t < PF; ++t) {
+      const int idx = tid + 256 * t;
+      const int cc = idx % C, rest = idx / C;
+      const int p = rest / D, d = rest - p * D;
+      if (idx < np * D * C && c0 + cc < J.n_cols) {
+        const int i12 = s_i12[d];
+        const int k1 = i12 / n2, k2 = i12 - k1 * n2;
+        buf[lds_idx(p, k1, k2, cc, n1, n2, C)] = pre[t];
+      }
+    }
+    for (int idx = tid + 256 * PF; idx < np * D * C; idx += 256) {
       const int cc = idx % C, rest = idx / C;
       const int p = rest / D, d = rest - p * D;
       const int c = c0 + cc;
@@ -1017,6 +1071,9 @@ __global__ __launch_bounds__(256) void k_sfft_planes(SfftLaunch L) {
       }
     }
     __syncthreads();
+    // the next unit's pencils are in flight from here to its placement
+    const int un = next_wanted(u + (int)gridDim.x);
+    prefetch(un);
     // along axis 1: lines (p, k2, cc), stride one padded row
     for (int ln = tid; ln < np * n2 * C; ln += 256) {
       const int cc = ln % C, rest = ln / C;
@@ -1065,6 +1122,7 @@ __global__ __launch_bounds__(256) void k_sfft_planes(SfftLaunch L) {
       }
     }
     __syncthreads();
+    u = un;
   }
 }
 
