@@ -16,8 +16,10 @@
 //   FP64   : double2 (complex) / double (real)
 //   FP32   : float2 / float
 //   BF16X3 : per 8-band group, parts [re_hi][re_lo][im_hi][im_lo] x 8 bf16
-//            (complex, 64 B) or [hi][lo] x 8 bf16 (real, 32 B), where
-//            hi = bf16(x) and lo = bf16(x - hi), both round-to-nearest-even.
+//            (complex, 64 B) or [hi][lo] x 8 bf16 (real, 32 B), where, with
+//            x the FP32 operand of the FP32 path, hi = bf16(x) and
+//            lo = bf16(x - hi), both round-to-nearest-even (x - hi is exact
+//            in FP32: hi keeps the leading 8 of x's 24 significand bits).
 #include "common.h"
 
 namespace gw {
@@ -37,9 +39,9 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
 }
 
 // split x into hi + lo, both bf16
-__device__ __forceinline__ void split_bf16(double x, uint16_t &hi, uint16_t &lo) {
-  hi = f32_to_bf16_rne((float)x);
-  lo = f32_to_bf16_rne((float)(x - (double)bf16_to_f32(hi)));
+__device__ __forceinline__ void split_bf16(float x, uint16_t &hi, uint16_t &lo) {
+  hi = f32_to_bf16_rne(x);
+  lo = f32_to_bf16_rne(x - bf16_to_f32(hi));
 }
 
 __global__ __launch_bounds__(256) void k_stage(StageLaunch L) {
@@ -106,8 +108,8 @@ __global__ __launch_bounds__(256) void k_stage(StageLaunch L) {
           for (int e = 0; e < 8; ++e) {
             const double2 v = tile[g * 8 + e][rr];
             const double s = sc[g * 8 + e];
-            split_bf16(v.x * s, hr[e], lr[e]);
-            split_bf16(v.y * s, hi_[e], li[e]);
+            split_bf16((float)(v.x * s), hr[e], lr[e]);
+            split_bf16((float)(v.y * s), hi_[e], li[e]);
           }
           const int64_t row_bytes = (int64_t)op.k_pad * 2 * parts;   // 8 bands * 2 B * parts / 8
           char *dst = out + (int64_t)(r0 + rr) * row_bytes + (int64_t)((k0 / 8) + g) * 16 * parts;
