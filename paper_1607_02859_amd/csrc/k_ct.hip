@@ -34,6 +34,12 @@ __device__ __forceinline__ int find_tile(const CtItem *items, int n, int t) {
   return lo;
 }
 
+// The cosine coefficients of a tile's frequencies, read through the constant
+// address space: the index is the same in every lane, so they load as
+// scalars (no vector registers, and no wait for them holds up the input
+// loads in flight).
+typedef __attribute__((address_space(4))) const double *ct_coef_ptr;
+
 // One block per 32 (G) x 16 (G') output tile; thread (tx, ty) owns the two
 // elements (a0 + ty + 16 i, b0 + tx), i = 0, 1, for CH frequencies.  The
 // stored matrices are transposed, x_j[g'][g], so each tile of x_j is staged
@@ -44,7 +50,8 @@ __global__ __launch_bounds__(256) void k_ct(CtLaunch L, int k0) {
   __shared__ double2 t2[32][17];     // x_j[a0 + .][b0 + .]  = X[g'][g] transposed
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;   // ty in [0, 16)
   for (int t = blockIdx.x; t < L.n_tiles; t += gridDim.x) {
-    const CtItem it = L.items[find_tile(L.items, L.n_items, t)];
+    // the item index is the same in every lane: its fields load as scalars
+    const CtItem it = L.items[__builtin_amdgcn_readfirstlane(find_tile(L.items, L.n_items, t))];
     if (k0 >= it.n_omega) continue;
     const int ng = it.n_g;
     const int ntb = (ng + 15) / 16;
@@ -136,7 +143,8 @@ __global__ __launch_bounds__(1024, 4) void k_ct_herm(CtLaunch L, int k0) {
   const int tx = tid & 31, ty = tid >> 5;    // ty in [0, 32)
   typedef typename std::conditional<sizeof(T) == 8, double2, float2>::type V;
   for (int t = blockIdx.x; t < L.n_tiles; t += gridDim.x) {
-    const CtItem it = L.items[find_tile(L.items, L.n_items, t)];
+    // the item index is the same in every lane: its fields load as scalars
+    const CtItem it = L.items[__builtin_amdgcn_readfirstlane(find_tile(L.items, L.n_items, t))];
     if (k0 >= it.n_omega) continue;
     const int ng = it.n_g;
     const int lt = t - it.tile0;
@@ -157,6 +165,9 @@ __global__ __launch_bounds__(1024, 4) void k_ct_herm(CtLaunch L, int k0) {
                    ? reinterpret_cast<const double2 *>(it.out)[(int64_t)(k0 + k) * mat +
                                                                (int64_t)g * ng + gp]
                    : make_double2(0.0, 0.0);
+    // those loads have landed: no wait for them stays in the tau loop (where
+    // it would also wait for the input loads in flight)
+    __builtin_amdgcn_s_waitcnt(0);
     // element (row ty, column tx) of each 32x32 input tile; the two tiles of
     // tau j + PD are fetched into register slot j % PD while tau j is used
     V r1[PD], r2[PD];
@@ -169,6 +180,7 @@ __global__ __launch_bounds__(1024, 4) void k_ct_herm(CtLaunch L, int k0) {
       q2 = ok2 ? x[base + (int64_t)g2 * ng + gp2] : V{0, 0};
     };
     const int nt = it.n_tau_x;
+    const ct_coef_ptr cf = (ct_coef_ptr)(it.coef + (int64_t)k0 * it.n_tau + it.j0);
     sfor<0, PD>([&](auto ss) {
       constexpr int sl = decltype(ss)::value;
       if (sl < nt) fetch(sl, r1[sl], r2[sl]);
@@ -189,7 +201,7 @@ __global__ __launch_bounds__(1024, 4) void k_ct_herm(CtLaunch L, int k0) {
 #pragma unroll
           for (int k = 0; k < CH; ++k) {
             if (k0 + k < it.n_omega) {
-              const double c = it.coef[(int64_t)(k0 + k) * it.n_tau + it.j0 + j];
+              const double c = cf[(int64_t)k * it.n_tau + j];
               acc[k].x += c * xr;
               acc[k].y += c * xi;
             }
@@ -219,6 +231,150 @@ __global__ __launch_bounds__(1024, 4) void k_ct_herm(CtLaunch L, int k0) {
           out[(int64_t)(k0 + k) * mat + (int64_t)(b0 + ty) * ng + a0 + tx] = make_double2(v.x, -v.y);
       }
       // the next tile's first tau writes buffer 0
+      __syncthreads();
+    }
+  }
+}
+
+// FP32 inputs (the FP32 and split-BF16 paths): the same tiles, sums and
+// mirror as k_ct_herm, with the input tiles of the coming taus loaded
+// straight into a ring of R LDS stages instead of registers, so that R - 1
+// taus (17 KB each) are in flight per block against the two of the register
+// form.  A stage holds the transposed tile (rows x_j[b0 + r][a0 + .]) and the
+// block's own tile (rows x_j[a0 + r][b0 + .]), 32 rows each of 32 complex
+// values, one 256-byte wave load per row, rows padded to 272 bytes so that
+// the column-wise reads of the transposed tile spread over the banks.  Rows
+// and columns past n_g load a clamped valid address; they only feed outputs
+// that are never stored.
+// The loads are written out (global to LDS, 4 bytes per lane, M0 holding the
+// wave's LDS row, written one wait state before the load) so that the
+// compiler adds no wait of its own for them; the ring's waits order the
+// stages: stage j is read after the vmcnt wait and barrier that cover its
+// loads and refilled only after the barrier that follows its last reads.  No
+// other code in this kernel reads M0.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void ct_dma4(const float *g, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dword %0, off"
+               :
+               : "v"(g), "s"(lds)
+               : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
+// at most N vector-memory operations of this wave in flight, then the
+// workgroup barrier (no fence: later stages' loads stay in flight)
+template <int N>
+__device__ __forceinline__ void ct_wait_barrier() {
+  static_assert(N >= 0 && N < 64, "vmcnt has 6 bits");
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int CH>
+__global__ __launch_bounds__(1024, 4) void k_ct_herm_ring(CtLaunch L, int k0) {
+  constexpr int R = 6;                       // stages
+  constexpr int ROWB = 272;                  // 32 complex FP32 + 16 bytes of padding
+  constexpr int STG = 64 * ROWB;             // transposed tile, then own tile
+  constexpr int QW = 4;                      // row loads per wave per stage
+  static_assert(R >= 2 && R - 2 <= 5 && QW * (R - 2) < 64, "waits cover the ring");
+  __shared__ __attribute__((aligned(16))) char ring[R * STG];
+  __shared__ double2 tt[2][32][33];          // mirror transposes
+  const int tid = threadIdx.x;
+  const int tx = tid & 31, ty = tid >> 5;    // ty in [0, 32)
+  const int wv = tid >> 6, lane = tid & 63;
+  const uint32_t lds_ring = __builtin_amdgcn_readfirstlane(
+      (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char *)ring);
+  for (int t = blockIdx.x; t < L.n_tiles; t += gridDim.x) {
+    // the item index is the same in every lane: its fields load as scalars
+    const CtItem it = L.items[__builtin_amdgcn_readfirstlane(find_tile(L.items, L.n_items, t))];
+    if (k0 >= it.n_omega) continue;
+    const int ng = it.n_g;
+    const int lt = t - it.tile0;
+    int ta = (int)((sqrt(8.0 * lt + 1.0) - 1.0) * 0.5);
+    while ((ta + 1) * (ta + 2) / 2 <= lt) ++ta;
+    while (ta * (ta + 1) / 2 > lt) --ta;
+    const int tb = lt - ta * (ta + 1) / 2;
+    const int a0 = ta * 32, b0 = tb * 32;
+    const int64_t mat = (int64_t)ng * ng;
+    const int g = a0 + ty, gp = b0 + tx;
+    const bool in = g < ng && gp < ng;
+    double2 acc[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k)
+      acc[k] = (it.accumulate && in && k0 + k < it.n_omega)
+                   ? reinterpret_cast<const double2 *>(it.out)[(int64_t)(k0 + k) * mat +
+                                                               (int64_t)g * ng + gp]
+                   : make_double2(0.0, 0.0);
+    // those loads have landed: no wait for them stays in the tau loop (where
+    // it would also wait for the input loads in flight)
+    __builtin_amdgcn_s_waitcnt(0);
+    // this wave's rows of a stage: q = 0, 1 transposed-tile rows 2 wv + q,
+    // q = 2, 3 own-tile rows 2 wv + q - 2; lane = 2 * column + (re, im)
+    // (offsets formed at each issue: registers go to the accumulators)
+    const float *xf = reinterpret_cast<const float *>(it.x);
+    const int nt = it.n_tau_x;
+    const ct_coef_ptr cf = (ct_coef_ptr)(it.coef + (int64_t)k0 * it.n_tau + it.j0);
+    auto issue = [&](int j) {
+      const float *xj = xf + (int64_t)j * mat * 2;
+      const uint32_t sb = lds_ring + (uint32_t)((j % R) * STG);
+#pragma unroll
+      for (int q = 0; q < QW; ++q) {
+        const int r = 2 * wv + (q & 1);
+        const bool own = q >= 2;
+        const int row = min((own ? a0 : b0) + r, ng - 1);
+        const int col = min((own ? b0 : a0) + (lane >> 1), ng - 1);
+        const int64_t off = ((int64_t)row * ng + col) * 2 + (lane & 1);
+        ct_dma4(xj + off, __builtin_amdgcn_readfirstlane(sb + (uint32_t)((own ? 32 + r : r) * ROWB)));
+      }
+    };
+    for (int j = 0; j < R - 1 && j < nt; ++j) issue(j);
+    for (int j = 0; j < nt; ++j) {
+      // stage j has landed in every wave; the stages issued after it
+      // (min(R - 2, nt - 1 - j) of them) may still be in flight
+      switch (min(R - 2, nt - 1 - j)) {
+        case 0: ct_wait_barrier<0>(); break;
+        case 1: ct_wait_barrier<QW>(); break;
+        case 2: ct_wait_barrier<2 * QW>(); break;
+        case 3: ct_wait_barrier<3 * QW>(); break;
+        default: ct_wait_barrier<4 * QW>(); break;
+      }
+      // refill the stage of tau j - 1, which every wave finished before this barrier
+      if (j + R - 1 < nt) issue(j + R - 1);
+      const char *st = ring + (j % R) * STG;
+      const float2 u = *reinterpret_cast<const float2 *>(st + tx * ROWB + ty * 8);
+      const float2 w = *reinterpret_cast<const float2 *>(st + (32 + ty) * ROWB + tx * 8);
+      const double xr = (double)u.x + (double)w.x, xi = (double)u.y - (double)w.y;
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        if (k0 + k < it.n_omega) {
+          const double c = cf[(int64_t)k * it.n_tau + j];
+          acc[k].x += c * xr;
+          acc[k].y += c * xi;
+        }
+      }
+    }
+    double2 *out = reinterpret_cast<double2 *>(it.out);
+    if (in) {
+#pragma unroll
+      for (int k = 0; k < CH; ++k)
+        if (k0 + k < it.n_omega) out[(int64_t)(k0 + k) * mat + (int64_t)g * ng + gp] = acc[k];
+    }
+    // every read of the ring is done before the next tile refills it
+    __syncthreads();
+    if (ta != tb) {
+      // mirror tile out[k][b0 + .][a0 + .] = conj(acc)^T through alternating buffers
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        if (k0 + k >= it.n_omega) break;
+        tt[k & 1][ty][tx] = acc[k];
+        __syncthreads();
+        const double2 v = tt[k & 1][tx][ty];
+        if (a0 + tx < ng && b0 + ty < ng)
+          out[(int64_t)(k0 + k) * mat + (int64_t)(b0 + ty) * ng + a0 + tx] = make_double2(v.x, -v.y);
+      }
       __syncthreads();
     }
   }
@@ -274,17 +430,25 @@ __global__ __launch_bounds__(256) void k_fill_zero(uint4 *p, int64_t n16, char *
   if (blockIdx.x == 0 && (int)threadIdx.x < tail_n) tail[threadIdx.x] = 0;
 }
 
+template <typename T, int CH>
+void launch_ct_herm_ch(const CtLaunch &L, int grid, int k0, hipStream_t s) {
+  if constexpr (sizeof(T) == 4)
+    hipLaunchKernelGGL((k_ct_herm_ring<CH>), dim3(grid), dim3(1024), 0, s, L, k0);
+  else
+    hipLaunchKernelGGL((k_ct_herm<T, CH>), dim3(grid), dim3(1024), 0, s, L, k0);
+}
+
 template <typename T>
 hipError_t launch_ct_herm(const CtLaunch &L, int max_omega, hipStream_t s) {
   const int grid = L.n_tiles < 65536 ? L.n_tiles : 65536;
   int k0 = 0;
   while (k0 < max_omega) {
     const int left = max_omega - k0;
-    if (left <= 4) hipLaunchKernelGGL((k_ct_herm<T, 4>), dim3(grid), dim3(1024), 0, s, L, k0);
-    else if (left <= 8) hipLaunchKernelGGL((k_ct_herm<T, 8>), dim3(grid), dim3(1024), 0, s, L, k0);
-    else if (left <= 12) hipLaunchKernelGGL((k_ct_herm<T, 12>), dim3(grid), dim3(1024), 0, s, L, k0);
-    else if (left <= 16) hipLaunchKernelGGL((k_ct_herm<T, 16>), dim3(grid), dim3(1024), 0, s, L, k0);
-    else hipLaunchKernelGGL((k_ct_herm<T, 20>), dim3(grid), dim3(1024), 0, s, L, k0);
+    if (left <= 4) launch_ct_herm_ch<T, 4>(L, grid, k0, s);
+    else if (left <= 8) launch_ct_herm_ch<T, 8>(L, grid, k0, s);
+    else if (left <= 12) launch_ct_herm_ch<T, 12>(L, grid, k0, s);
+    else if (left <= 16) launch_ct_herm_ch<T, 16>(L, grid, k0, s);
+    else launch_ct_herm_ch<T, 20>(L, grid, k0, s);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k0 += left <= 4 ? 4 : left <= 8 ? 8 : left <= 12 ? 12 : left <= 16 ? 16 : 20;
