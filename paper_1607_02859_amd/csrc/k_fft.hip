@@ -88,6 +88,14 @@ __device__ __forceinline__ void st_g(cx<T> *p, int64_t i, cx<T> v) {
   ((__attribute__((address_space(1))) v2 *)p)[i] = v2{v.x, v.y};
 }
 
+// A record every lane reads at the same index, through the constant address
+// space: it loads as scalars, so no vector-memory wait for it also waits for
+// the loads of later data already in flight.
+template <typename R>
+__device__ __forceinline__ R ld_c(const R *p, int i) {
+  return ((const __attribute__((address_space(4))) R *)p)[i];
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) {
   return {a.x + b.x, a.y + b.y};
@@ -242,10 +250,13 @@ __device__ __forceinline__ int lds_idx(int p, int i1, int i2, int cc, int n1, in
 }
 
 __device__ __forceinline__ int find_job(const FftJob *jobs, int n, int u, bool pencils) {
+  // u is the same in every lane: the table reads go through the constant
+  // address space (scalar loads)
+  const __attribute__((address_space(4))) FftJob *cj = (const __attribute__((address_space(4))) FftJob *)jobs;
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    const int u0 = pencils ? jobs[mid].unit0_pencils : jobs[mid].unit0_planes;
+    const int u0 = pencils ? cj[mid].unit0_pencils : cj[mid].unit0_planes;
     if (u0 <= u) lo = mid;
     else hi = mid - 1;
   }
@@ -261,8 +272,8 @@ __global__ __launch_bounds__(256) void k_fft_planes(FftLaunch L) {
   const int tid = threadIdx.x;
   constexpr int EC = (int)sizeof(cx<T>);
   for (int u = blockIdx.x; u < L.n_units_planes; u += gridDim.x) {
-    const FftJob J = L.jobs[find_job(L.jobs, L.n_jobs, u, false)];
-    const Geo G = L.geos[J.geo];
+    const FftJob J = ld_c(L.jobs, __builtin_amdgcn_readfirstlane(find_job(L.jobs, L.n_jobs, u, false)));
+    const Geo G = ld_c(L.geos, J.geo);
     const int n0 = G.n0, n1 = G.n1, n2 = G.n2;
     const int C = G.cols;
     const int P = G.planes;
@@ -394,8 +405,8 @@ void k_fft_planes_c(FftLaunch L) {
   const int cc = tid % C, ln = tid / C;
   const int a = ln % NC, p = ln / NC;      // step 1: a = i1; step 2: a = k2
   for (int u = blockIdx.x; u < L.n_units_planes; u += gridDim.x) {
-    const FftJob J = L.jobs[find_job(L.jobs, L.n_jobs, u, false)];
-    const Geo G = L.geos[J.geo];
+    const FftJob J = ld_c(L.jobs, __builtin_amdgcn_readfirstlane(find_job(L.jobs, L.n_jobs, u, false)));
+    const Geo G = ld_c(L.geos, J.geo);
     const int D = G.n_disk;
     const int lu = u - J.unit0_planes;
     const int cg = lu / npg, pg = lu - cg * npg;
@@ -627,8 +638,8 @@ __device__ __forceinline__ void pencil_pk_n(const FftJob &J, const Geo &G, int d
 template <typename T, int SIGN, int NC>
 __global__ __launch_bounds__(256) void k_fft_pencils(FftLaunch L) {
   for (int u = blockIdx.x; u < L.n_units_pencils; u += gridDim.x) {
-    const FftJob J = L.jobs[find_job(L.jobs, L.n_jobs, u, true)];
-    const Geo G = L.geos[J.geo];
+    const FftJob J = ld_c(L.jobs, __builtin_amdgcn_readfirstlane(find_job(L.jobs, L.n_jobs, u, true)));
+    const Geo G = ld_c(L.geos, J.geo);
     if (L.packed) {
       // units: (mirror pair q, 256 packed lines)
       const int n_pc = packed_lines(J.n_cols, G.cols);
@@ -735,8 +746,8 @@ __global__ __launch_bounds__(256, 2) void k_fft_fused(FftLaunch L) {
   };
   auto unit = [&](int uu) -> Unit {
     Unit x;
-    x.job = find_job(L.jobs, L.n_jobs, uu, false);
-    const FftJob &J = L.jobs[x.job];
+    x.job = __builtin_amdgcn_readfirstlane(find_job(L.jobs, L.n_jobs, uu, false));
+    const FftJob J = ld_c(L.jobs, x.job);
     x.line = uu - J.unit0_planes;
     x.za = L.lower_only ? (int64_t)J.col0 + x.line : 0;
     x.b0 = 0;
@@ -747,9 +758,9 @@ __global__ __launch_bounds__(256, 2) void k_fft_fused(FftLaunch L) {
   // instruction; lanes past the batch read its first bytes again (their
   // stage bytes are never used)
   auto issue = [&](const Unit &x, int b) {
-    const FftJob &J = L.jobs[x.job];
+    const FftJob J = ld_c(L.jobs, x.job);
     const char *g = reinterpret_cast<const char *>(reinterpret_cast<const cx<T> *>(J.in) +
-                                                    ((int64_t)x.line * L.geos[J.geo].n_r +
+                                                    ((int64_t)x.line * ld_c(L.geos, J.geo).n_r +
                                                      (int64_t)b * PB * plane));
     const int np = NC - b * PB < PB ? NC - b * PB : PB;
     const int bytes = np * plane * (int)sizeof(cx<T>);
@@ -765,15 +776,20 @@ __global__ __launch_bounds__(256, 2) void k_fft_fused(FftLaunch L) {
     issue(cur, cur.b0);
   }
   for (; u < L.n_units_planes; u += gridDim.x) {
-    const FftJob J = L.jobs[cur.job];
-    const Geo G = L.geos[J.geo];
+    const FftJob J = ld_c(L.jobs, cur.job);
+    const Geo G = ld_c(L.geos, J.geo);
     const int un = u + (int)gridDim.x;
     const bool has_next = un < L.n_units_planes;
     const Unit nxt = has_next ? unit(un) : cur;
-    // thread t owns disk pencil t = (k1, k2)
+    // thread t owns disk pencil t = (k1, k2); its output slots are loaded
+    // now, in flight with the column's first batch, and not one by one
+    // between the stores at the end
     const bool own = tid < G.n_disk;
     const int i12 = ld_g(G.disk_i12, (int64_t)(own ? tid : 0));
     const int k1 = i12 / NC, k2 = i12 - k1 * NC;
+    int slot[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) slot[k] = ld_g(G.slot_of, (int64_t)(own ? tid : 0) * NC + k);
     cx<T> zp[NC];
     sfor<0, NB>([&](auto bb) {
       constexpr int b = decltype(bb)::value;
@@ -826,10 +842,8 @@ __global__ __launch_bounds__(256, 2) void k_fft_fused(FftLaunch L) {
     };
     if (own) {
 #pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        const int sl = ld_g(G.slot_of, (int64_t)tid * NC + k);
-        if (sl >= 0) st_g(out, at(sl, (int64_t)J.col0 + cur.line), o[k]);
-      }
+      for (int k = 0; k < NC; ++k)
+        if (slot[k] >= 0) st_g(out, at(slot[k], (int64_t)J.col0 + cur.line), o[k]);
     }
     cur = nxt;
   }
@@ -917,10 +931,12 @@ __device__ __forceinline__ cx<T> ld_in(const SfftLaunch &L, const SfftJob &J, in
 }
 
 __device__ __forceinline__ int find_sjob(const SfftJob *jobs, int n, int u, bool pencils) {
+  // u is the same in every lane: scalar loads, as in find_job
+  const __attribute__((address_space(4))) SfftJob *cj = (const __attribute__((address_space(4))) SfftJob *)jobs;
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    const int u0 = pencils ? jobs[mid].unit0_pencils : jobs[mid].unit0_planes;
+    const int u0 = pencils ? cj[mid].unit0_pencils : cj[mid].unit0_planes;
     if (u0 <= u) lo = mid;
     else hi = mid - 1;
   }
@@ -957,8 +973,8 @@ __device__ __forceinline__ void spencil_n(const SfftLaunch &L, const SfftJob &J,
 template <typename T, int SIGN>
 __global__ __launch_bounds__(256) void k_sfft_pencils(SfftLaunch L) {
   for (int u = blockIdx.x; u < L.n_units_pencils; u += gridDim.x) {
-    const SfftJob J = L.jobs[find_sjob(L.jobs, L.n_jobs, u, true)];
-    const Geo G = L.geos[J.geo];
+    const SfftJob J = ld_c(L.jobs, __builtin_amdgcn_readfirstlane(find_sjob(L.jobs, L.n_jobs, u, true)));
+    const Geo G = ld_c(L.geos, J.geo);
     const int nch = (J.n_cols + 255) / 256;
     const int lu = u - J.unit0_pencils;
     const int d = lu / nch, ch = lu - d * nch;
@@ -993,9 +1009,9 @@ __global__ __launch_bounds__(256) void k_sfft_planes(SfftLaunch L) {
   // unit u: job index, first column and plane, planes; false for a block
   // whose rows all lie above its first column (not wanted with lower_only)
   auto locate = [&](int u, int &ji, int &c0, int &p0, int &np) -> bool {
-    ji = find_sjob(L.jobs, L.n_jobs, u, false);
-    const SfftJob &J = L.jobs[ji];
-    const Geo &G = L.geos[J.geo];
+    ji = __builtin_amdgcn_readfirstlane(find_sjob(L.jobs, L.n_jobs, u, false));
+    const SfftJob J = ld_c(L.jobs, ji);
+    const Geo G = ld_c(L.geos, J.geo);
     const int plane = G.n1 * G.n2;
     const int npg = (G.n0 + G.planes - 1) / G.planes;
     const int lu = u - J.unit0_planes;
@@ -1017,8 +1033,8 @@ __global__ __launch_bounds__(256) void k_sfft_planes(SfftLaunch L) {
     if (u >= L.n_units_planes) return;
     int ji, c0, p0, np;
     locate(u, ji, c0, p0, np);
-    const SfftJob &J = L.jobs[ji];
-    const Geo &G = L.geos[J.geo];
+    const SfftJob J = ld_c(L.jobs, ji);
+    const Geo G = ld_c(L.geos, J.geo);
     const int C = G.cols, D = G.n_disk;
     const cx<T> *tmp = reinterpret_cast<const cx<T> *>(J.tmp);
     const int n_cols = J.n_cols;
@@ -1037,8 +1053,8 @@ __global__ __launch_bounds__(256) void k_sfft_planes(SfftLaunch L) {
   while (u < L.n_units_planes) {
     int ji, c0, p0, np;
     locate(u, ji, c0, p0, np);
-    const SfftJob J = L.jobs[ji];
-    const Geo G = L.geos[J.geo];
+    const SfftJob J = ld_c(L.jobs, ji);
+    const Geo G = ld_c(L.geos, J.geo);
     const int n1 = G.n1, n2 = G.n2;
     const int C = G.cols, P = G.planes, D = G.n_disk;
     const int plane = n1 * n2;
