@@ -92,8 +92,15 @@ __device__ __forceinline__ void st_g(cx<T> *p, int64_t i, cx<T> v) {
 // space: it loads as scalars, so no vector-memory wait for it also waits for
 // the loads of later data already in flight.
 template <typename R>
-__device__ __forceinline__ R ld_c(const R *p, int i) {
-  return ((const __attribute__((address_space(4))) R *)p)[i];
+__device__ __forceinline__ R ld_c(const R *p, int64_t i) {
+  static_assert(sizeof(R) % 4 == 0, "whole words");
+  typedef const __attribute__((address_space(4))) uint32_t cw;
+  cw *w = (cw *)(p + i);
+  R r;
+  uint32_t *d = reinterpret_cast<uint32_t *>(&r);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(R) / 4); ++k) d[k] = w[k];
+  return r;
 }
 
 template <typename T>
