@@ -95,6 +95,21 @@ __device__ __forceinline__ uint4 neg_bf8(uint4 q) {
   return q;
 }
 
+// A record every lane reads at the same index, through the constant address
+// space, word by word: it loads as scalars (no vector registers held, and no
+// vector-memory wait for it also waits for the previous tile's stores).
+template <typename R>
+__device__ __forceinline__ R ld_c(const R *p, int64_t i) {
+  static_assert(sizeof(R) % 4 == 0, "whole words");
+  typedef const __attribute__((address_space(4))) uint32_t cw;
+  cw *w = (cw *)(p + i);
+  R r;
+  uint32_t *d = reinterpret_cast<uint32_t *>(&r);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(R) / 4); ++k) d[k] = w[k];
+  return r;
+}
+
 // Workgroup tile: WM x 2 waves, each owning WTM x WTN MFMA blocks; K is
 // consumed in chunks of KC bands.  The operand rows of one chunk (BM rows of
 // the tile, then BN rows of its columns) sit in LDS as rows of ROWB bytes made
@@ -649,8 +664,8 @@ struct Gemm {
     constexpr int ST = T::ST;
     for (int u = next_unit(L, -1, &s_u, &s_q); u < L.n_units;
          u = next_unit(L, u, &s_u, &s_q)) {
-      const int4 unit = L.units[u];
-      const GemmJob job = L.jobs[unit.x];
+      const int4 unit = ld_c(L.units, u);
+      const GemmJob job = ld_c(L.jobs, unit.x);
       const int r0 = unit.y, c0 = unit.z;
       uint32_t grow[T::LPW], sb[T::LPW];
       sfor<0, T::LPW>([&](auto tt) {
