@@ -198,15 +198,23 @@ struct Gemm {
 
   // Direct global -> LDS loads: wave w issues the 1 KB blocks w, w + NW, ...
   // of a stage; lane l of block b fills bytes 16 l .. 16 l + 15 of it, which
-  // hold logical slot ((16 l) % ROWB / 16) ^ swz(row) of that row.  Per lane
-  // and load t: the operand row and the byte offset of the slot.
-  static __device__ __forceinline__ void dma_lane(int t, int r0, int c0, uint32_t &grow,
-                                                  uint32_t &sb) {
+  // hold logical slot ((16 l) % ROWB / 16) ^ swz(row) of that row.  From one
+  // load of a lane to its next the row advances by DR = NW KB / ROWB, a
+  // multiple of 16 (so the slot and its swizzle stay the same), and the tile's
+  // BM rows of A and BN rows of B are whole numbers of DR: load t of every
+  // lane lies in A when t DR < BM, else in B.  A lane keeps only its first
+  // row and slot byte (row0, sb0); the rest is per load and the same for all
+  // lanes.
+  static constexpr int DR = T::NW * 1024 / T::ROWB;
+  static_assert((T::NW * 1024) % T::ROWB == 0 && DR % 16 == 0 && T::BM % DR == 0 &&
+                    T::BN % DR == 0 && T::LPW * DR == T::BM + T::BN,
+                "loads advance by whole swizzle periods and split at the A/B boundary");
+  static __device__ __forceinline__ void dma_lane(uint32_t &row0, uint32_t &sb0) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int byte = (w + t * T::NW) * 1024 + l * 16;
+    const int byte = w * 1024 + l * 16;
     const int row = byte / T::ROWB, p = (byte % T::ROWB) >> 4;
-    grow = (uint32_t)(row < T::BM ? r0 + row : c0 + (row - T::BM));
-    sb = (uint32_t)((p ^ T::swz(row)) << 4);
+    row0 = (uint32_t)row;
+    sb0 = (uint32_t)((p ^ T::swz(row)) << 4);
   }
   // the loads of one chunk: base points at the chunk's first band of row 0,
   // pitchB is the operand's row pitch in bytes (row offsets in 64 bits: an
@@ -232,15 +240,17 @@ struct Gemm {
                  : "memory", "m0");
   }
 #pragma clang diagnostic pop
-  static __device__ __forceinline__ void issue(const char *base, uint32_t pitchB,
-                                               const uint32_t (&grow)[T::LPW],
-                                               const uint32_t (&sb)[T::LPW], char *buf) {
+  // operand row of load t: r0 + row (A) or c0 + row - BM (B), row = row0 + t DR
+  static __device__ __forceinline__ void issue(const char *base, uint32_t pitchB, int r0, int c0,
+                                               uint32_t row0, uint32_t sb0, char *buf) {
     const int w = threadIdx.x >> 6;
     const uint32_t lds0 = __builtin_amdgcn_readfirstlane(
         (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char *)(buf + w * 1024));
+    const char *lane = base + sb0;
     sfor<0, T::LPW>([&](auto tt) {
       constexpr int t = decltype(tt)::value;
-      dma16(base + ((uint64_t)grow[t] * pitchB + sb[t]), lds0 + t * T::NW * 1024);
+      const uint32_t g = (uint32_t)((t * DR < T::BM ? r0 : c0 - T::BM) + t * DR) + row0;
+      dma16(lane + (uint64_t)g * pitchB, lds0 + t * T::NW * 1024);
     });
   }
 
@@ -667,11 +677,8 @@ struct Gemm {
       const int4 unit = ld_c(L.units, u);
       const GemmJob job = ld_c(L.jobs, unit.x);
       const int r0 = unit.y, c0 = unit.z;
-      uint32_t grow[T::LPW], sb[T::LPW];
-      sfor<0, T::LPW>([&](auto tt) {
-        constexpr int t = decltype(tt)::value;
-        dma_lane(t, r0, c0, grow[t], sb[t]);
-      });
+      uint32_t row0, sb0;
+      dma_lane(row0, sb0);
       // one pipelined pass over the n chunks of an operand into acc
       // three: the three-product form (Acc3 x holds S3), else x is unused
       auto pipe = [&](auto three, Acc &acc, Acc3 &x, const void *psi, int ld, int n) {
@@ -680,7 +687,7 @@ struct Gemm {
         const uint32_t pitch = (uint32_t)ld * M::BPB;
         sfor<0, ST - 1>([&](auto ss) {
           if (decltype(ss)::value < n)
-            issue(base + (size_t)decltype(ss)::value * CB, pitch, grow, sb, stage(ss));
+            issue(base + (size_t)decltype(ss)::value * CB, pitch, r0, c0, row0, sb0, stage(ss));
         });
         for (int cb = 0; cb < n; cb += ST) {
           sfor<0, ST>([&](auto ss) {
@@ -692,7 +699,7 @@ struct Gemm {
               else wait_then_barrier<0>();
               // refill the stage of chunk c - 1, which every wave has finished
               if (c + ST - 1 < n)
-                issue(base + (size_t)(c + ST - 1) * CB, pitch, grow, sb,
+                issue(base + (size_t)(c + ST - 1) * CB, pitch, r0, c0, row0, sb0,
                       stage(std::integral_constant<int, (s + ST - 1) % ST>{}));
               if constexpr (decltype(three)::value) compute3(acc, x, stage(ss), wr, wc);
               else compute(acc, stage(ss), wr, wc);

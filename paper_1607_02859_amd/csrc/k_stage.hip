@@ -44,13 +44,28 @@ __device__ __forceinline__ void split_bf16(float x, uint16_t &hi, uint16_t &lo) 
   lo = f32_to_bf16_rne(x - bf16_to_f32(hi));
 }
 
+// A record every lane reads at the same index, through the constant address
+// space, word by word: it loads as scalars, so no vector-memory wait for it
+// (the wait counter being in order) also waits for the previous tau's stores.
+template <typename R>
+__device__ __forceinline__ R ld_c(const R *p, int64_t i) {
+  static_assert(sizeof(R) % 4 == 0, "whole words");
+  typedef const __attribute__((address_space(4))) uint32_t cw;
+  cw *w = (cw *)(p + i);
+  R r;
+  uint32_t *d = reinterpret_cast<uint32_t *>(&r);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(R) / 4); ++k) d[k] = w[k];
+  return r;
+}
+
 __global__ __launch_bounds__(256) void k_stage(StageLaunch L) {
   __shared__ double2 tile[kStageK][kStageR + 1];
   __shared__ double sc[kStageK];
   const int tid = threadIdx.x;
   for (int b = blockIdx.x; b < L.n_blocks; b += gridDim.x) {
-    const int4 blk = L.blocks[b];
-    const StageOp op = L.ops[blk.x];
+    const int4 blk = ld_c(L.blocks, b);
+    const StageOp op = ld_c(L.ops, blk.x);
     const int r0 = blk.y * kStageR;
     const int k0 = blk.z * kStageK;
     // load Phi[perm[k]][r] for the tile, zero outside the real ranges
@@ -68,16 +83,19 @@ __global__ __launch_bounds__(256) void k_stage(StageLaunch L) {
       }
       tile[kk][rr] = v;
     }
+    // the band's eigenvalue once per block; per tau only scalar loads
+    const double eps_k = (tid < kStageK && k0 + tid < op.k) ? op.eps[k0 + tid] : 0.0;
     for (int j = 0; j < op.n_jobs; ++j) {
       __syncthreads();
+      const double tau_j = ld_c(op.tau, j);
       if (tid < kStageK) {
         const int k = k0 + tid;
         double s = 0.0;
-        if (k < op.k) s = exp(0.5 * op.sign * (op.eps[k] - op.edge) * op.tau[j]);
+        if (k < op.k) s = exp(0.5 * op.sign * (eps_k - op.edge) * tau_j);
         sc[tid] = s;
       }
       __syncthreads();
-      char *out = reinterpret_cast<char *>(op.psi[j]);
+      char *out = reinterpret_cast<char *>(ld_c(op.psi, j));
       if (L.prec == P_FP64 || L.prec == P_FP32) {
         for (int idx = tid; idx < kStageK * kStageR; idx += 256) {
           const int rr = idx / kStageK, kk = idx % kStageK;
@@ -126,8 +144,15 @@ __global__ __launch_bounds__(256) void k_stage(StageLaunch L) {
           w[1] = pack(lr);
           w[2] = pack(hi_);
           w[3] = pack(li);
+          // constant indices: w stays in registers (a run-time loop over the
+          // parts put it in scratch memory, one load, wait and store per part)
           uint4 *d4 = reinterpret_cast<uint4 *>(dst);
-          for (int p = 0; p < parts; ++p) d4[p] = w[p];
+          d4[0] = w[0];
+          d4[1] = w[1];
+          if (parts == 4) {
+            d4[2] = w[2];
+            d4[3] = w[3];
+          }
         }
       }
     }
