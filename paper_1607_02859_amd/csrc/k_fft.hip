@@ -643,7 +643,7 @@ __device__ __forceinline__ void pencil_pk_n(const FftJob &J, const Geo &G, int d
 }
 
 template <typename T, int SIGN, int NC>
-__global__ __launch_bounds__(256) void k_fft_pencils(FftLaunch L) {
+__device__ __forceinline__ void fft_pencils_body(const FftLaunch &L) {
   for (int u = blockIdx.x; u < L.n_units_pencils; u += gridDim.x) {
     const FftJob J = ld_c(L.jobs, __builtin_amdgcn_readfirstlane(find_job(L.jobs, L.n_jobs, u, true)));
     const Geo G = ld_c(L.geos, J.geo);
@@ -692,6 +692,18 @@ __global__ __launch_bounds__(256) void k_fft_pencils(FftLaunch L) {
       }
     }
   }
+}
+
+template <typename T, int SIGN, int NC>
+__global__ __launch_bounds__(256) void k_fft_pencils(FftLaunch L) {
+  fft_pencils_body<T, SIGN, NC>(L);
+}
+// over r' (the scattered transposed stores of chi(tau)): at most two waves
+// per SIMD, which measured faster there than more resident blocks
+template <typename T, int NC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void k_fft_pencils_rp(FftLaunch L) {
+  fft_pencils_body<T, 1, NC>(L);
 }
 
 // ---------------------------------------------------------------------------
@@ -899,7 +911,10 @@ hipError_t launch_fft_t(const FftLaunch &L, int lds_bytes, hipStream_t s) {
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (g2 > 0) hipLaunchKernelGGL((k_fft_pencils<T, S, NC>), dim3(g2), dim3(256), 0, s, L);
+  if (g2 > 0) {
+    if constexpr (S > 0) hipLaunchKernelGGL((k_fft_pencils_rp<T, NC>), dim3(g2), dim3(256), 0, s, L);
+    else hipLaunchKernelGGL((k_fft_pencils<T, S, NC>), dim3(g2), dim3(256), 0, s, L);
+  }
   return hipGetLastError();
 }
 
