@@ -555,6 +555,17 @@ __device__ __forceinline__ void pencil_n(const FftJob &J, const Geo &G, int d, i
     const cx<T> x = ld_g(tmp, ok ? ((int64_t)i * G.n_disk + d) * J.n_cols + c : 0);
     v[i] = ok ? x : cx<T>{(T)0, (T)0};
   }
+  // FP32 with half rows: the mirror slots are loaded before the transform,
+  // not one by one between the stores (each wait for one would also wait for
+  // the stores); FP64 has no registers to spare for them
+  constexpr int NS = sizeof(T) == 4 ? N : 1;
+  int sn[NS];
+  if constexpr (sizeof(T) == 4) {
+    if (J.half_rows) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) sn[k] = ld_g(G.gneg, (int64_t)(so[k] >= 0 ? so[k] : 0));
+    }
+  }
   reg_fft<N, SIGN, T, 1>(v, o);
   if (J.half_rows) {
     // column c is row g = hrow[c] of the kept half; chi(-G, -G') is the
@@ -566,9 +577,12 @@ __device__ __forceinline__ void pencil_n(const FftJob &J, const Geo &G, int d, i
     for (int k = 0; k < N; ++k) {
       if (so[k] >= 0) {
         st_g(out, (int64_t)so[k] * J.o_slot + (int64_t)g * J.o_col, o[k]);
-        if (gm != g)
-          st_g(out, (int64_t)ld_g(G.gneg, (int64_t)so[k]) * J.o_slot + (int64_t)gm * J.o_col,
-               cx<T>{o[k].x, -o[k].y});
+        if (gm != g) {
+          int m;
+          if constexpr (sizeof(T) == 4) m = sn[k];
+          else m = ld_g(G.gneg, (int64_t)so[k]);
+          st_g(out, (int64_t)m * J.o_slot + (int64_t)gm * J.o_col, cx<T>{o[k].x, -o[k].y});
+        }
       }
     }
     return;
@@ -974,10 +988,26 @@ __device__ __forceinline__ void spencil_n(const SfftLaunch &L, const SfftJob &J,
   for (int k = 0; k < N; ++k) so[k] = ld_g(G.slot_of, (int64_t)d * N + k);
   cx<T> v[N], o[N];
   const int64_t col = (int64_t)(J.col0 + c) * J.i_col;
+  // all N loads out before any is used: one branch on the input type around
+  // the whole batch (a branch per load made each conversion wait for its load)
+  if (L.in_f64) {
+    cx<double> xd[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+      xd[k] = ld_g(reinterpret_cast<const cx<double> *>(J.in),
+                   so[k] >= 0 ? (int64_t)so[k] * J.i_slot + col : col);
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = cx<T>{(T)xd[k].x, (T)xd[k].y};
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+      v[k] = ld_g(reinterpret_cast<const cx<T> *>(J.in),
+                  so[k] >= 0 ? (int64_t)so[k] * J.i_slot + col : col);
+  }
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    const cx<T> x = ld_in<T>(L, J, so[k] >= 0 ? (int64_t)so[k] * J.i_slot + col : col);
-    v[k] = so[k] >= 0 ? x : cx<T>{(T)0, (T)0};
+    if (L.conj_in) v[k].y = -v[k].y;
+    if (so[k] < 0) v[k] = cx<T>{(T)0, (T)0};
   }
   reg_fft<N, SIGN, T, 1>(v, o);
   cx<T> *tmp = reinterpret_cast<cx<T> *>(J.tmp);
@@ -1062,12 +1092,14 @@ __global__ __launch_bounds__(256) void k_sfft_planes(SfftLaunch L) {
     const int n_cols = J.n_cols;
 #pragma unroll
     for (int t = 0; t < PF; ++t) {
+      // unconditional (element 0 stands in past the unit), so that no load
+      // is waited for before the next goes out
       const int idx = tid + 256 * t;
       const int cc = idx % C, rest = idx / C;
       const int p = rest / D, d = rest - p * D;
       const int c = c0 + cc;
-      if (idx < np * D * C && c < n_cols)
-        pre[t] = ld_g(tmp, ((int64_t)(p0 + p) * D + d) * n_cols + c);
+      const bool ok = idx < np * D * C && c < n_cols;
+      pre[t] = ld_g(tmp, ok ? ((int64_t)(p0 + p) * D + d) * n_cols + c : 0);
     }
   };
   int u = next_wanted((int)blockIdx.x);
